@@ -1,0 +1,130 @@
+/*
+ * jk.h -- C ABI of the MI355X (gfx950) integral-direct Coulomb/exchange builder.
+ *
+ * Computes, for a symmetric density D over contracted Gaussian shells (l <= 4),
+ *     J[mu,nu] = sum_{la,si} (mu nu|la si) D[la,si]
+ *     K[mu,nu] = sum_{la,si} (mu la|nu si) D[la,si]
+ * with the two-electron integrals evaluated by Rys quadrature (paper section 2: the
+ * ERI as an exact N-point quadrature over three 2D integrals, N = floor(L/2) + 1) and
+ * contracted with D in the same pass (section 3, Algorithms 2 and 3: the six J/K
+ * updates per integral). Shell quartets are screened with the Cauchy-Schwarz factor
+ * and the density block maxima (section 3, the pair prescreen I_ab > tau and the
+ * density-weighted test I_ab I_cd P >= tau).
+ *
+ * Conventions (all arguments):
+ *  - Atomic units. Row-major. Doubles are IEEE binary64, indices are int32.
+ *  - A shell is (atom, l, nprim, prim_off, pure). Its primitives are exps[prim_off +
+ *    k], coefs[prim_off + k] for k < nprim. A coefficient multiplies the UNNORMALISED
+ *    primitive x^ax y^ay z^az exp(-a r^2) centred on the atom; the library applies no
+ *    normalisation of its own.
+ *  - Cartesian components of a shell are ordered ax descending, then ay descending
+ *    (for l = 2: xx, xy, xz, yy, yz, zz).
+ *  - pure = 1 (allowed for any l, acts only for l >= 2): the shell carries the 2l+1
+ *    real solid harmonics sqrt(4pi/(2l+1)) r^l Y_lm, m = -l..l (m < 0: sin-type),
+ *    written in the Cartesian components with, in each row, the largest-magnitude
+ *    coefficient positive (the first in component order on ties). l = 0, 1 are always
+ *    Cartesian (s; x, y, z).
+ *  - AO order: shells in input order, functions of a shell contiguous. nao is the sum
+ *    of the shell sizes (2l+1 for pure l >= 2, else (l+1)(l+2)/2).
+ *  - Device buffers (D, J, K, ERI) are caller-owned, on the current HIP device, nao*nao
+ *    doubles, contiguous. Host buffers are noted as such.
+ *
+ * Errors: every int-returning call returns JK_OK (0) or a negative JK_E* code, never
+ * aborts and never throws. jk_last_error() returns a thread-local message for the last
+ * failure on the calling thread. After an error the outputs are unspecified and any
+ * plan remains valid to destroy.
+ */
+#ifndef JK_H
+#define JK_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JK_OK 0
+#define JK_EINVAL (-1)        /* bad argument: null pointer, size mismatch, non-finite */
+#define JK_EUNSUPPORTED (-2)  /* l > 4, nprim > 64, or a feature not built */
+#define JK_ENOMEM (-3)        /* host or device allocation failed */
+#define JK_EDEVICE (-4)       /* a HIP call failed; the message carries its string */
+#define JK_ENODEV (-5)        /* no HIP device */
+
+#define JK_FP64 0
+#define JK_MIXED 1
+
+typedef struct {
+  int nshell;
+  const int *atom;       /* [nshell] atom index of each shell, 0 <= atom < natom */
+  const int *l;          /* [nshell] angular momentum, 0..4 */
+  const int *nprim;      /* [nshell] contraction order K, 1..64 */
+  const int *prim_off;   /* [nshell] first primitive of the shell in exps/coefs */
+  const int *pure;       /* [nshell] 0 Cartesian, 1 real solid harmonics */
+  int nprim_total;       /* length of exps and coefs */
+  const double *exps;    /* [nprim_total] exponents, > 0 */
+  const double *coefs;   /* [nprim_total] contraction coefficients (see above) */
+} jk_basis_t;            /* all pointers are HOST pointers, read during plan creation only */
+
+typedef struct {
+  double thresh;         /* tau: quartet kept iff I_ab > tau, I_cd > tau, I_ab I_cd P >= tau */
+  int precision;         /* JK_FP64 (default) or JK_MIXED */
+  double fp32_cutoff;    /* JK_MIXED: quartets with I_ab I_cd P below this run in FP32 */
+  int flags;             /* reserved, 0 */
+} jk_opts_t;
+
+typedef struct jk_plan jk_plan_t;
+
+typedef struct {
+  long long kept_quartets;      /* unique shell quartets that passed the screen (last execute) */
+  long long candidate_quartets; /* quartets tested by the screen (last execute) */
+  long long kept_fp32;          /* of kept_quartets, those evaluated in FP32 (mixed mode) */
+  long long prim_quartets;      /* primitive quartets of the kept quartets */
+  int npairs_kept;              /* shell pairs with I_ab > tau */
+  int nao, nao_cart, nshell;
+  double plan_ms;               /* host wall time of jk_plan_create */
+} jk_stats_t;
+
+/* Create a plan for one molecule: validates the basis on the host, builds the shell
+ * pair tables, uploads them and computes the Cauchy-Schwarz factors on the device
+ * (section 3: I_ab = max over the functions of |(ab|ab)|^(1/2)). coords: HOST, natom x 3.
+ * opts may be NULL (tau = 1e-12, FP64). The plan owns all device workspace; *out is
+ * set only on success. Synchronises the device. */
+int jk_plan_create(const jk_basis_t *basis, const double *coords, int natom, const jk_opts_t *opts,
+                   jk_plan_t **out);
+
+/* J and K for the density D (DEVICE, nao x nao, symmetric, caller-owned). J and K are
+ * OVERWRITTEN (DEVICE, nao x nao). Work is enqueued on `stream` (a hipStream_t, NULL =
+ * default stream); results are valid after the stream synchronises. One small
+ * device-to-host read of the density maximum sizes the screened work lists, so the
+ * call blocks until the screen has run. A plan must not be executed concurrently. */
+int jk_plan_execute(jk_plan_t *plan, const double *D, double *J, double *K, void *stream);
+
+/* jk_plan_create + jk_plan_execute + jk_plan_destroy; thresh overrides opts->thresh. */
+int jk_build(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh,
+             double *J, double *K, const jk_opts_t *opts, void *stream);
+
+void jk_plan_destroy(jk_plan_t *plan);
+
+/* nao (final basis) and nao_cart (all shells Cartesian) of a plan. */
+int jk_plan_sizes(const jk_plan_t *plan, int *nao, int *nao_cart);
+
+/* Statistics of the plan and its last execute (HOST struct). */
+int jk_stats(const jk_plan_t *plan, jk_stats_t *out);
+
+/* Test hook: full Cartesian ERI tensor (DEVICE, nao_cart^4 doubles, overwritten),
+ * unscreened, with the same integral kernels as jk_plan_execute. Small inputs only. */
+int jk_eri_tensor(jk_plan_t *plan, double *eri, void *stream);
+
+/* Test hook: Cauchy-Schwarz factors per shell pair (HOST, nshell x nshell, symmetric),
+ * computed over the Cartesian components of the shells. */
+int jk_schwarz(const jk_plan_t *plan, double *out);
+
+/* Host-only helper: the library's Cartesian -> real-solid-harmonic matrix for l
+ * (HOST out, (2l+1) x (l+1)(l+2)/2, row-major). Needs no device. l in 2..4. */
+int jk_sph_matrix(int l, double *out);
+
+/* Thread-local message of the last failure (never NULL). */
+const char *jk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JK_H */

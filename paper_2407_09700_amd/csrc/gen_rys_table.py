@@ -150,11 +150,11 @@ def write_header(tables, path):
     lines = ["/* Generated by gen_rys_table.py -- do not edit. Rys roots u_n = t_n^2 and weights w_n.",
              " * coef layout per N: [interval k][root n][u|w][power 0..RYS_DEG] in s = 2(T-k)-1. */",
              "#pragma once", f"#define RYS_NMAX {NMAX}", f"#define RYS_DEG {DEG}",
-             "static const int RYS_TMAX[RYS_NMAX + 1] = {" + ", ".join(str(t) for t in TMAX) + "};"]
+             "static constexpr int RYS_TMAX[RYS_NMAX + 1] = {" + ", ".join(str(t) for t in TMAX) + "};"]
     offs = [0] * (NMAX + 2)
     for N in range(1, NMAX + 1):
         offs[N + 1] = offs[N] + tables[N].size
-    lines.append("static const int RYS_OFF[RYS_NMAX + 2] = {" + ", ".join(str(o) for o in offs) + "};")
+    lines.append("static constexpr int RYS_OFF[RYS_NMAX + 2] = {" + ", ".join(str(o) for o in offs) + "};")
     lines.append(f"#define RYS_NCOEF {offs[NMAX + 1]}")
     lines.append("RYS_STORAGE double RYS_COEF[RYS_NCOEF] = {")
     for N in range(1, NMAX + 1):
@@ -169,7 +169,7 @@ def write_header(tables, path):
         s2all += s2
         wall += w
         hoff[N + 1] = hoff[N] + N
-    lines.append("static const int RYS_HOFF[RYS_NMAX + 2] = {" + ", ".join(str(o) for o in hoff) + "};")
+    lines.append("static constexpr int RYS_HOFF[RYS_NMAX + 2] = {" + ", ".join(str(o) for o in hoff) + "};")
     lines.append("RYS_STORAGE double RYS_HERM_S2[" + str(len(s2all)) + "] = {" + ", ".join(v.hex() for v in s2all) + "};")
     lines.append("RYS_STORAGE double RYS_HERM_W[" + str(len(wall)) + "] = {" + ", ".join(v.hex() for v in wall) + "};")
     with open(path, "w") as f:

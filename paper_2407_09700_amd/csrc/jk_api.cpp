@@ -1,0 +1,627 @@
+// Host side of the J/K library: argument validation, shell-pair planning, the
+// Cauchy-Schwarz pass, the per-build screening and the class launches (C ABI in jk.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/jk.h"
+#include "jk_aux.h"
+#include "jk_classes.h"
+
+using namespace jk;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                             \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      if (e_ == hipErrorOutOfMemory) return fail(JK_ENOMEM, "%s: %s", #expr, hipGetErrorString(e_)); \
+      return fail(JK_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));                          \
+    }                                                                                            \
+  } while (0)
+
+ClassInfo g_classes[NQCLASS];
+bool g_classes_ready = false;
+
+void ensure_classes() {
+  if (g_classes_ready) return;
+  register_classes_l0(g_classes);
+  register_classes_l1(g_classes);
+  register_classes_l2(g_classes);
+  register_classes_l3(g_classes);
+  register_classes_l4(g_classes);
+  g_classes_ready = true;
+}
+
+// ------------------------------------------------------------------ solid harmonics
+double fact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+double binomd(int n, int k) { return (k < 0 || k > n) ? 0.0 : fact(n) / (fact(k) * fact(n - k)); }
+
+int cart_index(int l, int ax, int ay) {   // position of (ax, ay, l-ax-ay) in ax-desc, ay-desc order
+  int idx = 0;
+  for (int x = l; x > ax; --x) idx += l - x + 1;
+  return idx + (l - ax - ay);
+}
+
+// Real solid harmonics in Racah normalisation from the closed form of Helgaker,
+// Joergensen & Olsen, "Molecular Electronic-Structure Theory", eq. 6.4.47-6.4.50:
+// S_lm = N_lm sum_{t,u,v} C^{lm}_{tuv} x^(2t+|m|-2(u+v)) y^(2(u+v)) z^(l-2t-|m|).
+void solid_harmonics(int l, double *T) {
+  const int nc = (l + 1) * (l + 2) / 2;
+  for (int i = 0; i < (2 * l + 1) * nc; ++i) T[i] = 0.0;
+  for (int m = -l; m <= l; ++m) {
+    const int am = std::abs(m);
+    double *row = T + (m + l) * nc;
+    const double nlm = 1.0 / (std::pow(2.0, am) * fact(l)) *
+                       std::sqrt(2.0 * fact(l + am) * fact(l - am) / (m == 0 ? 2.0 : 1.0));
+    const double vm = m < 0 ? 0.5 : 0.0;
+    for (int t = 0; t <= (l - am) / 2; ++t)
+      for (int u = 0; u <= t; ++u) {
+        const int vmax2 = (int)std::floor(am / 2.0 - vm);   // v = vm + j, j = 0..vmax2
+        for (int j = 0; j <= vmax2; ++j) {
+          const double v = vm + j;
+          const int v2 = (int)std::lround(2 * v);
+          const double sgn = ((t + (int)std::lround(v - vm)) % 2) ? -1.0 : 1.0;
+          const double c = sgn * std::pow(0.25, t) * binomd(l, t) * binomd(l - t, am + t) * binomd(t, u) *
+                           binomd(am, v2);
+          const int px = 2 * t + am - 2 * u - v2, py = 2 * u + v2, pz = l - 2 * t - am;
+          if (px < 0 || py < 0 || pz < 0) continue;
+          row[cart_index(l, px, py)] += nlm * c;
+        }
+      }
+    // sign convention: largest-magnitude coefficient positive (first on ties)
+    double amax = 0.0;
+    for (int k = 0; k < nc; ++k) amax = std::max(amax, std::fabs(row[k]));
+    for (int k = 0; k < nc; ++k) {
+      if (std::fabs(std::fabs(row[k]) - amax) <= 1e-12 * amax) {
+        if (row[k] < 0)
+          for (int q = 0; q < nc; ++q) row[q] = -row[q];
+        break;
+      }
+    }
+    for (int k = 0; k < nc; ++k)
+      if (std::fabs(row[k]) < 1e-15) row[k] = 0.0;
+  }
+}
+
+template <class T>
+int dalloc(T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? JK_ENOMEM : JK_EDEVICE, "hipMalloc(%zu bytes): %s", n * sizeof(T),
+                hipGetErrorString(e));
+  }
+  return JK_OK;
+}
+
+template <class T>
+int dupload(T **p, const std::vector<T> &v) {
+  int rc = dalloc(p, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return JK_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct jk_plan {
+  int nshell = 0, natom = 0, nao = 0, nc = 0;
+  double tau = 1e-12;
+  int precision = JK_FP64;
+  double fp32_cutoff = 1e-6;
+  std::vector<int> l, pure, atom, cart_off, ao_off;
+  std::vector<double> coords;
+  std::vector<double> schwarz;         // nshell x nshell
+  int npairs = 0;
+  std::vector<int> cls_beg;            // 16
+  std::vector<Pair> pairs;             // kept pairs (host copy)
+  // device
+  Pair *d_pairs = nullptr;
+  PrimPair *d_pp = nullptr;
+  double *d_pairI = nullptr;
+  int *d_pair_cls = nullptr, *d_pair_sa = nullptr, *d_pair_sb = nullptr, *d_cls_beg = nullptr;
+  int *d_l = nullptr, *d_pure = nullptr, *d_cart_off = nullptr, *d_ao_off = nullptr;
+  int *d_cart2shell = nullptr, *d_ao2shell = nullptr;
+  double *d_tsph = nullptr;
+  double *d_Dc = nullptr, *d_Jc = nullptr, *d_Kc = nullptr, *d_Pblk = nullptr, *d_gmax = nullptr;
+  unsigned long long *d_cap = nullptr;
+  int *d_count = nullptr;
+  long long *d_list_off = nullptr;
+  int2 *d_lists = nullptr;
+  long long list_capacity = 0;
+  double *d_scratch = nullptr;
+  long long scratch_doubles = 0;
+  ShellInfo S{};
+  jk_stats_t stats{};
+  int device = 0;
+};
+
+namespace {
+
+void plan_free(jk_plan *p) {
+  dfree(p->d_pairs); dfree(p->d_pp); dfree(p->d_pairI); dfree(p->d_pair_cls); dfree(p->d_pair_sa);
+  dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_l); dfree(p->d_pure); dfree(p->d_cart_off);
+  dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell); dfree(p->d_tsph); dfree(p->d_Dc);
+  dfree(p->d_Jc); dfree(p->d_Kc); dfree(p->d_Pblk); dfree(p->d_gmax); dfree(p->d_cap); dfree(p->d_count);
+  dfree(p->d_list_off); dfree(p->d_lists); dfree(p->d_scratch);
+}
+
+constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes for k_small
+constexpr int GRID_TEAM_MAX = 1024;    // workgroups for k_team
+
+int class_grid(const ClassInfo &ci, long long nquartets) {
+  long long g = (nquartets + ci.per_block - 1) / ci.per_block;
+  const long long gmax = ci.team ? GRID_TEAM_MAX : GRID_SMALL_MAX;
+  if (g > gmax) g = gmax;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int ensure_scratch(jk_plan *p, long long doubles) {
+  if (doubles <= p->scratch_doubles) return JK_OK;
+  dfree(p->d_scratch);
+  p->scratch_doubles = 0;
+  int rc = dalloc(&p->d_scratch, (size_t)doubles);
+  if (rc) return rc;
+  p->scratch_doubles = doubles;
+  return JK_OK;
+}
+
+// Build primitive pairs and pair records for every shell pair i >= j (canonical order
+// l_a >= l_b inside the pair).
+void build_pairs(const jk_basis_t *B, const double *coords, const std::vector<int> &cart_off,
+                 std::vector<Pair> &pairs, std::vector<PrimPair> &pps) {
+  const int ns = B->nshell;
+  pairs.clear();
+  pps.clear();
+  pairs.reserve((size_t)ns * (ns + 1) / 2);
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j <= i; ++j) {
+      int a = i, b = j;
+      if (B->l[i] < B->l[j]) std::swap(a, b);
+      Pair P{};
+      const double *A = coords + 3 * B->atom[a], *Bc = coords + 3 * B->atom[b];
+      double ab2 = 0;
+      for (int d = 0; d < 3; ++d) {
+        P.A[d] = A[d];
+        P.B[d] = Bc[d];
+        ab2 += (A[d] - Bc[d]) * (A[d] - Bc[d]);
+      }
+      P.sa = a; P.sb = b;
+      P.ca = cart_off[a]; P.cb = cart_off[b];
+      P.pp_off = (int)pps.size();
+      P.npp = B->nprim[a] * B->nprim[b];
+      P.cls = pair_class(B->l[a], B->l[b]);
+      P.I = 0.f;
+      for (int ka = 0; ka < B->nprim[a]; ++ka)
+        for (int kb = 0; kb < B->nprim[b]; ++kb) {
+          const double ea = B->exps[B->prim_off[a] + ka], eb = B->exps[B->prim_off[b] + kb];
+          const double ca = B->coefs[B->prim_off[a] + ka], cb = B->coefs[B->prim_off[b] + kb];
+          PrimPair q{};
+          q.p = ea + eb;
+          q.Px = (ea * A[0] + eb * Bc[0]) / q.p;
+          q.Py = (ea * A[1] + eb * Bc[1]) / q.p;
+          q.Pz = (ea * A[2] + eb * Bc[2]) / q.p;
+          q.K = ca * cb * std::exp(-ea * eb / q.p * ab2);
+          pps.push_back(q);
+        }
+      pairs.push_back(P);
+    }
+}
+
+int validate(const jk_basis_t *B, const double *coords, int natom) {
+  if (!B) return fail(JK_EINVAL, "basis is NULL");
+  if (!coords) return fail(JK_EINVAL, "coords is NULL");
+  if (natom <= 0) return fail(JK_EINVAL, "natom must be positive (got %d)", natom);
+  if (B->nshell <= 0) return fail(JK_EINVAL, "nshell must be positive (got %d)", B->nshell);
+  if (!B->atom || !B->l || !B->nprim || !B->prim_off || !B->pure || !B->exps || !B->coefs)
+    return fail(JK_EINVAL, "a basis array is NULL");
+  if (B->nprim_total <= 0) return fail(JK_EINVAL, "nprim_total must be positive");
+  for (int a = 0; a < 3 * natom; ++a)
+    if (!std::isfinite(coords[a])) return fail(JK_EINVAL, "coordinate %d is not finite", a);
+  for (int s = 0; s < B->nshell; ++s) {
+    if (B->l[s] < 0) return fail(JK_EINVAL, "shell %d: negative l", s);
+    if (B->l[s] > LMAX) return fail(JK_EUNSUPPORTED, "shell %d: l = %d > %d", s, B->l[s], LMAX);
+    if (B->nprim[s] <= 0) return fail(JK_EINVAL, "shell %d: nprim must be positive", s);
+    if (B->nprim[s] > 64) return fail(JK_EUNSUPPORTED, "shell %d: nprim = %d > 64", s, B->nprim[s]);
+    if (B->atom[s] < 0 || B->atom[s] >= natom) return fail(JK_EINVAL, "shell %d: atom %d out of range", s, B->atom[s]);
+    if (B->prim_off[s] < 0 || B->prim_off[s] + B->nprim[s] > B->nprim_total)
+      return fail(JK_EINVAL, "shell %d: primitive range out of bounds", s);
+    if (B->pure[s] != 0 && B->pure[s] != 1) return fail(JK_EINVAL, "shell %d: pure must be 0 or 1", s);
+    for (int k = 0; k < B->nprim[s]; ++k) {
+      const double e = B->exps[B->prim_off[s] + k], c = B->coefs[B->prim_off[s] + k];
+      if (!(e > 0.0) || !std::isfinite(e)) return fail(JK_EINVAL, "shell %d: exponent %d not positive/finite", s, k);
+      if (!std::isfinite(c)) return fail(JK_EINVAL, "shell %d: coefficient %d not finite", s, k);
+    }
+  }
+  return JK_OK;
+}
+
+int launch_class_mode(jk_plan *p, int qc, int mode, const int2 *list, const int *count, long long nq, double *out,
+                      hipStream_t st) {
+  const ClassInfo &ci = g_classes[qc];
+  if (!ci.launch[mode]) return fail(JK_EUNSUPPORTED, "class %d has no launcher for mode %d", qc, mode);
+  const int grid = class_grid(ci, nq);
+  if (ci.scratch_per_wg > 0) {
+    int rc = ensure_scratch(p, ci.scratch_per_wg * (long long)grid);
+    if (rc) return rc;
+  }
+  ClassArgs a{};
+  a.pairs = p->d_pairs;
+  a.pp = p->d_pp;
+  a.quartets = list;
+  a.count = count;
+  a.Dc = p->d_Dc;
+  a.Jc = p->d_Jc;
+  a.Kc = p->d_Kc;
+  a.out = out;
+  a.scratch = p->d_scratch;
+  a.scratch_per_wg = ci.scratch_per_wg;
+  a.nc = p->nc;
+  a.mode = mode;
+  HIPCHK(ci.launch[mode](a, grid, st));
+  return JK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *jk_last_error(void) { return g_err.c_str(); }
+
+int jk_sph_matrix(int l, double *out) {
+  if (!out) return fail(JK_EINVAL, "out is NULL");
+  if (l < 2 || l > LMAX) return fail(JK_EINVAL, "l must be in 2..4 (got %d)", l);
+  solid_harmonics(l, out);
+  return JK_OK;
+}
+
+int jk_plan_sizes(const jk_plan_t *plan, int *nao, int *nao_cart) {
+  if (!plan) return fail(JK_EINVAL, "plan is NULL");
+  if (nao) *nao = plan->nao;
+  if (nao_cart) *nao_cart = plan->nc;
+  return JK_OK;
+}
+
+int jk_stats(const jk_plan_t *plan, jk_stats_t *out) {
+  if (!plan || !out) return fail(JK_EINVAL, "NULL argument");
+  *out = plan->stats;
+  return JK_OK;
+}
+
+int jk_schwarz(const jk_plan_t *plan, double *out) {
+  if (!plan || !out) return fail(JK_EINVAL, "NULL argument");
+  std::memcpy(out, plan->schwarz.data(), sizeof(double) * plan->schwarz.size());
+  return JK_OK;
+}
+
+void jk_plan_destroy(jk_plan_t *plan) {
+  if (!plan) return;
+  plan_free(plan);
+  delete plan;
+}
+
+int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const jk_opts_t *opts, jk_plan_t **out) {
+  if (!out) return fail(JK_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(B, coords, natom);
+  if (rc) return rc;
+  double tau = 1e-12;
+  int precision = JK_FP64;
+  double fp32_cutoff = 1e-6;
+  if (opts) {
+    tau = opts->thresh;
+    precision = opts->precision;
+    fp32_cutoff = opts->fp32_cutoff;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(JK_EINVAL, "thresh must be finite and >= 0");
+    if (precision != JK_FP64 && precision != JK_MIXED) return fail(JK_EINVAL, "unknown precision %d", precision);
+    if (precision == JK_MIXED) return fail(JK_EUNSUPPORTED, "mixed precision is not built yet");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(JK_ENODEV, "no HIP device");
+  ensure_classes();
+  const auto t0 = std::chrono::steady_clock::now();
+
+  jk_plan *p = new jk_plan();
+  p->nshell = B->nshell;
+  p->natom = natom;
+  p->tau = tau;
+  p->precision = precision;
+  p->fp32_cutoff = fp32_cutoff;
+  (void)hipGetDevice(&p->device);
+  const int ns = B->nshell;
+  p->l.assign(B->l, B->l + ns);
+  p->pure.assign(B->pure, B->pure + ns);
+  p->atom.assign(B->atom, B->atom + ns);
+  p->coords.assign(coords, coords + 3 * natom);
+  p->cart_off.resize(ns + 1);
+  p->ao_off.resize(ns + 1);
+  p->cart_off[0] = p->ao_off[0] = 0;
+  for (int s = 0; s < ns; ++s) {
+    const int l = B->l[s];
+    p->cart_off[s + 1] = p->cart_off[s] + ncart(l);
+    p->ao_off[s + 1] = p->ao_off[s] + ((B->pure[s] && l >= 2) ? 2 * l + 1 : ncart(l));
+  }
+  p->nc = p->cart_off[ns];
+  p->nao = p->ao_off[ns];
+
+  auto cleanup = [&](int code) {
+    plan_free(p);
+    delete p;
+    return code;
+  };
+
+  // shell tables
+  std::vector<int> c2s(p->nc), a2s(p->nao);
+  for (int s = 0; s < ns; ++s) {
+    for (int k = p->cart_off[s]; k < p->cart_off[s + 1]; ++k) c2s[k] = s;
+    for (int k = p->ao_off[s]; k < p->ao_off[s + 1]; ++k) a2s[k] = s;
+  }
+  std::vector<double> tsph(5 * 6 + 7 * 10 + 9 * 15);
+  solid_harmonics(2, tsph.data());
+  solid_harmonics(3, tsph.data() + 30);
+  solid_harmonics(4, tsph.data() + 100);
+  if ((rc = dupload(&p->d_l, p->l)) || (rc = dupload(&p->d_pure, p->pure)) ||
+      (rc = dupload(&p->d_cart_off, p->cart_off)) || (rc = dupload(&p->d_ao_off, p->ao_off)) ||
+      (rc = dupload(&p->d_cart2shell, c2s)) || (rc = dupload(&p->d_ao2shell, a2s)) ||
+      (rc = dupload(&p->d_tsph, tsph)))
+    return cleanup(rc);
+  p->S.l = p->d_l; p->S.pure = p->d_pure; p->S.cart_off = p->d_cart_off; p->S.ao_off = p->d_ao_off;
+  p->S.cart2shell = p->d_cart2shell; p->S.ao2shell = p->d_ao2shell; p->S.tsph = p->d_tsph;
+  p->S.toff[0] = p->S.toff[1] = 0; p->S.toff[2] = 0; p->S.toff[3] = 30; p->S.toff[4] = 100;
+  p->S.nshell = ns; p->S.nc = p->nc; p->S.nao = p->nao;
+
+  // all shell pairs
+  std::vector<Pair> all;
+  std::vector<PrimPair> pps;
+  build_pairs(B, coords, p->cart_off, all, pps);
+  const int nall = (int)all.size();
+  if ((rc = dupload(&p->d_pairs, all)) || (rc = dupload(&p->d_pp, pps))) return cleanup(rc);
+
+  // Cauchy-Schwarz factors: the diagonal quartets (ab|ab), one class launch per pair class
+  {
+    double *d_smax = nullptr;
+    int2 *d_diag = nullptr;
+    int *d_cnt = nullptr;
+    if ((rc = dalloc(&d_smax, nall)) || (rc = dalloc(&d_diag, nall)) || (rc = dalloc(&d_cnt, NPAIRCLASS))) {
+      dfree(d_smax); dfree(d_diag);
+      return cleanup(rc);
+    }
+    std::vector<int2> diag(nall);
+    std::vector<int> cnt(NPAIRCLASS, 0), beg(NPAIRCLASS + 1, 0);
+    for (int i = 0; i < nall; ++i) cnt[all[i].cls]++;
+    for (int c = 0; c < NPAIRCLASS; ++c) beg[c + 1] = beg[c] + cnt[c];
+    std::vector<int> fillp(beg.begin(), beg.end() - 1);
+    for (int i = 0; i < nall; ++i) diag[fillp[all[i].cls]++] = make_int2(i, i);
+    hipError_t e = hipMemcpy(d_diag, diag.data(), sizeof(int2) * nall, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_cnt, cnt.data(), sizeof(int) * NPAIRCLASS, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_smax, 0, sizeof(double) * nall);
+    if (e != hipSuccess) {
+      dfree(d_smax); dfree(d_diag); dfree(d_cnt);
+      return cleanup(fail(JK_EDEVICE, "Schwarz setup: %s", hipGetErrorString(e)));
+    }
+    for (int c = 0; c < NPAIRCLASS && !rc; ++c) {
+      if (!cnt[c]) continue;
+      rc = launch_class_mode(p, qclass_index(c, c), MODE_SCHWARZ, d_diag + beg[c], d_cnt + c, cnt[c], d_smax, 0);
+    }
+    std::vector<double> smax(nall);
+    if (!rc) {
+      e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipMemcpy(smax.data(), d_smax, sizeof(double) * nall, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) rc = fail(JK_EDEVICE, "Schwarz pass: %s", hipGetErrorString(e));
+    }
+    dfree(d_smax); dfree(d_diag); dfree(d_cnt);
+    if (rc) return cleanup(rc);
+    p->schwarz.assign((size_t)ns * ns, 0.0);
+    for (int i = 0; i < nall; ++i) {
+      const double I = std::sqrt(smax[i]);
+      p->schwarz[(size_t)all[i].sa * ns + all[i].sb] = I;
+      p->schwarz[(size_t)all[i].sb * ns + all[i].sa] = I;
+      all[i].I = (float)I;
+    }
+    // keep pairs with I > tau, sorted by class then I descending (stable)
+    std::vector<int> order;
+    order.reserve(nall);
+    for (int i = 0; i < nall; ++i)
+      if (std::sqrt(smax[i]) > tau) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      if (all[x].cls != all[y].cls) return all[x].cls < all[y].cls;
+      return smax[x] > smax[y];
+    });
+    p->npairs = (int)order.size();
+    std::vector<Pair> kept(p->npairs);
+    std::vector<PrimPair> kpp;
+    std::vector<double> kI(p->npairs);
+    std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs);
+    p->cls_beg.assign(NPAIRCLASS + 1, 0);
+    for (int k = 0; k < p->npairs; ++k) {
+      Pair P = all[order[k]];
+      const int off = (int)kpp.size();
+      for (int q = 0; q < P.npp; ++q) kpp.push_back(pps[P.pp_off + q]);
+      P.pp_off = off;
+      kept[k] = P;
+      kI[k] = std::sqrt(smax[order[k]]);
+      kcls[k] = P.cls;
+      ksa[k] = P.sa;
+      ksb[k] = P.sb;
+      p->cls_beg[P.cls + 1]++;
+    }
+    for (int c = 0; c < NPAIRCLASS; ++c) p->cls_beg[c + 1] += p->cls_beg[c];
+    p->pairs = kept;
+    dfree(p->d_pairs);
+    dfree(p->d_pp);
+    if ((rc = dupload(&p->d_pairs, kept)) || (rc = dupload(&p->d_pp, kpp)) || (rc = dupload(&p->d_pairI, kI)) ||
+        (rc = dupload(&p->d_pair_cls, kcls)) || (rc = dupload(&p->d_pair_sa, ksa)) ||
+        (rc = dupload(&p->d_pair_sb, ksb)) || (rc = dupload(&p->d_cls_beg, p->cls_beg)))
+      return cleanup(rc);
+  }
+
+  // build workspace
+  const size_t nc2 = (size_t)p->nc * p->nc;
+  if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
+      (rc = dalloc(&p->d_Pblk, (size_t)ns * ns)) || (rc = dalloc(&p->d_gmax, 1)) ||
+      (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
+      (rc = dalloc(&p->d_list_off, NQCLASS)))
+    return cleanup(rc);
+  HIPCHK(hipDeviceSynchronize());
+  p->stats.npairs_kept = p->npairs;
+  p->stats.nao = p->nao;
+  p->stats.nao_cart = p->nc;
+  p->stats.nshell = ns;
+  p->stats.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = p;
+  return JK_OK;
+}
+
+int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *stream) {
+  if (!p) return fail(JK_EINVAL, "plan is NULL");
+  if (!D || !J || !K) return fail(JK_EINVAL, "D, J and K must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nc2 = (size_t)p->nc * p->nc;
+  HIPCHK(hipMemsetAsync(p->d_Jc, 0, nc2 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(p->d_Kc, 0, nc2 * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(p->d_gmax, 0, sizeof(double), st));
+  HIPCHK(hipMemsetAsync(p->d_cap, 0, sizeof(unsigned long long) * NQCLASS, st));
+  HIPCHK(hipMemsetAsync(p->d_count, 0, sizeof(int) * NQCLASS, st));
+  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+  HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+
+  ScreenArgs A{};
+  A.pairI = p->d_pairI;
+  A.pair_cls = p->d_pair_cls;
+  A.pair_sa = p->d_pair_sa;
+  A.pair_sb = p->d_pair_sb;
+  A.cls_beg = p->d_cls_beg;
+  A.Pblk = p->d_Pblk;
+  A.gmax = p->d_gmax;
+  A.cap = p->d_cap;
+  A.count = p->d_count;
+  A.list_off = p->d_list_off;
+  A.tau = p->tau;
+  A.npairs = p->npairs;
+  A.nshell = p->nshell;
+  if (p->npairs > 0) HIPCHK(launch_capacity(A, st));
+  unsigned long long cap[NQCLASS];
+  HIPCHK(hipMemcpyAsync(cap, p->d_cap, sizeof(cap), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  long long off[NQCLASS], total = 0;
+  for (int c = 0; c < NQCLASS; ++c) {
+    if (cap[c] > 0x7fffffffULL) return fail(JK_EUNSUPPORTED, "class %d: %llu candidate quartets exceed 2^31", c, cap[c]);
+    off[c] = total;
+    total += (long long)cap[c];
+  }
+  if (total > p->list_capacity) {
+    dfree(p->d_lists);
+    p->list_capacity = 0;
+    int rc = dalloc(&p->d_lists, (size_t)total + 1);
+    if (rc) return rc;
+    p->list_capacity = total;
+  }
+  HIPCHK(hipMemcpyAsync(p->d_list_off, off, sizeof(off), hipMemcpyHostToDevice, st));
+  A.lists = p->d_lists;
+  if (p->npairs > 0) HIPCHK(launch_screen(A, st));
+  for (int c = 0; c < NQCLASS; ++c) {
+    if (!cap[c]) continue;
+    int rc = launch_class_mode(p, c, MODE_JK, p->d_lists + off[c], p->d_count + c, (long long)cap[c], nullptr, st);
+    if (rc) return rc;
+  }
+  HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, J, K, st));
+  p->stats.candidate_quartets = total;
+  return JK_OK;
+}
+
+int jk_build(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh, double *J,
+             double *K, const jk_opts_t *opts, void *stream) {
+  jk_opts_t o{};
+  if (opts) o = *opts;
+  o.thresh = thresh;
+  jk_plan_t *p = nullptr;
+  int rc = jk_plan_create(basis, coords, natom, &o, &p);
+  if (rc) return rc;
+  rc = jk_plan_execute(p, D, J, K, stream);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  jk_plan_destroy(p);
+  return rc;
+}
+
+int jk_eri_tensor(jk_plan_t *p, double *eri, void *stream) {
+  if (!p || !eri) return fail(JK_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  // every (bra, ket) of kept pairs with bra class >= ket class (triangle inside a class)
+  std::vector<int2> lst;
+  std::vector<long long> off(NQCLASS + 1, 0);
+  std::vector<int> cnt(NQCLASS, 0);
+  for (int cb = 0; cb < NPAIRCLASS; ++cb)
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int qc = qclass_index(cb, ck);
+      off[qc] = (long long)lst.size();
+      for (int i = p->cls_beg[cb]; i < p->cls_beg[cb + 1]; ++i)
+        for (int k = p->cls_beg[ck]; k < p->cls_beg[ck + 1]; ++k) {
+          if (ck == cb && k > i) break;
+          lst.push_back(make_int2(i, k));
+        }
+      cnt[qc] = (int)((long long)lst.size() - off[qc]);
+    }
+  int2 *d_lst = nullptr;
+  int *d_cnt = nullptr;
+  int rc;
+  if ((rc = dupload(&d_lst, lst)) || (rc = dupload(&d_cnt, cnt))) {
+    dfree(d_lst);
+    return rc;
+  }
+  const size_t n4 = (size_t)p->nc * p->nc * p->nc * p->nc;
+  hipError_t e = hipMemsetAsync(eri, 0, n4 * sizeof(double), st);
+  if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
+  for (int cb = 0; cb < NPAIRCLASS && !rc; ++cb)
+    for (int ck = 0; ck <= cb && !rc; ++ck) {
+      const int qc = qclass_index(cb, ck);
+      if (!cnt[qc]) continue;
+      rc = launch_class_mode(p, qc, MODE_ERI, d_lst + off[qc], d_cnt + qc, cnt[qc], eri, st);
+    }
+  if (!rc) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  dfree(d_lst);
+  dfree(d_cnt);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+// Auxiliary kernels of the J/K build: density transform, block maxima, screening into
+// per-class quartet lists, and the final symmetrise + spherical transform.
+#include <hip/hip_runtime.h>
+
+#include "jk_aux.h"
+#include "jk_device.h"
+
+namespace jk {
+
+// D_cart[a][b] = sum_{mu in shell(a), nu in shell(b)} T[mu][a] D[mu][nu] T[nu][b]
+// (T = identity for Cartesian shells): the density in the Cartesian components, so that
+// digestion in the Cartesian basis followed by J = T Jc T^T reproduces the spherical result.
+__global__ void k_dcart(ShellInfo S, const double *__restrict__ D, double *__restrict__ Dc) {
+  const long long n = (long long)S.nc * S.nc;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    const int a = (int)(t / S.nc), b = (int)(t % S.nc);
+    const int sa = S.cart2shell[a], sb = S.cart2shell[b];
+    const int ia = a - S.cart_off[sa], ib = b - S.cart_off[sb];
+    const int la = S.l[sa], lb = S.l[sb];
+    const bool pa = S.pure[sa] && la >= 2, pb = S.pure[sb] && lb >= 2;
+    const int ma = pa ? 2 * la + 1 : 1, mb = pb ? 2 * lb + 1 : 1;
+    const double *Ta = pa ? S.tsph + S.toff[la] : nullptr;
+    const double *Tb = pb ? S.tsph + S.toff[lb] : nullptr;
+    const int na = ncart(la), nb = ncart(lb);
+    double v = 0.0;
+    for (int m = 0; m < ma; ++m) {
+      const int mu = S.ao_off[sa] + (pa ? m : ia);
+      const double ta = pa ? Ta[m * na + ia] : 1.0;
+      if (ta == 0.0) continue;
+      double r = 0.0;
+      for (int k = 0; k < mb; ++k) {
+        const int nu = S.ao_off[sb] + (pb ? k : ib);
+        const double tb = pb ? Tb[k * nb + ib] : 1.0;
+        r = fma(D[(size_t)mu * S.nao + nu], tb, r);
+      }
+      v = fma(ta, r, v);
+    }
+    Dc[t] = v;
+  }
+}
+
+// Pblk[i][j] = max |D_cart| over the block of shells i, j; *gmax = max over all blocks.
+__global__ void k_blockmax(ShellInfo S, const double *__restrict__ Dc, double *__restrict__ Pblk, double *gmax) {
+  const long long n = (long long)S.nshell * S.nshell;
+  double local = 0.0;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / S.nshell), j = (int)(t % S.nshell);
+    const int na = ncart(S.l[i]), nb = ncart(S.l[j]);
+    double m = 0.0;
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < nb; ++b) m = fmax(m, fabs(Dc[(size_t)(S.cart_off[i] + a) * S.nc + S.cart_off[j] + b]));
+    Pblk[t] = m;
+    local = fmax(local, m);
+  }
+  atomic_max_nonneg(gmax, local);
+}
+
+// Number of ket pairs of one class that can pass the screen for one bra pair, under
+// the global density bound: kets are sorted by I descending, so they form a prefix.
+__device__ __forceinline__ int ket_prefix(const double *__restrict__ Iket, int nket, double Ibra, double pglob,
+                                          double tau) {
+  if (tau <= 0.0) return nket;
+  const double prod = Ibra * pglob;
+  if (!(prod > 0.0)) return 0;
+  int lo = 0, hi = nket;          // first k with Ibra*Ik*pglob < tau
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (Ibra * Iket[mid] * pglob >= tau) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Upper bound of the kept quartets of every class (cap[120]), from the global bound.
+__global__ void k_capacity(ScreenArgs A) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.npairs; i += gridDim.x * blockDim.x) {
+    const int cb = A.pair_cls[i];
+    const int li = i - A.cls_beg[cb];
+    const double Ib = A.pairI[i];
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int nk = A.cls_beg[ck + 1] - A.cls_beg[ck];
+      int n = ket_prefix(A.pairI + A.cls_beg[ck], nk, Ib, *A.gmax, A.tau);
+      if (ck == cb) n = min(n, li + 1);
+      if (n > 0) atomicAdd(&A.cap[qclass_index(cb, ck)], (unsigned long long)n);
+    }
+  }
+}
+
+// One wave per bra pair: tests the candidates of every ket class with the exact
+// predicate I_ab I_cd P >= tau (P = max |D_cart| over the six shell-pair blocks) and
+// appends the kept (bra, ket) pairs to the class list with one atomic per wave step.
+__global__ void k_screen(ScreenArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const double tau = A.tau;
+  const double pglob = *A.gmax;
+  for (int i = wave; i < A.npairs; i += nwaves) {
+    const int cb = A.pair_cls[i];
+    const int li = i - A.cls_beg[cb];
+    const double Ib = A.pairI[i];
+    const int sa = A.pair_sa[i], sb = A.pair_sb[i];
+    const double *Pa = A.Pblk + (size_t)sa * A.nshell;
+    const double *Pb = A.Pblk + (size_t)sb * A.nshell;
+    const double pab = Pa[sb];
+    for (int ck = 0; ck <= cb; ++ck) {
+      const int kb = A.cls_beg[ck];
+      const int nk = A.cls_beg[ck + 1] - kb;
+      int n = ket_prefix(A.pairI + kb, nk, Ib, pglob, tau);
+      if (ck == cb) n = min(n, li + 1);
+      const int qc = qclass_index(cb, ck);
+      int2 *out = A.lists + A.list_off[qc];
+      for (int k0 = 0; k0 < n; k0 += 64) {
+        const int k = k0 + lane;
+        bool keep = false;
+        if (k < n) {
+          const int kg = kb + k;
+          const int sc = A.pair_sa[kg], sd = A.pair_sb[kg];
+          double p = pab;
+          p = fmax(p, A.Pblk[(size_t)sc * A.nshell + sd]);
+          p = fmax(p, Pa[sc]);
+          p = fmax(p, Pa[sd]);
+          p = fmax(p, Pb[sc]);
+          p = fmax(p, Pb[sd]);
+          keep = Ib * A.pairI[kg] * p >= tau;
+        }
+        const unsigned long long mask = __ballot(keep);
+        if (mask == 0ull) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&A.count[qc], __popcll(mask));
+        base = __shfl(base, 0);
+        if (keep) {
+          const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+          out[pos] = make_int2(i, kb + k);
+        }
+      }
+    }
+  }
+}
+
+// J[mu][nu] = sum_{a,b} T[mu][a] (Jc[a][b] + Jc[b][a]) T[nu][b], same for K.
+__global__ void k_finalize(ShellInfo S, const double *__restrict__ Jc, const double *__restrict__ Kc,
+                           double *__restrict__ J, double *__restrict__ K) {
+  const long long n = (long long)S.nao * S.nao;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+    const int mu = (int)(t / S.nao), nu = (int)(t % S.nao);
+    const int si = S.ao2shell[mu], sj = S.ao2shell[nu];
+    const int im = mu - S.ao_off[si], jn = nu - S.ao_off[sj];
+    const int li = S.l[si], lj = S.l[sj];
+    const bool pi = S.pure[si] && li >= 2, pj = S.pure[sj] && lj >= 2;
+    const int ni = ncart(li), nj = ncart(lj);
+    const double *Ti = pi ? S.tsph + S.toff[li] + im * ni : nullptr;
+    const double *Tj = pj ? S.tsph + S.toff[lj] + jn * nj : nullptr;
+    const int a0 = pi ? 0 : im, a1 = pi ? ni : im + 1;
+    const int b0 = pj ? 0 : jn, b1 = pj ? nj : jn + 1;
+    double vj = 0.0, vk = 0.0;
+    for (int a = a0; a < a1; ++a) {
+      const double ta = pi ? Ti[a] : 1.0;
+      if (ta == 0.0) continue;
+      double rj = 0.0, rk = 0.0;
+      const size_t ra = (size_t)(S.cart_off[si] + a);
+      for (int b = b0; b < b1; ++b) {
+        const double tb = pj ? Tj[b] : 1.0;
+        const size_t rb = (size_t)(S.cart_off[sj] + b);
+        rj = fma(tb, Jc[ra * S.nc + rb] + Jc[rb * S.nc + ra], rj);
+        rk = fma(tb, Kc[ra * S.nc + rb] + Kc[rb * S.nc + ra], rk);
+      }
+      vj = fma(ta, rj, vj);
+      vk = fma(ta, rk, vk);
+    }
+    J[t] = vj;
+    K[t] = vk;
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long long v) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+__global__ void k_fill_i32(int *p, long long n, int v) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+static int grid_for(long long n, int block) {
+  long long g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  return (int)g;
+}
+
+hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, hipStream_t st) {
+  hipLaunchKernelGGL(k_dcart, dim3(grid_for((long long)S.nc * S.nc, 256)), dim3(256), 0, st, S, D, Dc);
+  return hipGetLastError();
+}
+hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, double *gmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_blockmax, dim3(grid_for((long long)S.nshell * S.nshell, 256)), dim3(256), 0, st, S, Dc, Pblk,
+                     gmax);
+  return hipGetLastError();
+}
+hipError_t launch_capacity(const ScreenArgs &A, hipStream_t st) {
+  hipLaunchKernelGGL(k_capacity, dim3(grid_for(A.npairs, 256)), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+hipError_t launch_screen(const ScreenArgs &A, hipStream_t st) {
+  long long waves = A.npairs;
+  int grid = (int)((waves * 64 + 255) / 256);
+  if (grid > 16384) grid = 16384;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_screen, dim3(grid), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for((long long)S.nao * S.nao, 256)), dim3(256), 0, st, S, Jc, Kc, J, K);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int *p, long long n, int v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace jk

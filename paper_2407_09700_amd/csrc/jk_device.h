@@ -1,0 +1,178 @@
+// Device building blocks of the J/K build on gfx950 (included by the class translation units).
+//
+// ERI evaluation follows the Rys quadrature of the paper (section 2): for a primitive
+// quartet [ab|cd] the integral is a sum over N = floor((la+lb+lc+ld)/2) + 1 roots of
+// the product of three 2D integrals. Here the 2D integrals G(e, f) (e quanta on A, f on C)
+// come from the Rys two-dimensional recurrence in the variable u = t^2:
+//   G(e+1, f) = C00 G(e,f) + e B10 G(e-1,f) + f B00 G(e,f-1)
+//   G(e, f+1) = C00' G(e,f) + f B01 G(e,f-1) + e B00 G(e-1,f)
+//   B00 = u / (2(p+q)),  B10 = (1 - u q/(p+q)) / (2p),  B01 = (1 - u p/(p+q)) / (2q)
+//   C00 = (P-A) - u q/(p+q) (P-Q),  C00' = (Q-C) + u p/(p+q) (P-Q)
+// with the Rys weight and the prefactor 2 pi^(5/2) / (p q sqrt(p+q)) K_ab K_cd folded into
+// the z direction (paper section 3 folds weights and coefficients into the 2D integrals).
+// Products are accumulated over primitives at the [e0|f0] level (e = a + k on centre A,
+// f = c + k' on centre C); the transfer to (ab|cd) is applied once per contracted quartet
+// with the binomial form of the horizontal relation
+//   (a b| = sum_k C(b,k) (A-B)^(b-k) (a+k, 0|   (componentwise), and likewise for |c d).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "jk_common.h"
+
+#define RYS_STORAGE static __device__ const
+#include "rys_table.h"
+
+namespace jk {
+
+// ------------------------------------------------------------------ Cartesian tables
+struct CartTable {
+  int x[165], y[165], z[165];
+  int start[10];          // first flat index of each total degree 0..8 (start[9] = 165)
+  int idx[9][9][9];       // flat index of (x, y, z)
+};
+
+constexpr CartTable make_cart_table() {
+  CartTable t{};
+  int n = 0;
+  for (int L = 0; L <= 8; ++L) {
+    t.start[L] = n;
+    for (int ax = L; ax >= 0; --ax)
+      for (int ay = L - ax; ay >= 0; --ay) {
+        t.x[n] = ax; t.y[n] = ay; t.z[n] = L - ax - ay;
+        t.idx[ax][ay][L - ax - ay] = n;
+        ++n;
+      }
+  }
+  t.start[9] = n;
+  return t;
+}
+
+static constexpr CartTable CT = make_cart_table();
+static __constant__ CartTable CTD = make_cart_table();   // for run-time indexing
+
+constexpr __host__ __device__ int range_count(int lo, int hi) {  // components of degrees lo..hi
+  int n = 0;
+  for (int L = lo; L <= hi; ++L) n += ncart(L);
+  return n;
+}
+
+constexpr __host__ __device__ int binom(int n, int k) {
+  int r = 1;
+  for (int i = 0; i < k; ++i) r = r * (n - i) / (i + 1);
+  return r;
+}
+
+constexpr double PI_2P5_X2 = 34.98683665524972;   // 2 pi^(5/2)
+
+// ------------------------------------------------------------------ Rys roots and weights
+// All N roots for one T (compile-time N). Interval k = floor(T) of width 1 carries a
+// degree-RYS_DEG polynomial in s = 2(T - k) - 1 per root and weight; beyond RYS_TMAX[N]
+// the Gauss-Hermite limit u = s^2 / T, w = W / sqrt(T) holds to double precision.
+template <int N>
+__device__ __forceinline__ void rys_roots(double T, double (&u)[N], double (&w)[N]) {
+  if (T >= (double)RYS_TMAX[N]) {
+    const double it = 1.0 / T;
+    const double isq = sqrt(it);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      u[n] = RYS_HERM_S2[RYS_HOFF[N] + n] * it;
+      w[n] = RYS_HERM_W[RYS_HOFF[N] + n] * isq;
+    }
+  } else {
+    const int k = min(max((int)T, 0), RYS_TMAX[N] - 1);   // T is finite and >= 0; the clamp only guards the table
+    const double s = 2.0 * (T - (double)k) - 1.0;
+    const double *c = RYS_COEF + RYS_OFF[N] + k * (N * 2 * (RYS_DEG + 1));
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      const double *cu = c + n * 2 * (RYS_DEG + 1);
+      const double *cw = cu + (RYS_DEG + 1);
+      double pu = cu[RYS_DEG], pw = cw[RYS_DEG];
+#pragma unroll
+      for (int d = RYS_DEG - 1; d >= 0; --d) {
+        pu = fma(pu, s, cu[d]);
+        pw = fma(pw, s, cw[d]);
+      }
+      u[n] = pu;
+      w[n] = pw;
+    }
+  }
+}
+
+// One root n (run-time) of the N-point rule.
+template <int N>
+__device__ __forceinline__ void rys_root1(double T, int n, double &u, double &w) {
+  if (T >= (double)RYS_TMAX[N]) {
+    const double it = 1.0 / T;
+    u = RYS_HERM_S2[RYS_HOFF[N] + n] * it;
+    w = RYS_HERM_W[RYS_HOFF[N] + n] * sqrt(it);
+  } else {
+    const int k = min(max((int)T, 0), RYS_TMAX[N] - 1);
+    const double s = 2.0 * (T - (double)k) - 1.0;
+    const double *cu = RYS_COEF + RYS_OFF[N] + k * (N * 2 * (RYS_DEG + 1)) + n * 2 * (RYS_DEG + 1);
+    const double *cw = cu + (RYS_DEG + 1);
+    double pu = cu[RYS_DEG], pw = cw[RYS_DEG];
+#pragma unroll
+    for (int d = RYS_DEG - 1; d >= 0; --d) {
+      pu = fma(pu, s, cu[d]);
+      pw = fma(pw, s, cw[d]);
+    }
+    u = pu;
+    w = pw;
+  }
+}
+
+// ------------------------------------------------------------------ 2D recurrence
+template <int E, int F>
+__device__ __forceinline__ void vrr2d(double (&G)[E + 1][F + 1], double g00, double c00, double c00p, double b10,
+                                      double b01, double b00) {
+  G[0][0] = g00;
+  if constexpr (E > 0) G[1][0] = c00 * g00;
+#pragma unroll
+  for (int e = 1; e < E; ++e) G[e + 1][0] = fma(c00, G[e][0], (double)e * b10 * G[e - 1][0]);
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+#pragma unroll
+    for (int e = 0; e <= E; ++e) {
+      double v = c00p * G[e][f];
+      if (f > 0) v = fma((double)f * b01, G[e][f - 1], v);
+      if (e > 0) v = fma((double)e * b00, G[e - 1][f], v);
+      G[e][f + 1] = v;
+    }
+  }
+}
+
+// Per-primitive-quartet scalars shared by the roots.
+struct PrimQuartet {
+  double p, q, pq_inv, PQ[3], PA[3], QC[3], pref, T;
+};
+
+__device__ __forceinline__ void prim_quartet(const PrimPair &b, const PrimPair &k, const double *A, const double *C,
+                                             PrimQuartet &o) {
+  o.p = b.p;
+  o.q = k.p;
+  const double pq = b.p + k.p;
+  o.pq_inv = 1.0 / pq;
+  o.PQ[0] = b.Px - k.Px; o.PQ[1] = b.Py - k.Py; o.PQ[2] = b.Pz - k.Pz;
+  o.PA[0] = b.Px - A[0]; o.PA[1] = b.Py - A[1]; o.PA[2] = b.Pz - A[2];
+  o.QC[0] = k.Px - C[0]; o.QC[1] = k.Py - C[1]; o.QC[2] = k.Pz - C[2];
+  const double rho = b.p * k.p * o.pq_inv;
+  o.T = rho * (o.PQ[0] * o.PQ[0] + o.PQ[1] * o.PQ[1] + o.PQ[2] * o.PQ[2]);
+  o.pref = PI_2P5_X2 / (b.p * k.p * sqrt(pq)) * b.K * k.K;
+}
+
+// Symmetry factor of a unique shell quartet: 1 / |stabiliser| in the eight-fold group.
+__device__ __forceinline__ double sym_factor(const Pair &bra, const Pair &ket, int bi, int ki) {
+  double s = 1.0;
+  if (bra.sa == bra.sb) s *= 0.5;
+  if (ket.sa == ket.sb) s *= 0.5;
+  if (bi == ki) s *= 0.5;
+  return s;
+}
+
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+__device__ __forceinline__ void atomic_max_nonneg(double *p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+}  // namespace jk

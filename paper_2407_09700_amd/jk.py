@@ -1,0 +1,181 @@
+"""Python binding of libjk.so (argument marshalling only; every step runs in the library).
+
+The library must be built (``python -m paper_2407_09700_amd.build``); importing this
+module without it raises immediately -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjk.so")
+
+JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE, JK_ENODEV = 0, -1, -2, -3, -4, -5
+JK_FP64, JK_MIXED = 0, 1
+
+# every symbol declared in include/jk.h
+EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_build", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
+           "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_last_error"]
+
+
+class JKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"jk error {code}: {msg}")
+        self.code = code
+
+
+class Basis(ctypes.Structure):
+    _fields_ = [("nshell", ctypes.c_int), ("atom", ctypes.POINTER(ctypes.c_int)), ("l", ctypes.POINTER(ctypes.c_int)),
+                ("nprim", ctypes.POINTER(ctypes.c_int)), ("prim_off", ctypes.POINTER(ctypes.c_int)),
+                ("pure", ctypes.POINTER(ctypes.c_int)), ("nprim_total", ctypes.c_int),
+                ("exps", ctypes.POINTER(ctypes.c_double)), ("coefs", ctypes.POINTER(ctypes.c_double))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("thresh", ctypes.c_double), ("precision", ctypes.c_int), ("fp32_cutoff", ctypes.c_double),
+                ("flags", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kept_quartets", ctypes.c_longlong), ("candidate_quartets", ctypes.c_longlong),
+                ("kept_fp32", ctypes.c_longlong), ("prim_quartets", ctypes.c_longlong),
+                ("npairs_kept", ctypes.c_int), ("nao", ctypes.c_int), ("nao_cart", ctypes.c_int),
+                ("nshell", ctypes.c_int), ("plan_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2407_09700_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.jk_plan_create.argtypes = [ctypes.POINTER(Basis), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                     ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.jk_plan_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.jk_build.argtypes = [ctypes.POINTER(Basis), ctypes.POINTER(ctypes.c_double), ctypes.c_int, vp,
+                               ctypes.c_double, vp, vp, ctypes.POINTER(Opts), vp]
+        L.jk_plan_destroy.argtypes = [vp]
+        L.jk_plan_destroy.restype = None
+        L.jk_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.jk_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.jk_eri_tensor.argtypes = [vp, vp, vp]
+        L.jk_schwarz.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.jk_sph_matrix.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.jk_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().jk_last_error().decode()
+
+
+def check(rc):
+    if rc != JK_OK:
+        raise JKError(rc, last_error())
+
+
+def sph_matrix(l: int) -> np.ndarray:
+    out = np.zeros((2 * l + 1) * (l + 1) * (l + 2) // 2)
+    check(lib().jk_sph_matrix(int(l), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(2 * l + 1, (l + 1) * (l + 2) // 2)
+
+
+class BasisArrays:
+    """Keeps the numpy arrays behind a Basis struct alive."""
+
+    def __init__(self, shell_atom, shell_l, shell_nprim, shell_off, shell_pure, prim_exp, prim_coef):
+        ip = ctypes.POINTER(ctypes.c_int)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.arrs = [np.ascontiguousarray(a, np.int32) for a in (shell_atom, shell_l, shell_nprim, shell_off, shell_pure)]
+        self.exps = np.ascontiguousarray(prim_exp, np.float64)
+        self.coefs = np.ascontiguousarray(prim_coef, np.float64)
+        a = self.arrs
+        self.struct = Basis(len(a[1]), a[0].ctypes.data_as(ip), a[1].ctypes.data_as(ip), a[2].ctypes.data_as(ip),
+                            a[3].ctypes.data_as(ip), a[4].ctypes.data_as(ip), len(self.exps),
+                            self.exps.ctypes.data_as(dp), self.coefs.ctypes.data_as(dp))
+
+    @classmethod
+    def from_molecule(cls, mol):
+        return cls(mol.shell_atom, mol.shell_l, mol.shell_nprim, mol.shell_off, mol.shell_pure, mol.prim_exp,
+                   mol.prim_coef)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+class Plan:
+    """A J/K plan for one molecule. D, J, K are torch float64 CUDA tensors (nao x nao)."""
+
+    def __init__(self, coords, basis: BasisArrays, thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6):
+        self.basis = basis
+        self.coords = np.ascontiguousarray(coords, np.float64)
+        self.opts = Opts(float(thresh), int(precision), float(fp32_cutoff), 0)
+        h = ctypes.c_void_p()
+        check(lib().jk_plan_create(ctypes.byref(basis.struct),
+                                   self.coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   int(self.coords.shape[0]), ctypes.byref(self.opts), ctypes.byref(h)))
+        self.h = h
+        nao, nc = ctypes.c_int(), ctypes.c_int()
+        check(lib().jk_plan_sizes(self.h, ctypes.byref(nao), ctypes.byref(nc)))
+        self.nao, self.nao_cart = nao.value, nc.value
+
+    @classmethod
+    def from_molecule(cls, mol, thresh=None, **kw):
+        return cls(mol.coords, BasisArrays.from_molecule(mol), mol.thresh if thresh is None else thresh, **kw)
+
+    def execute(self, D, J=None, K=None, stream=None):
+        import torch
+        assert D.dtype == torch.float64 and D.is_cuda and D.is_contiguous() and D.shape == (self.nao, self.nao)
+        if J is None:
+            J = torch.empty_like(D)
+        if K is None:
+            K = torch.empty_like(D)
+        for t in (J, K):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.shape == (self.nao, self.nao)
+        check(lib().jk_plan_execute(self.h, _ptr(D), _ptr(J), _ptr(K), _stream(stream)))
+        return J, K
+
+    def eri_tensor(self, stream=None):
+        import torch
+        n = self.nao_cart
+        out = torch.empty((n, n, n, n), dtype=torch.float64, device="cuda")
+        check(lib().jk_eri_tensor(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def schwarz(self):
+        ns = len(self.basis.arrs[1])
+        out = np.zeros((ns, ns))
+        check(lib().jk_schwarz(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def stats(self):
+        s = Stats()
+        check(lib().jk_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().jk_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

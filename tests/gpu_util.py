@@ -1,0 +1,28 @@
+"""Helpers for the GPU parity tests: run the HIP library and the oracle on one molecule."""
+import sys
+
+import numpy as np
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_jk(mol, thresh=None, D=None, repeat=1):
+    import torch
+    from paper_2407_09700_amd import jk
+    plan = jk.Plan.from_molecule(mol, thresh=thresh)
+    Dt = torch.from_numpy(np.ascontiguousarray(mol.D if D is None else D)).cuda()
+    out = []
+    for _ in range(repeat):
+        J, K = plan.execute(Dt)
+        torch.cuda.synchronize()
+        out.append((J.cpu().numpy(), K.cpu().numpy()))
+    stats = plan.stats()
+    plan.close()
+    return (out if repeat > 1 else out[0]), stats
+
+
+def maxabs(a, b):
+    return float(np.max(np.abs(a - b))) if a.size else 0.0
