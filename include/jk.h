@@ -51,6 +51,8 @@ extern "C" {
 #define JK_FP64 0
 #define JK_MIXED 1
 
+#define JK_FLAG_PROFILE 1     /* jk_opts_t.flags: time every kernel launch of jk_plan_execute */
+
 typedef struct {
   int nshell;
   const int *atom;       /* [nshell] atom index of each shell, 0 <= atom < natom */
@@ -67,7 +69,7 @@ typedef struct {
   double thresh;         /* tau: quartet kept iff I_ab > tau, I_cd > tau, I_ab I_cd P >= tau */
   int precision;         /* JK_FP64 (default) or JK_MIXED */
   double fp32_cutoff;    /* JK_MIXED: quartets with I_ab I_cd P below this run in FP32 */
-  int flags;             /* reserved, 0 */
+  int flags;             /* JK_FLAG_PROFILE or 0 */
 } jk_opts_t;
 
 typedef struct jk_plan jk_plan_t;
@@ -108,6 +110,28 @@ int jk_plan_sizes(const jk_plan_t *plan, int *nao, int *nao_cart);
 
 /* Statistics of the plan and its last execute (HOST struct). */
 int jk_stats(const jk_plan_t *plan, jk_stats_t *out);
+
+/* Per-launch profile of the last jk_plan_execute of a plan created with JK_FLAG_PROFILE.
+ * One entry per quartet class that had work (kind 0), plus the preparation launches
+ * (kind 1: density transform, block maxima, screening) and the final symmetrise and
+ * transform (kind 2). ms is the HIP-event time of the launch on the caller's stream;
+ * flops is the algorithmic count of the class, prim_quartets * 3 N nc(a)nc(b)nc(c)nc(d)
+ * (the three-operand Rys product of section 2 per root) plus quartets * 12
+ * nc(a)nc(b)nc(c)nc(d) (the six multiply-adds per integral of the digestion, Algorithm
+ * 2). out is HOST memory of max_entries entries; *n_entries receives the count.
+ * Synchronises the plan's last stream. */
+typedef struct {
+  int kind;                     /* 0 class kernel, 1 preparation, 2 finalisation */
+  int la, lb, lc, ld;           /* class (kind 0) */
+  int team;                     /* 1 workgroup-per-quartet kernel, 0 lane-per-quartet */
+  int nroots;                   /* Rys roots N of the class */
+  long long quartets;           /* kept unique shell quartets */
+  long long prim_quartets;      /* their primitive quartets */
+  double ms;                    /* kernel time */
+  double flops;                 /* algorithmic flops (see above) */
+} jk_profile_t;
+
+int jk_profile(jk_plan_t *plan, jk_profile_t *out, int max_entries, int *n_entries);
 
 /* Test hook: full Cartesian ERI tensor (DEVICE, nao_cart^4 doubles, overwritten),
  * unscreened, with the same integral kernels as jk_plan_execute. Small inputs only. */

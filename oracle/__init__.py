@@ -53,6 +53,8 @@ def lib():
         L.oracle_jk_block.argtypes = basis + [dp, ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_int,
                                               dp, dp, ctypes.c_int]
         L.oracle_screen_tables.argtypes = basis + [dp, dp, dp]
+        L.oracle_jk_sample.argtypes = basis + [dp, ctypes.c_double, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int]
+        L.oracle_jk_sample.restype = ctypes.c_longlong
         L.oracle_count_kept.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double]
         L.oracle_count_kept.restype = ctypes.c_longlong
         _lib = L
@@ -145,6 +147,13 @@ class Oracle:
         Pp = None if P is None else _p(np.ascontiguousarray(P, np.float64))
         lib().oracle_jk_block(*self._b(), _p(D), tau, Ip, Pp, int(si), int(sj), _p(Jb), _p(Kb), int(nthreads))
         return Jb, Kb
+
+    def jk_sample(self, stride, offset=0, D=None, tau=None, nthreads=0):
+        """Run the full J/K loop on the unique quartets of every stride-th bra pair;
+        returns the number of kept quartets processed (for timing)."""
+        D = np.ascontiguousarray(self.mol.D if D is None else D, np.float64)
+        tau = float(self.mol.thresh if tau is None else tau)
+        return int(lib().oracle_jk_sample(*self._b(), _p(D), tau, int(stride), int(offset), int(nthreads)))
 
     def count_kept(self, I, P, tau):
         I = np.ascontiguousarray(I, np.float64)

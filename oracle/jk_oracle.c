@@ -671,3 +671,69 @@ int oracle_eri_tensor(const double *coords, int nshell, const int *sh_atom, cons
   free(off);
   return 0;
 }
+
+/* Bounded sample of the full J/K loop, for timing: the unique quartets (ij|kl), kl <= ij,
+ * of every bra pair index ij with ij % stride == offset, evaluated and digested exactly
+ * as in oracle_jk (same screening, same explicit updates into private J/K that are then
+ * discarded). Returns the number of kept unique quartets processed. */
+long long oracle_jk_sample(const double *coords, int nshell, const int *sh_atom, const int *sh_l, const int *sh_nprim,
+                           const int *sh_off, const int *sh_pure, const double *pexp, const double *pcoef,
+                           const double *tsph, const double *D, double tau, long long stride, long long offset,
+                           int nthreads) {
+  init_tables();
+  basis_t B; make_basis(&B, coords, nshell, sh_atom, sh_l, sh_nprim, sh_off, sh_pure, pexp, pcoef, tsph);
+  int *off = (int *)malloc(sizeof(int) * (nshell + 1));
+  ao_offsets(&B, off);
+  const int nbf = off[nshell];
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  double *I = (double *)malloc(sizeof(double) * nshell * nshell);
+  double *P = (double *)malloc(sizeof(double) * nshell * nshell);
+  oracle_schwarz(coords, nshell, sh_atom, sh_l, sh_nprim, sh_off, sh_pure, pexp, pcoef, tsph, I);
+  density_blockmax(&B, off, D, nbf, P);
+  const long long npair = (long long)nshell * (nshell + 1) / 2;
+  long long kept = 0;
+#pragma omp parallel reduction(+ : kept)
+  {
+    work_t w; work_alloc(&w);
+    double *cart = (double *)malloc(sizeof(double) * BLK_MAX), *fin = (double *)malloc(sizeof(double) * BLK_MAX);
+    double *tmp = (double *)malloc(sizeof(double) * BLK_MAX), *img = (double *)malloc(sizeof(double) * BLK_MAX);
+    double *Jt = (double *)calloc((size_t)nbf * nbf, sizeof(double));
+    double *Kt = (double *)calloc((size_t)nbf * nbf, sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+    for (long long ij = offset; ij < npair; ij += stride) {
+      int i = (int)((sqrt(8.0 * ij + 1) - 1) / 2);
+      while ((long long)i * (i + 1) / 2 > ij) --i;
+      while ((long long)(i + 1) * (i + 2) / 2 <= ij) ++i;
+      const int j = (int)(ij - (long long)i * (i + 1) / 2);
+      for (long long kl = 0; kl <= ij; ++kl) {
+        int k = (int)((sqrt(8.0 * kl + 1) - 1) / 2);
+        while ((long long)k * (k + 1) / 2 > kl) --k;
+        while ((long long)(k + 1) * (k + 2) / 2 <= kl) ++k;
+        const int l = (int)(kl - (long long)k * (k + 1) / 2);
+        if (!keep_quartet(I, P, nshell, i, j, k, l, tau)) continue;
+        ++kept;
+        const int sh[4] = {i, j, k, l};
+        eri_cart(&B, i, j, k, l, &w, cart);
+        to_final(&B, sh, cart, fin, tmp);
+        const int n[4] = {nsph(sh_l[i], sh_pure[i]), nsph(sh_l[j], sh_pure[j]),
+                          nsph(sh_l[k], sh_pure[k]), nsph(sh_l[l], sh_pure[l])};
+        int seen[8][4], nseen = 0;
+        for (int p = 0; p < 8; ++p) {
+          int t[4];
+          for (int q = 0; q < 4; ++q) t[q] = sh[PERMS[p][q]];
+          int dup = 0;
+          for (int s = 0; s < nseen; ++s)
+            if (seen[s][0] == t[0] && seen[s][1] == t[1] && seen[s][2] == t[2] && seen[s][3] == t[3]) dup = 1;
+          if (dup) continue;
+          memcpy(seen[nseen++], t, sizeof(t));
+          int nout[4];
+          permute_block(fin, n, PERMS[p], img, nout);
+          digest(off, nbf, D, img, t, nout, Jt, Kt);
+        }
+      }
+    }
+    free(Jt); free(Kt); free(cart); free(fin); free(tmp); free(img); work_free(&w);
+  }
+  free(I); free(P); free(off);
+  return kept;
+}

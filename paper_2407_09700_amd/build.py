@@ -22,8 +22,18 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-ato
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps.append(os.path.join(HERE, "..", "include", "jk.h"))
+    return max(os.path.getmtime(d) for d in deps) > os.path.getmtime(obj)
+
+
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if os.environ.get("JK_RESOURCE_USAGE"):
         cmd.append("-Rpass-analysis=kernel-resource-usage")
@@ -36,14 +46,15 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = True, force: bool = True) -> str:
+    """Compile every source (force=True, the default) or only stale ones, then link."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or int(os.environ.get("MAX_JOBS", "0")) or min(8, os.cpu_count() or 1)
     t0 = time.time()
     # biggest units first
     order = sorted(SOURCES, key=lambda s: -("l4" in s) * 4 - ("l3" in s) * 3 - ("l2" in s) * 2)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = dict(zip(order, ex.map(_compile, order)))
+        objs = dict(zip(order, ex.map(lambda s: _compile(s, force), order)))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[objs[s] for s in SOURCES], "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,4 +70,4 @@ if __name__ == "__main__":
     j = None
     if "-j" in sys.argv:
         j = int(sys.argv[sys.argv.index("-j") + 1])
-    build(j)
+    build(j, force="--incremental" not in sys.argv)

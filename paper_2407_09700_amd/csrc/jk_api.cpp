@@ -158,8 +158,12 @@ struct jk_plan {
   int *d_cart2shell = nullptr, *d_ao2shell = nullptr;
   double *d_tsph = nullptr;
   double *d_Dc = nullptr, *d_Jc = nullptr, *d_Kc = nullptr, *d_Pblk = nullptr, *d_gmax = nullptr;
-  unsigned long long *d_cap = nullptr;
-  int *d_count = nullptr;
+  unsigned long long *d_cap = nullptr, *d_nprim = nullptr;
+  int *d_count = nullptr, *d_pair_npp = nullptr;
+  int flags = 0;
+  hipStream_t last_stream = nullptr;
+  std::vector<hipEvent_t> events;      // profiling: 2 per class + prep + finalize
+  unsigned long long cap_last[NQCLASS] = {0};
   long long *d_list_off = nullptr;
   int2 *d_lists = nullptr;
   long long list_capacity = 0;
@@ -177,7 +181,9 @@ void plan_free(jk_plan *p) {
   dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_l); dfree(p->d_pure); dfree(p->d_cart_off);
   dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell); dfree(p->d_tsph); dfree(p->d_Dc);
   dfree(p->d_Jc); dfree(p->d_Kc); dfree(p->d_Pblk); dfree(p->d_gmax); dfree(p->d_cap); dfree(p->d_count);
-  dfree(p->d_list_off); dfree(p->d_lists); dfree(p->d_scratch);
+  dfree(p->d_list_off); dfree(p->d_lists); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  p->events.clear();
 }
 
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes for k_small
@@ -320,6 +326,63 @@ int jk_plan_sizes(const jk_plan_t *plan, int *nao, int *nao_cart) {
 int jk_stats(const jk_plan_t *plan, jk_stats_t *out) {
   if (!plan || !out) return fail(JK_EINVAL, "NULL argument");
   *out = plan->stats;
+  if (plan->d_count) {
+    int cnt[NQCLASS];
+    unsigned long long np[NQCLASS];
+    HIPCHK(hipStreamSynchronize(plan->last_stream));
+    HIPCHK(hipMemcpy(cnt, plan->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(np, plan->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
+    out->kept_quartets = 0;
+    out->prim_quartets = 0;
+    for (int c = 0; c < NQCLASS; ++c) {
+      out->kept_quartets += cnt[c];
+      out->prim_quartets += (long long)np[c];
+    }
+  }
+  return JK_OK;
+}
+
+int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries) {
+  if (!p || !out || !n_entries) return fail(JK_EINVAL, "NULL argument");
+  if (!(p->flags & JK_FLAG_PROFILE)) return fail(JK_EINVAL, "plan was not created with JK_FLAG_PROFILE");
+  HIPCHK(hipStreamSynchronize(p->last_stream));
+  int cnt[NQCLASS];
+  unsigned long long np[NQCLASS];
+  HIPCHK(hipMemcpy(cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(np, p->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
+  int n = 0;
+  auto push = [&](const jk_profile_t &e) {
+    if (n < max_entries) out[n] = e;
+    ++n;
+  };
+  float ms = 0.f;
+  jk_profile_t e{};
+  e.kind = 1;
+  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NQCLASS], p->events[2 * NQCLASS + 1]));
+  e.ms = ms;
+  push(e);
+  for (int c = 0; c < NQCLASS; ++c) {
+    if (!p->cap_last[c]) continue;
+    const ClassInfo &ci = g_classes[c];
+    jk_profile_t r{};
+    r.kind = 0;
+    r.la = ci.la; r.lb = ci.lb; r.lc = ci.lc; r.ld = ci.ld;
+    r.team = ci.team;
+    r.nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
+    r.quartets = cnt[c];
+    r.prim_quartets = (long long)np[c];
+    HIPCHK(hipEventElapsedTime(&ms, p->events[2 * c], p->events[2 * c + 1]));
+    r.ms = ms;
+    const double nel = (double)ncart(ci.la) * ncart(ci.lb) * ncart(ci.lc) * ncart(ci.ld);
+    r.flops = (double)r.prim_quartets * 3.0 * r.nroots * nel + (double)r.quartets * 12.0 * nel;
+    push(r);
+  }
+  e = jk_profile_t{};
+  e.kind = 2;
+  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NQCLASS + 2], p->events[2 * NQCLASS + 3]));
+  e.ms = ms;
+  push(e);
+  *n_entries = n;
   return JK_OK;
 }
 
@@ -362,6 +425,7 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
   p->tau = tau;
   p->precision = precision;
   p->fp32_cutoff = fp32_cutoff;
+  p->flags = opts ? opts->flags : 0;
   (void)hipGetDevice(&p->device);
   const int ns = B->nshell;
   p->l.assign(B->l, B->l + ns);
@@ -466,7 +530,7 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
     std::vector<Pair> kept(p->npairs);
     std::vector<PrimPair> kpp;
     std::vector<double> kI(p->npairs);
-    std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs);
+    std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs), knpp(p->npairs);
     p->cls_beg.assign(NPAIRCLASS + 1, 0);
     for (int k = 0; k < p->npairs; ++k) {
       Pair P = all[order[k]];
@@ -478,6 +542,7 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
       kcls[k] = P.cls;
       ksa[k] = P.sa;
       ksb[k] = P.sb;
+      knpp[k] = P.npp;
       p->cls_beg[P.cls + 1]++;
     }
     for (int c = 0; c < NPAIRCLASS; ++c) p->cls_beg[c + 1] += p->cls_beg[c];
@@ -486,7 +551,8 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
     dfree(p->d_pp);
     if ((rc = dupload(&p->d_pairs, kept)) || (rc = dupload(&p->d_pp, kpp)) || (rc = dupload(&p->d_pairI, kI)) ||
         (rc = dupload(&p->d_pair_cls, kcls)) || (rc = dupload(&p->d_pair_sa, ksa)) ||
-        (rc = dupload(&p->d_pair_sb, ksb)) || (rc = dupload(&p->d_cls_beg, p->cls_beg)))
+        (rc = dupload(&p->d_pair_sb, ksb)) || (rc = dupload(&p->d_cls_beg, p->cls_beg)) ||
+        (rc = dupload(&p->d_pair_npp, knpp)))
       return cleanup(rc);
   }
 
@@ -495,8 +561,13 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
   if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
       (rc = dalloc(&p->d_Pblk, (size_t)ns * ns)) || (rc = dalloc(&p->d_gmax, 1)) ||
       (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
-      (rc = dalloc(&p->d_list_off, NQCLASS)))
+      (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_list_off, NQCLASS)))
     return cleanup(rc);
+  if (p->flags & JK_FLAG_PROFILE) {
+    p->events.resize(2 * NQCLASS + 4, nullptr);
+    for (auto &e : p->events)
+      if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(JK_EDEVICE, "hipEventCreate failed"));
+  }
   HIPCHK(hipDeviceSynchronize());
   p->stats.npairs_kept = p->npairs;
   p->stats.nao = p->nao;
@@ -517,6 +588,10 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   HIPCHK(hipMemsetAsync(p->d_gmax, 0, sizeof(double), st));
   HIPCHK(hipMemsetAsync(p->d_cap, 0, sizeof(unsigned long long) * NQCLASS, st));
   HIPCHK(hipMemsetAsync(p->d_count, 0, sizeof(int) * NQCLASS, st));
+  HIPCHK(hipMemsetAsync(p->d_nprim, 0, sizeof(unsigned long long) * NQCLASS, st));
+  const bool prof = (p->flags & JK_FLAG_PROFILE) != 0;
+  p->last_stream = st;
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS], st));
   HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
   HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
 
@@ -530,6 +605,8 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   A.gmax = p->d_gmax;
   A.cap = p->d_cap;
   A.count = p->d_count;
+  A.nprim = p->d_nprim;
+  A.pair_npp = p->d_pair_npp;
   A.list_off = p->d_list_off;
   A.tau = p->tau;
   A.npairs = p->npairs;
@@ -554,12 +631,18 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   HIPCHK(hipMemcpyAsync(p->d_list_off, off, sizeof(off), hipMemcpyHostToDevice, st));
   A.lists = p->d_lists;
   if (p->npairs > 0) HIPCHK(launch_screen(A, st));
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS + 1], st));
   for (int c = 0; c < NQCLASS; ++c) {
+    p->cap_last[c] = cap[c];
     if (!cap[c]) continue;
+    if (prof) HIPCHK(hipEventRecord(p->events[2 * c], st));
     int rc = launch_class_mode(p, c, MODE_JK, p->d_lists + off[c], p->d_count + c, (long long)cap[c], nullptr, st);
     if (rc) return rc;
+    if (prof) HIPCHK(hipEventRecord(p->events[2 * c + 1], st));
   }
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS + 2], st));
   HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, J, K, st));
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS + 3], st));
   p->stats.candidate_quartets = total;
   return JK_OK;
 }

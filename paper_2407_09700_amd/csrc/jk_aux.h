@@ -22,6 +22,8 @@ struct ScreenArgs {           // device pointers
   const double *gmax;         // global maximum
   unsigned long long *cap;    // [120] capacity (k_capacity)
   int *count;                 // [120] kept quartets (k_screen)
+  unsigned long long *nprim;  // [120] primitive quartets of the kept quartets (k_screen)
+  const int *pair_npp;        // primitive pairs per kept pair
   const long long *list_off;  // [120] offsets into lists
   int2 *lists;
   double tau;

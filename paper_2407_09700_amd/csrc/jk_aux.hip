@@ -102,6 +102,7 @@ __global__ void k_screen(ScreenArgs A) {
     const double *Pa = A.Pblk + (size_t)sa * A.nshell;
     const double *Pb = A.Pblk + (size_t)sb * A.nshell;
     const double pab = Pa[sb];
+    const int nppb = A.pair_npp[i];
     for (int ck = 0; ck <= cb; ++ck) {
       const int kb = A.cls_beg[ck];
       const int nk = A.cls_beg[ck + 1] - kb;
@@ -126,7 +127,13 @@ __global__ void k_screen(ScreenArgs A) {
         const unsigned long long mask = __ballot(keep);
         if (mask == 0ull) continue;
         int base = 0;
-        if (lane == 0) base = atomicAdd(&A.count[qc], __popcll(mask));
+        unsigned long long np = keep ? (unsigned long long)nppb * (unsigned long long)A.pair_npp[kb + k] : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+        if (lane == 0) {
+          base = atomicAdd(&A.count[qc], __popcll(mask));
+          atomicAdd(&A.nprim[qc], np);
+        }
         base = __shfl(base, 0);
         if (keep) {
           const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));

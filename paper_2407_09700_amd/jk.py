@@ -18,7 +18,8 @@ JK_FP64, JK_MIXED = 0, 1
 
 # every symbol declared in include/jk.h
 EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_build", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
-           "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_last_error"]
+           "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_last_error"]
+JK_FLAG_PROFILE = 1
 
 
 class JKError(RuntimeError):
@@ -37,6 +38,13 @@ class Basis(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("thresh", ctypes.c_double), ("precision", ctypes.c_int), ("fp32_cutoff", ctypes.c_double),
                 ("flags", ctypes.c_int)]
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("la", ctypes.c_int), ("lb", ctypes.c_int), ("lc", ctypes.c_int),
+                ("ld", ctypes.c_int), ("team", ctypes.c_int), ("nroots", ctypes.c_int),
+                ("quartets", ctypes.c_longlong), ("prim_quartets", ctypes.c_longlong), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -65,6 +73,7 @@ def lib():
         L.jk_plan_destroy.restype = None
         L.jk_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.jk_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.jk_profile.argtypes = [vp, ctypes.POINTER(ProfileEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.jk_eri_tensor.argtypes = [vp, vp, vp]
         L.jk_schwarz.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.jk_sph_matrix.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -122,10 +131,10 @@ def _stream(stream):
 class Plan:
     """A J/K plan for one molecule. D, J, K are torch float64 CUDA tensors (nao x nao)."""
 
-    def __init__(self, coords, basis: BasisArrays, thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6):
+    def __init__(self, coords, basis: BasisArrays, thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6, profile=False):
         self.basis = basis
         self.coords = np.ascontiguousarray(coords, np.float64)
-        self.opts = Opts(float(thresh), int(precision), float(fp32_cutoff), 0)
+        self.opts = Opts(float(thresh), int(precision), float(fp32_cutoff), JK_FLAG_PROFILE if profile else 0)
         h = ctypes.c_void_p()
         check(lib().jk_plan_create(ctypes.byref(basis.struct),
                                    self.coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -168,6 +177,12 @@ class Plan:
         s = Stats()
         check(lib().jk_stats(self.h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def profile(self):
+        buf = (ProfileEntry * 256)()
+        n = ctypes.c_int()
+        check(lib().jk_profile(self.h, buf, 256, ctypes.byref(n)))
+        return [{k: getattr(buf[i], k) for k, _ in ProfileEntry._fields_} for i in range(min(n.value, 256))]
 
     def close(self):
         if getattr(self, "h", None):
