@@ -110,7 +110,15 @@ def main():
     tot_flops = sum(v["flops"] for v in per_class.values()) / args.steps
     class_ms = sum(v["ms"] for v in per_class.values()) / args.steps
     top = sorted(per_class.items(), key=lambda kv: -kv[1]["ms"])[:8]
-    classes = [{"class": "(%d%d|%d%d)" % k, "kernel": "team" if v["team"] else "small",
+    def cname(k):
+        return "(%d%d|**)" % k[:2] if k[2] < 0 else "(%d%d|%d%d)" % k
+
+    def kname(k, v):
+        if v["team"] == 2:
+            return "k_bra<%d,%d>" % k[:2]
+        return "k_cls<%d,%d,%d,%d>" % k + (" team" if v["team"] else " lane")
+
+    classes = [{"class": cname(k), "kernel": kname(k, v),
                 "ms": round(v["ms"] / args.steps, 4), "quartets": v["quartets"] // args.steps,
                 "tflops": round(v["flops"] / v["ms"] * 1e-9, 3) if v["ms"] > 0 else 0.0} for k, v in top]
 
@@ -122,7 +130,7 @@ def main():
                                f"{mol.nbf} AOs, Schwarz tau {mol.thresh:g}, FP64",
                    "natom": mol.natom, "nao": mol.nbf, "nshell": mol.nshell, "tau": mol.thresh,
                    "kept_quartets": kept, "prim_quartets": st["prim_quartets"], "plan_ms": round(plan_ms, 2)},
-        "roofline": {"bound": "alu", "kernel": "class (%d%d|%d%d) %s" % (*dom_key, "k_team" if dom["team"] else "k_small"),
+        "roofline": {"bound": "alu", "kernel": kname(dom_key, dom),
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "kernel_ms": dom_ms},

@@ -16,8 +16,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libjk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["jk_api.cpp", "jk_aux.hip", "classes_l0.hip", "classes_l1.hip", "classes_l2.hip", "classes_l3.hip",
-           "classes_l4.hip"]
+SOURCES = ["jk_api.cpp", "jk_aux.hip"] + [f"classes_{c}.hip" for c in
+                                         ("44", "43", "42", "33", "41", "32", "40", "31", "22", "30", "21", "20",
+                                          "11", "10", "00")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 
@@ -51,8 +52,7 @@ def build(jobs: int | None = None, verbose: bool = True, force: bool = True) -> 
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or int(os.environ.get("MAX_JOBS", "0")) or min(8, os.cpu_count() or 1)
     t0 = time.time()
-    # biggest units first
-    order = sorted(SOURCES, key=lambda s: -("l4" in s) * 4 - ("l3" in s) * 3 - ("l2" in s) * 2)
+    order = SOURCES[2:] + SOURCES[:2]          # biggest class units first
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = dict(zip(order, ex.map(lambda s: _compile(s, force), order)))
     tmp = LIB + ".tmp%d" % os.getpid()

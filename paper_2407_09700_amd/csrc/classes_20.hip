@@ -1,0 +1,5 @@
+// Kernels of the bra class (la, lb) = (2, 0) and every ket class up to it.
+#include "jk_classes_impl.h"
+namespace jk {
+void register_bra_20(ClassInfo *classes, BraInfo *bras) { register_bra<2, 0>(classes, bras); }
+}  // namespace jk

@@ -1,0 +1,5 @@
+// Kernels of the bra class (la, lb) = (4, 2) and every ket class up to it.
+#include "jk_classes_impl.h"
+namespace jk {
+void register_bra_42(ClassInfo *classes, BraInfo *bras) { register_bra<4, 2>(classes, bras); }
+}  // namespace jk

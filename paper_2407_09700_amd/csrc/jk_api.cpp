@@ -15,6 +15,7 @@
 #include "../../include/jk.h"
 #include "jk_aux.h"
 #include "jk_classes.h"
+#include "jk_kernels.h"
 
 using namespace jk;
 
@@ -42,15 +43,16 @@ int fail(int code, const char *fmt, ...) {
   } while (0)
 
 ClassInfo g_classes[NQCLASS];
+BraInfo g_bras[NPAIRCLASS];
 bool g_classes_ready = false;
 
 void ensure_classes() {
   if (g_classes_ready) return;
-  register_classes_l0(g_classes);
-  register_classes_l1(g_classes);
-  register_classes_l2(g_classes);
-  register_classes_l3(g_classes);
-  register_classes_l4(g_classes);
+  register_bra_00(g_classes, g_bras); register_bra_10(g_classes, g_bras); register_bra_11(g_classes, g_bras);
+  register_bra_20(g_classes, g_bras); register_bra_21(g_classes, g_bras); register_bra_22(g_classes, g_bras);
+  register_bra_30(g_classes, g_bras); register_bra_31(g_classes, g_bras); register_bra_32(g_classes, g_bras);
+  register_bra_33(g_classes, g_bras); register_bra_40(g_classes, g_bras); register_bra_41(g_classes, g_bras);
+  register_bra_42(g_classes, g_bras); register_bra_43(g_classes, g_bras); register_bra_44(g_classes, g_bras);
   g_classes_ready = true;
 }
 
@@ -160,12 +162,17 @@ struct jk_plan {
   double *d_Dc = nullptr, *d_Jc = nullptr, *d_Kc = nullptr, *d_Pblk = nullptr, *d_gmax = nullptr;
   unsigned long long *d_cap = nullptr, *d_nprim = nullptr;
   int *d_count = nullptr, *d_pair_npp = nullptr;
+  int *d_pair_ca = nullptr, *d_pair_cb = nullptr, *d_pair_la = nullptr, *d_pair_lb = nullptr;
+  int *d_segoff = nullptr, *d_segcnt = nullptr, *d_next = nullptr;
+  long long *d_class_off = nullptr, *d_jp_off = nullptr;
+  double *d_Jpair = nullptr;
+  long long jp_total = 0;
+  std::vector<long long> jp_off;       // 15
   int flags = 0;
   hipStream_t last_stream = nullptr;
-  std::vector<hipEvent_t> events;      // profiling: 2 per class + prep + finalize
-  unsigned long long cap_last[NQCLASS] = {0};
-  long long *d_list_off = nullptr;
-  int2 *d_lists = nullptr;
+  std::vector<hipEvent_t> events;      // profiling: 2 per launch slot (15 fused + 120 per class) + prep + tail
+  std::vector<int> launched;           // launch slots used by the last execute
+  int *d_kets = nullptr;
   long long list_capacity = 0;
   double *d_scratch = nullptr;
   long long scratch_doubles = 0;
@@ -181,21 +188,16 @@ void plan_free(jk_plan *p) {
   dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_l); dfree(p->d_pure); dfree(p->d_cart_off);
   dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell); dfree(p->d_tsph); dfree(p->d_Dc);
   dfree(p->d_Jc); dfree(p->d_Kc); dfree(p->d_Pblk); dfree(p->d_gmax); dfree(p->d_cap); dfree(p->d_count);
-  dfree(p->d_list_off); dfree(p->d_lists); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
+  dfree(p->d_kets); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
+  dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
+  dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
 }
 
-constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes for k_small
-constexpr int GRID_TEAM_MAX = 1024;    // workgroups for k_team
-
-int class_grid(const ClassInfo &ci, long long nquartets) {
-  long long g = (nquartets + ci.per_block - 1) / ci.per_block;
-  const long long gmax = ci.team ? GRID_TEAM_MAX : GRID_SMALL_MAX;
-  if (g > gmax) g = gmax;
-  if (g < 1) g = 1;
-  return (int)g;
-}
+constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
+constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels
+constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
 
 int ensure_scratch(jk_plan *p, long long doubles) {
   if (doubles <= p->scratch_doubles) return JK_OK;
@@ -277,29 +279,26 @@ int validate(const jk_basis_t *B, const double *coords, int natom) {
   return JK_OK;
 }
 
-int launch_class_mode(jk_plan *p, int qc, int mode, const int2 *list, const int *count, long long nq, double *out,
-                      hipStream_t st) {
+int launch_mode_list(jk_plan *p, int qc, int mode, const int2 *list, int count, double *out, hipStream_t st) {
   const ClassInfo &ci = g_classes[qc];
-  if (!ci.launch[mode]) return fail(JK_EUNSUPPORTED, "class %d has no launcher for mode %d", qc, mode);
-  const int grid = class_grid(ci, nq);
+  if (!ci.launch_mode[mode]) return fail(JK_EUNSUPPORTED, "class %d has no launcher for mode %d", qc, mode);
+  if (count <= 0) return JK_OK;
+  long long g = ((long long)count + ci.per_block - 1) / ci.per_block;
+  const int grid = (int)std::max(1LL, std::min(g, (long long)(ci.team ? GRID_TEAM_MAX : GRID_SMALL_MAX)));
   if (ci.scratch_per_wg > 0) {
     int rc = ensure_scratch(p, ci.scratch_per_wg * (long long)grid);
     if (rc) return rc;
   }
-  ClassArgs a{};
-  a.pairs = p->d_pairs;
-  a.pp = p->d_pp;
-  a.quartets = list;
-  a.count = count;
-  a.Dc = p->d_Dc;
-  a.Jc = p->d_Jc;
-  a.Kc = p->d_Kc;
-  a.out = out;
-  a.scratch = p->d_scratch;
-  a.scratch_per_wg = ci.scratch_per_wg;
-  a.nc = p->nc;
-  a.mode = mode;
-  HIPCHK(ci.launch[mode](a, grid, st));
+  ModeArgs m{};
+  m.pairs = p->d_pairs;
+  m.pp = p->d_pp;
+  m.quartets = list;
+  m.count = count;
+  m.out = out;
+  m.scratch = p->d_scratch;
+  m.scratch_per_wg = ci.scratch_per_wg;
+  m.nc = p->nc;
+  HIPCHK(ci.launch_mode[mode](m, grid, st));
   return JK_OK;
 }
 
@@ -350,36 +349,48 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
   unsigned long long np[NQCLASS];
   HIPCHK(hipMemcpy(cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(np, p->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
+  const int NSLOT = NPAIRCLASS + NQCLASS;
   int n = 0;
   auto push = [&](const jk_profile_t &e) {
     if (n < max_entries) out[n] = e;
     ++n;
   };
+  auto class_flops = [&](int qc, jk_profile_t &r) {
+    const ClassInfo &ci = g_classes[qc];
+    const int nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
+    const double nel = (double)ncart(ci.la) * ncart(ci.lb) * ncart(ci.lc) * ncart(ci.ld);
+    r.quartets += cnt[qc];
+    r.prim_quartets += (long long)np[qc];
+    r.flops += (double)np[qc] * 3.0 * nroots * nel + (double)cnt[qc] * 12.0 * nel;
+  };
   float ms = 0.f;
   jk_profile_t e{};
   e.kind = 1;
-  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NQCLASS], p->events[2 * NQCLASS + 1]));
+  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NSLOT], p->events[2 * NSLOT + 1]));
   e.ms = ms;
   push(e);
-  for (int c = 0; c < NQCLASS; ++c) {
-    if (!p->cap_last[c]) continue;
-    const ClassInfo &ci = g_classes[c];
+  for (int slot : p->launched) {
     jk_profile_t r{};
     r.kind = 0;
-    r.la = ci.la; r.lb = ci.lb; r.lc = ci.lc; r.ld = ci.ld;
-    r.team = ci.team;
-    r.nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
-    r.quartets = cnt[c];
-    r.prim_quartets = (long long)np[c];
-    HIPCHK(hipEventElapsedTime(&ms, p->events[2 * c], p->events[2 * c + 1]));
+    if (slot < NPAIRCLASS) {                      // fused launch of a bra class over its ket classes
+      const BraInfo &bi = g_bras[slot];
+      r.la = bi.la; r.lb = bi.lb; r.lc = -1; r.ld = -1;
+      r.team = 2;
+      for (int ck = 0; ck <= slot; ++ck) class_flops(qclass_index(slot, ck), r);
+    } else {
+      const ClassInfo &ci = g_classes[slot - NPAIRCLASS];
+      r.la = ci.la; r.lb = ci.lb; r.lc = ci.lc; r.ld = ci.ld;
+      r.team = ci.team;
+      r.nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
+      class_flops(slot - NPAIRCLASS, r);
+    }
+    HIPCHK(hipEventElapsedTime(&ms, p->events[2 * slot], p->events[2 * slot + 1]));
     r.ms = ms;
-    const double nel = (double)ncart(ci.la) * ncart(ci.lb) * ncart(ci.lc) * ncart(ci.ld);
-    r.flops = (double)r.prim_quartets * 3.0 * r.nroots * nel + (double)r.quartets * 12.0 * nel;
     push(r);
   }
   e = jk_profile_t{};
   e.kind = 2;
-  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NQCLASS + 2], p->events[2 * NQCLASS + 3]));
+  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NSLOT + 2], p->events[2 * NSLOT + 3]));
   e.ms = ms;
   push(e);
   *n_entries = n;
@@ -480,9 +491,8 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
   {
     double *d_smax = nullptr;
     int2 *d_diag = nullptr;
-    int *d_cnt = nullptr;
-    if ((rc = dalloc(&d_smax, nall)) || (rc = dalloc(&d_diag, nall)) || (rc = dalloc(&d_cnt, NPAIRCLASS))) {
-      dfree(d_smax); dfree(d_diag);
+    if ((rc = dalloc(&d_smax, nall)) || (rc = dalloc(&d_diag, nall))) {
+      dfree(d_smax);
       return cleanup(rc);
     }
     std::vector<int2> diag(nall);
@@ -492,15 +502,14 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
     std::vector<int> fillp(beg.begin(), beg.end() - 1);
     for (int i = 0; i < nall; ++i) diag[fillp[all[i].cls]++] = make_int2(i, i);
     hipError_t e = hipMemcpy(d_diag, diag.data(), sizeof(int2) * nall, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_cnt, cnt.data(), sizeof(int) * NPAIRCLASS, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(d_smax, 0, sizeof(double) * nall);
     if (e != hipSuccess) {
-      dfree(d_smax); dfree(d_diag); dfree(d_cnt);
+      dfree(d_smax); dfree(d_diag);
       return cleanup(fail(JK_EDEVICE, "Schwarz setup: %s", hipGetErrorString(e)));
     }
     for (int c = 0; c < NPAIRCLASS && !rc; ++c) {
       if (!cnt[c]) continue;
-      rc = launch_class_mode(p, qclass_index(c, c), MODE_SCHWARZ, d_diag + beg[c], d_cnt + c, cnt[c], d_smax, 0);
+      rc = launch_mode_list(p, qclass_index(c, c), MODE_SCHWARZ, d_diag + beg[c], cnt[c], d_smax, 0);
     }
     std::vector<double> smax(nall);
     if (!rc) {
@@ -508,7 +517,7 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
       if (e == hipSuccess) e = hipMemcpy(smax.data(), d_smax, sizeof(double) * nall, hipMemcpyDeviceToHost);
       if (e != hipSuccess) rc = fail(JK_EDEVICE, "Schwarz pass: %s", hipGetErrorString(e));
     }
-    dfree(d_smax); dfree(d_diag); dfree(d_cnt);
+    dfree(d_smax); dfree(d_diag);
     if (rc) return cleanup(rc);
     p->schwarz.assign((size_t)ns * ns, 0.0);
     for (int i = 0; i < nall; ++i) {
@@ -530,7 +539,8 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
     std::vector<Pair> kept(p->npairs);
     std::vector<PrimPair> kpp;
     std::vector<double> kI(p->npairs);
-    std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs), knpp(p->npairs);
+    std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs), knpp(p->npairs), kca(p->npairs),
+        kcb(p->npairs), kla(p->npairs), klb(p->npairs);
     p->cls_beg.assign(NPAIRCLASS + 1, 0);
     for (int k = 0; k < p->npairs; ++k) {
       Pair P = all[order[k]];
@@ -543,6 +553,10 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
       ksa[k] = P.sa;
       ksb[k] = P.sb;
       knpp[k] = P.npp;
+      kca[k] = P.ca;
+      kcb[k] = P.cb;
+      kla[k] = p->l[P.sa];
+      klb[k] = p->l[P.sb];
       p->cls_beg[P.cls + 1]++;
     }
     for (int c = 0; c < NPAIRCLASS; ++c) p->cls_beg[c + 1] += p->cls_beg[c];
@@ -552,7 +566,21 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
     if ((rc = dupload(&p->d_pairs, kept)) || (rc = dupload(&p->d_pp, kpp)) || (rc = dupload(&p->d_pairI, kI)) ||
         (rc = dupload(&p->d_pair_cls, kcls)) || (rc = dupload(&p->d_pair_sa, ksa)) ||
         (rc = dupload(&p->d_pair_sb, ksb)) || (rc = dupload(&p->d_cls_beg, p->cls_beg)) ||
-        (rc = dupload(&p->d_pair_npp, knpp)))
+        (rc = dupload(&p->d_pair_npp, knpp)) || (rc = dupload(&p->d_pair_ca, kca)) ||
+        (rc = dupload(&p->d_pair_cb, kcb)) || (rc = dupload(&p->d_pair_la, kla)) || (rc = dupload(&p->d_pair_lb, klb)))
+      return cleanup(rc);
+    // Coulomb pair buffer: per pair class, element-major over the pairs of the class
+    p->jp_off.assign(NPAIRCLASS, 0);
+    long long jt = 0;
+    for (int c = 0; c < NPAIRCLASS; ++c) {
+      p->jp_off[c] = jt;
+      const int la = (int)((std::sqrt(8.0 * c + 1) - 1) / 2), lb = c - la * (la + 1) / 2;
+      jt += (long long)(p->cls_beg[c + 1] - p->cls_beg[c]) * ncart(la) * ncart(lb);
+    }
+    p->jp_total = jt;
+    if ((rc = dupload(&p->d_jp_off, p->jp_off)) || (rc = dalloc(&p->d_Jpair, (size_t)std::max(1LL, jt))) ||
+        (rc = dalloc(&p->d_segoff, (size_t)p->npairs * NPAIRCLASS)) ||
+        (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)))
       return cleanup(rc);
   }
 
@@ -561,10 +589,11 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
   if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
       (rc = dalloc(&p->d_Pblk, (size_t)ns * ns)) || (rc = dalloc(&p->d_gmax, 1)) ||
       (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
-      (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_list_off, NQCLASS)))
+      (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
+      (rc = dalloc(&p->d_next, NPAIRCLASS + NQCLASS)))
     return cleanup(rc);
   if (p->flags & JK_FLAG_PROFILE) {
-    p->events.resize(2 * NQCLASS + 4, nullptr);
+    p->events.resize(2 * (NPAIRCLASS + NQCLASS) + 4, nullptr);
     for (auto &e : p->events)
       if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(JK_EDEVICE, "hipEventCreate failed"));
   }
@@ -583,15 +612,19 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   if (!D || !J || !K) return fail(JK_EINVAL, "D, J and K must be device pointers");
   hipStream_t st = (hipStream_t)stream;
   const size_t nc2 = (size_t)p->nc * p->nc;
-  HIPCHK(hipMemsetAsync(p->d_Jc, 0, nc2 * sizeof(double), st));
-  HIPCHK(hipMemsetAsync(p->d_Kc, 0, nc2 * sizeof(double), st));
-  HIPCHK(hipMemsetAsync(p->d_gmax, 0, sizeof(double), st));
-  HIPCHK(hipMemsetAsync(p->d_cap, 0, sizeof(unsigned long long) * NQCLASS, st));
-  HIPCHK(hipMemsetAsync(p->d_count, 0, sizeof(int) * NQCLASS, st));
-  HIPCHK(hipMemsetAsync(p->d_nprim, 0, sizeof(unsigned long long) * NQCLASS, st));
   const bool prof = (p->flags & JK_FLAG_PROFILE) != 0;
+  const int NSLOT = NPAIRCLASS + NQCLASS;
   p->last_stream = st;
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS], st));
+  p->launched.clear();
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT], st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jc, (long long)nc2, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Kc, (long long)nc2, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jpair, p->jp_total, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_nprim, NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
+  HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
   HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
   HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
 
@@ -600,14 +633,16 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   A.pair_cls = p->d_pair_cls;
   A.pair_sa = p->d_pair_sa;
   A.pair_sb = p->d_pair_sb;
+  A.pair_npp = p->d_pair_npp;
   A.cls_beg = p->d_cls_beg;
   A.Pblk = p->d_Pblk;
   A.gmax = p->d_gmax;
   A.cap = p->d_cap;
+  A.segoff = p->d_segoff;
+  A.segcnt = p->d_segcnt;
   A.count = p->d_count;
   A.nprim = p->d_nprim;
-  A.pair_npp = p->d_pair_npp;
-  A.list_off = p->d_list_off;
+  A.class_off = p->d_class_off;
   A.tau = p->tau;
   A.npairs = p->npairs;
   A.nshell = p->nshell;
@@ -622,27 +657,90 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
     total += (long long)cap[c];
   }
   if (total > p->list_capacity) {
-    dfree(p->d_lists);
+    dfree(p->d_kets);
     p->list_capacity = 0;
-    int rc = dalloc(&p->d_lists, (size_t)total + 1);
+    int rc = dalloc(&p->d_kets, (size_t)total + 1);
     if (rc) return rc;
     p->list_capacity = total;
   }
-  HIPCHK(hipMemcpyAsync(p->d_list_off, off, sizeof(off), hipMemcpyHostToDevice, st));
-  A.lists = p->d_lists;
+  HIPCHK(hipMemcpyAsync(p->d_class_off, off, sizeof(off), hipMemcpyHostToDevice, st));
+  A.kets = p->d_kets;
   if (p->npairs > 0) HIPCHK(launch_screen(A, st));
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS + 1], st));
-  for (int c = 0; c < NQCLASS; ++c) {
-    p->cap_last[c] = cap[c];
-    if (!cap[c]) continue;
-    if (prof) HIPCHK(hipEventRecord(p->events[2 * c], st));
-    int rc = launch_class_mode(p, c, MODE_JK, p->d_lists + off[c], p->d_count + c, (long long)cap[c], nullptr, st);
-    if (rc) return rc;
-    if (prof) HIPCHK(hipEventRecord(p->events[2 * c + 1], st));
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 1], st));
+
+  JKArgs J_{};
+  J_.pairs = p->d_pairs;
+  J_.pp = p->d_pp;
+  J_.kets = p->d_kets;
+  J_.class_off = p->d_class_off;
+  J_.segoff = p->d_segoff;
+  J_.segcnt = p->d_segcnt;
+  J_.Dc = p->d_Dc;
+  J_.Kc = p->d_Kc;
+  J_.Jpair = p->d_Jpair;
+  J_.jp_off = p->d_jp_off;
+  J_.cls_beg = p->d_cls_beg;
+  J_.nc = p->nc;
+  for (int cb = 0; cb < NPAIRCLASS; ++cb) {
+    const int nb = p->cls_beg[cb + 1] - p->cls_beg[cb];
+    bool any = false;
+    for (int ck = 0; ck <= cb; ++ck) any = any || cap[qclass_index(cb, ck)] > 0;
+    if (!nb || !any) continue;
+    J_.bra_beg = p->cls_beg[cb];
+    J_.bra_end = p->cls_beg[cb + 1];
+    const BraInfo &bi = g_bras[cb];
+    const int na = ncart(bi.la), nbb = ncart(bi.lb);
+    const size_t fused_lds = ((size_t)(na + nbb) * p->nc + ((na * nbb + 1) & ~1)) * 8 + (size_t)bi.pool_bytes;
+    const int grid = std::min(nb, GRID_TEAM_MAX);
+    if (bi.fusable && fused_lds <= FUSED_LDS_MAX) {
+      if (bi.scratch_per_wg > 0) {
+        int rc = ensure_scratch(p, bi.scratch_per_wg * (long long)grid);
+        if (rc) return rc;
+      }
+      J_.scratch = p->d_scratch;
+      J_.scratch_per_wg = bi.scratch_per_wg;
+      J_.next = p->d_next + cb;
+      if (prof) HIPCHK(hipEventRecord(p->events[2 * cb], st));
+      HIPCHK(bi.launch_bra(J_, grid, fused_lds, st));
+      if (prof) HIPCHK(hipEventRecord(p->events[2 * cb + 1], st));
+      p->launched.push_back(cb);
+    } else {
+      for (int ck = 0; ck <= cb; ++ck) {
+        const int qc = qclass_index(cb, ck);
+        if (!cap[qc]) continue;
+        const ClassInfo &ci = g_classes[qc];
+        if (ci.scratch_per_wg > 0) {
+          int rc = ensure_scratch(p, ci.scratch_per_wg * (long long)grid);
+          if (rc) return rc;
+        }
+        J_.scratch = p->d_scratch;
+        J_.scratch_per_wg = ci.scratch_per_wg;
+        J_.next = p->d_next + NPAIRCLASS + qc;
+        const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
+        const int slot = NPAIRCLASS + qc;
+        if (prof) HIPCHK(hipEventRecord(p->events[2 * slot], st));
+        HIPCHK(ci.launch_cls(J_, grid, lds, st));
+        if (prof) HIPCHK(hipEventRecord(p->events[2 * slot + 1], st));
+        p->launched.push_back(slot);
+      }
+    }
   }
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS + 2], st));
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 2], st));
+  FoldArgs F{};
+  F.pair_cls = p->d_pair_cls;
+  F.pair_ca = p->d_pair_ca;
+  F.pair_cb = p->d_pair_cb;
+  F.pair_la = p->d_pair_la;
+  F.pair_lb = p->d_pair_lb;
+  F.cls_beg = p->d_cls_beg;
+  F.jp_off = p->d_jp_off;
+  F.Jpair = p->d_Jpair;
+  F.Jc = p->d_Jc;
+  F.npairs = p->npairs;
+  F.nc = p->nc;
+  if (p->npairs > 0) HIPCHK(launch_fold(F, st));
   HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, J, K, st));
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NQCLASS + 3], st));
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 3], st));
   p->stats.candidate_quartets = total;
   return JK_OK;
 }
@@ -683,12 +781,8 @@ int jk_eri_tensor(jk_plan_t *p, double *eri, void *stream) {
       cnt[qc] = (int)((long long)lst.size() - off[qc]);
     }
   int2 *d_lst = nullptr;
-  int *d_cnt = nullptr;
   int rc;
-  if ((rc = dupload(&d_lst, lst)) || (rc = dupload(&d_cnt, cnt))) {
-    dfree(d_lst);
-    return rc;
-  }
+  if ((rc = dupload(&d_lst, lst))) return rc;
   const size_t n4 = (size_t)p->nc * p->nc * p->nc * p->nc;
   hipError_t e = hipMemsetAsync(eri, 0, n4 * sizeof(double), st);
   if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
@@ -696,14 +790,13 @@ int jk_eri_tensor(jk_plan_t *p, double *eri, void *stream) {
     for (int ck = 0; ck <= cb && !rc; ++ck) {
       const int qc = qclass_index(cb, ck);
       if (!cnt[qc]) continue;
-      rc = launch_class_mode(p, qc, MODE_ERI, d_lst + off[qc], d_cnt + qc, cnt[qc], eri, st);
+      rc = launch_mode_list(p, qc, MODE_ERI, d_lst + off[qc], cnt[qc], eri, st);
     }
   if (!rc) {
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
   }
   dfree(d_lst);
-  dfree(d_cnt);
   return rc;
 }
 

@@ -70,31 +70,51 @@ __device__ __forceinline__ int ket_prefix(const double *__restrict__ Iket, int n
   return lo;
 }
 
-// Upper bound of the kept quartets of every class (cap[120]), from the global bound.
-__global__ void k_capacity(ScreenArgs A) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.npairs; i += gridDim.x * blockDim.x) {
-    const int cb = A.pair_cls[i];
+// Segments: for every bra pair and ket class, room for the ket prefix that can pass the
+// screen under the global density bound. Each workgroup adds its per-class totals with one
+// global atomic per class and hands out offsets inside its block from LDS.
+__global__ __launch_bounds__(256) void k_capacity(ScreenArgs A) {
+  __shared__ unsigned long long s_tot[NQCLASS], s_base[NQCLASS];
+  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) s_tot[t] = 0ull;
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int loc[NPAIRCLASS];
+  int cb = -1;
+  if (i < A.npairs) {
+    cb = A.pair_cls[i];
     const int li = i - A.cls_beg[cb];
     const double Ib = A.pairI[i];
-    for (int ck = 0; ck <= cb; ++ck) {
+    const double pglob = *A.gmax;
+    for (int ck = 0; ck < NPAIRCLASS; ++ck) {
+      loc[ck] = 0;
+      if (ck > cb) continue;
       const int nk = A.cls_beg[ck + 1] - A.cls_beg[ck];
-      int n = ket_prefix(A.pairI + A.cls_beg[ck], nk, Ib, *A.gmax, A.tau);
+      int n = ket_prefix(A.pairI + A.cls_beg[ck], nk, Ib, pglob, A.tau);
       if (ck == cb) n = min(n, li + 1);
-      if (n > 0) atomicAdd(&A.cap[qclass_index(cb, ck)], (unsigned long long)n);
+      if (n > 0) loc[ck] = (int)atomicAdd(&s_tot[qclass_index(cb, ck)], (unsigned long long)n);
     }
   }
+  __syncthreads();
+  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x)
+    s_base[t] = s_tot[t] ? atomicAdd(&A.cap[t], s_tot[t]) : 0ull;
+  __syncthreads();
+  if (i < A.npairs)
+    for (int ck = 0; ck <= cb; ++ck) A.segoff[(size_t)i * NPAIRCLASS + ck] = (int)(s_base[qclass_index(cb, ck)] + loc[ck]);
 }
 
 // One wave per bra pair: tests the candidates of every ket class with the exact
-// predicate I_ab I_cd P >= tau (P = max |D_cart| over the six shell-pair blocks) and
-// appends the kept (bra, ket) pairs to the class list with one atomic per wave step.
-__global__ void k_screen(ScreenArgs A) {
+// predicate I_ab I_cd P >= tau (P = max |D_cart| over the six shell-pair blocks), writes the
+// kept kets to the front of the (bra, class) segment and its count.
+__global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
+  __shared__ int s_cnt[NQCLASS];
+  __shared__ unsigned long long s_np[NQCLASS];
+  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) { s_cnt[t] = 0; s_np[t] = 0ull; }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  const double tau = A.tau;
-  const double pglob = *A.gmax;
-  for (int i = wave; i < A.npairs; i += nwaves) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (i < A.npairs) {
+    const double tau = A.tau;
+    const double pglob = *A.gmax;
     const int cb = A.pair_cls[i];
     const int li = i - A.cls_beg[cb];
     const double Ib = A.pairI[i];
@@ -102,14 +122,16 @@ __global__ void k_screen(ScreenArgs A) {
     const double *Pa = A.Pblk + (size_t)sa * A.nshell;
     const double *Pb = A.Pblk + (size_t)sb * A.nshell;
     const double pab = Pa[sb];
-    const int nppb = A.pair_npp[i];
+    const unsigned long long nppb = (unsigned long long)A.pair_npp[i];
     for (int ck = 0; ck <= cb; ++ck) {
       const int kb = A.cls_beg[ck];
       const int nk = A.cls_beg[ck + 1] - kb;
       int n = ket_prefix(A.pairI + kb, nk, Ib, pglob, tau);
       if (ck == cb) n = min(n, li + 1);
       const int qc = qclass_index(cb, ck);
-      int2 *out = A.lists + A.list_off[qc];
+      int *out = A.kets + A.class_off[qc] + A.segoff[(size_t)i * NPAIRCLASS + ck];
+      int kept = 0;
+      unsigned long long np = 0ull;
       for (int k0 = 0; k0 < n; k0 += 64) {
         const int k = k0 + lane;
         bool keep = false;
@@ -123,24 +145,40 @@ __global__ void k_screen(ScreenArgs A) {
           p = fmax(p, Pb[sc]);
           p = fmax(p, Pb[sd]);
           keep = Ib * A.pairI[kg] * p >= tau;
+          if (keep) np += nppb * (unsigned long long)A.pair_npp[kg];
         }
         const unsigned long long mask = __ballot(keep);
-        if (mask == 0ull) continue;
-        int base = 0;
-        unsigned long long np = keep ? (unsigned long long)nppb * (unsigned long long)A.pair_npp[kb + k] : 0ull;
+        if (keep) out[kept + __popcll(mask & ((1ull << lane) - 1ull))] = kb + k;
+        kept += __popcll(mask);
+      }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
-        if (lane == 0) {
-          base = atomicAdd(&A.count[qc], __popcll(mask));
-          atomicAdd(&A.nprim[qc], np);
-        }
-        base = __shfl(base, 0);
-        if (keep) {
-          const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-          out[pos] = make_int2(i, kb + k);
+      for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+      if (lane == 0) {
+        A.segcnt[(size_t)i * NPAIRCLASS + ck] = kept;
+        if (kept) {
+          atomicAdd(&s_cnt[qc], kept);
+          atomicAdd(&s_np[qc], np);
         }
       }
     }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x)
+    if (s_cnt[t]) {
+      atomicAdd(&A.count[t], s_cnt[t]);
+      atomicAdd(&A.nprim[t], s_np[t]);
+    }
+}
+
+// Jt[ca + a][cb + b] = Coulomb pair buffer (each shell pair owns its block of Jt).
+__global__ void k_fold(FoldArgs F) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < F.npairs; p += gridDim.x * blockDim.x) {
+    const int c = F.pair_cls[p];
+    const int beg = F.cls_beg[c], np = F.cls_beg[c + 1] - beg;
+    const int na = ncart(F.pair_la[p]), nb = ncart(F.pair_lb[p]);
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < nb; ++b)
+        F.Jc[(size_t)(F.pair_ca[p] + a) * F.nc + F.pair_cb[p] + b] = F.Jpair[F.jp_off[c] + (long long)(a * nb + b) * np + (p - beg)];
   }
 }
 
@@ -206,15 +244,15 @@ hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, d
   return hipGetLastError();
 }
 hipError_t launch_capacity(const ScreenArgs &A, hipStream_t st) {
-  hipLaunchKernelGGL(k_capacity, dim3(grid_for(A.npairs, 256)), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_capacity, dim3((A.npairs + 255) / 256), dim3(256), 0, st, A);
   return hipGetLastError();
 }
 hipError_t launch_screen(const ScreenArgs &A, hipStream_t st) {
-  long long waves = A.npairs;
-  int grid = (int)((waves * 64 + 255) / 256);
-  if (grid > 16384) grid = 16384;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_screen, dim3(grid), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_screen, dim3((A.npairs + 3) / 4), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+hipError_t launch_fold(const FoldArgs &F, hipStream_t st) {
+  hipLaunchKernelGGL(k_fold, dim3(grid_for(F.npairs, 256)), dim3(256), 0, st, F);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,

@@ -1,25 +1,38 @@
-// Registry of the 120 quartet classes and their launchers.
+// Registry of the quartet classes and bra classes and their launchers.
 #pragma once
 #include "jk_common.h"
 
 namespace jk {
 
-typedef hipError_t (*class_launch_fn)(const ClassArgs &args, int grid, hipStream_t stream);
+struct JKArgs;
+struct ModeArgs;
 
-struct ClassInfo {
+typedef hipError_t (*jk_launch_fn)(const JKArgs &args, int grid, size_t lds, hipStream_t stream);
+typedef hipError_t (*mode_launch_fn)(const ModeArgs &args, int grid, hipStream_t stream);
+
+struct ClassInfo {           // one quartet class (la lb | lc ld)
   int la, lb, lc, ld;
-  int team;                  // 1: k_team, 0: k_small
-  int block;                 // threads per workgroup
-  int per_block;             // quartets one workgroup consumes per pass (lanes or QB)
-  long long scratch_per_wg;  // doubles of global scratch per workgroup (team, largest classes)
-  class_launch_fn launch[3]; // by mode
+  int team;                  // 1: workgroup body, 0: lane-per-quartet body
+  int block;                 // threads of k_cls / k_mode
+  int per_block;             // quartets one k_mode workgroup consumes per pass
+  int team_lds;              // bytes of team LDS (pool)
+  long long scratch_per_wg;  // doubles of global team buffer per workgroup
+  jk_launch_fn launch_cls;   // k_cls
+  mode_launch_fn launch_mode[3];
 };
 
-// filled by the class translation units (one per bra angular momentum la)
-void register_classes_l0(ClassInfo *table);
-void register_classes_l1(ClassInfo *table);
-void register_classes_l2(ClassInfo *table);
-void register_classes_l3(ClassInfo *table);
-void register_classes_l4(ClassInfo *table);
+struct BraInfo {             // one bra class (la lb)
+  int la, lb;
+  int fusable;               // k_bra can run every ket class with 256 lanes
+  int pool_bytes;            // team LDS of k_bra
+  long long scratch_per_wg;  // doubles of global team buffer per workgroup
+  jk_launch_fn launch_bra;   // k_bra (null if not fusable)
+};
+
+#define JK_DECL_BRA(LA, LB) void register_bra_##LA##LB(ClassInfo *classes, BraInfo *bras);
+JK_DECL_BRA(0, 0) JK_DECL_BRA(1, 0) JK_DECL_BRA(1, 1) JK_DECL_BRA(2, 0) JK_DECL_BRA(2, 1) JK_DECL_BRA(2, 2)
+JK_DECL_BRA(3, 0) JK_DECL_BRA(3, 1) JK_DECL_BRA(3, 2) JK_DECL_BRA(3, 3)
+JK_DECL_BRA(4, 0) JK_DECL_BRA(4, 1) JK_DECL_BRA(4, 2) JK_DECL_BRA(4, 3) JK_DECL_BRA(4, 4)
+#undef JK_DECL_BRA
 
 }  // namespace jk

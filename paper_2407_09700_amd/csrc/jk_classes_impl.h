@@ -5,25 +5,41 @@
 
 namespace jk {
 
-constexpr int SMALL_REG_LIMIT = 100;   // k_small when [e0|f0] accumulators + one root's 2D integrals fit
+constexpr int DYN_LDS_MAX = 150 * 1024;   // dynamic LDS the J/K kernels may request (CU: 160 KB)
 
 template <int LA, int LB, int LC, int LD>
-constexpr bool use_team() { return SmallCfg<LA, LB, LC, LD>::REGS > SMALL_REG_LIMIT; }
+hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_cls<LA, LB, LC, LD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              DYN_LDS_MAX);
+    (void)hipGetLastError();   // the attribute is a hint; do not leave its status for the launch check
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_cls<LA, LB, LC, LD>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), lds, stream, args);
+  return hipGetLastError();
+}
 
 template <int LA, int LB, int LC, int LD, int MODE>
-hipError_t launch_class(const ClassArgs &args, int grid, hipStream_t stream) {
-  if constexpr (use_team<LA, LB, LC, LD>()) {
-    using C = TeamCfg<LA, LB, LC, LD>;
-    hipLaunchKernelGGL((k_team<LA, LB, LC, LD, MODE>), dim3(grid), dim3(C::BLOCK), 0, stream, args);
-  } else {
-    hipLaunchKernelGGL((k_small<LA, LB, LC, LD, MODE>), dim3(grid), dim3(256), 0, stream, args);
+hipError_t launch_mode(const ModeArgs &args, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL((k_mode<LA, LB, LC, LD, MODE>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), 0, stream, args);
+  return hipGetLastError();
+}
+
+template <int LA, int LB>
+hipError_t launch_bra(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_bra<LA, LB>, hipFuncAttributeMaxDynamicSharedMemorySize, DYN_LDS_MAX);
+    (void)hipGetLastError();
+    attr = true;
   }
+  hipLaunchKernelGGL((k_bra<LA, LB>), dim3(grid), dim3(256), lds, stream, args);
   return hipGetLastError();
 }
 
 template <int LA, int LB, int LC, int LD>
 void register_one(ClassInfo *table) {
-  static_assert(LA >= LB && LC >= LD && LA * (LA + 1) / 2 + LB >= LC * (LC + 1) / 2 + LD, "canonical class");
   ClassInfo &ci = table[qclass_index(pair_class(LA, LB), pair_class(LC, LD))];
   ci.la = LA; ci.lb = LB; ci.lc = LC; ci.ld = LD;
   if constexpr (use_team<LA, LB, LC, LD>()) {
@@ -31,27 +47,41 @@ void register_one(ClassInfo *table) {
     ci.team = 1;
     ci.block = C::BLOCK;
     ci.per_block = C::QB;
+    ci.team_lds = C::LDS_BYTES;
     ci.scratch_per_wg = C::GLOBAL_BUF ? (long long)C::BUF : 0;
   } else {
     ci.team = 0;
     ci.block = 256;
     ci.per_block = 256;
+    ci.team_lds = 0;
     ci.scratch_per_wg = 0;
   }
-  ci.launch[MODE_JK] = launch_class<LA, LB, LC, LD, MODE_JK>;
-  ci.launch[MODE_SCHWARZ] = (LA == LC && LB == LD) ? launch_class<LA, LB, LC, LD, MODE_SCHWARZ> : nullptr;
-  ci.launch[MODE_ERI] = launch_class<LA, LB, LC, LD, MODE_ERI>;
+  ci.launch_cls = launch_cls<LA, LB, LC, LD>;
+  ci.launch_mode[MODE_JK] = nullptr;
+  ci.launch_mode[MODE_SCHWARZ] = (LA == LC && LB == LD) ? launch_mode<LA, LB, LC, LD, MODE_SCHWARZ> : nullptr;
+  ci.launch_mode[MODE_ERI] = launch_mode<LA, LB, LC, LD, MODE_ERI>;
 }
 
-// all ket classes (lc, ld) <= (LA, LB) for one bra class
+template <int LA, int LB, int P = 0>
+void register_kets(ClassInfo *table) {
+  if constexpr (P <= pair_class(LA, LB)) {
+    register_one<LA, LB, pc_la(P), pc_lb(P)>(table);
+    register_kets<LA, LB, P + 1>(table);
+  }
+}
+
 template <int LA, int LB>
-void register_bra(ClassInfo *table) {
-#define JK_REG_KET(LC, LD) \
-  if constexpr (LC * (LC + 1) / 2 + LD <= LA * (LA + 1) / 2 + LB) register_one<LA, LB, LC, LD>(table);
-  JK_REG_KET(0, 0) JK_REG_KET(1, 0) JK_REG_KET(1, 1) JK_REG_KET(2, 0) JK_REG_KET(2, 1) JK_REG_KET(2, 2)
-  JK_REG_KET(3, 0) JK_REG_KET(3, 1) JK_REG_KET(3, 2) JK_REG_KET(3, 3)
-  JK_REG_KET(4, 0) JK_REG_KET(4, 1) JK_REG_KET(4, 2) JK_REG_KET(4, 3) JK_REG_KET(4, 4)
-#undef JK_REG_KET
+void register_bra(ClassInfo *classes, BraInfo *bras) {
+  register_kets<LA, LB>(classes);
+  BraInfo &b = bras[pair_class(LA, LB)];
+  b.la = LA; b.lb = LB;
+  b.fusable = bra_fusable<LA, LB>();
+  b.pool_bytes = bra_pool_bytes<LA, LB>();
+  b.scratch_per_wg = bra_scratch_doubles<LA, LB>();
+  if constexpr (bra_fusable<LA, LB>())
+    b.launch_bra = launch_bra<LA, LB>;
+  else
+    b.launch_bra = nullptr;
 }
 
 }  // namespace jk

@@ -1,0 +1,372 @@
+// Contracted ERI blocks of one class, shared by every kernel of the build.
+//
+// Both bodies evaluate contracted shell quartets (ab|cd) of one class with la >= lb,
+// lc >= ld, (la,lb) >= (lc,ld): the Rys product of paper section 2 is accumulated over
+// primitive quartets at the [e0|f0] level (e = a + k on centre A, f = c + k' on centre C),
+// then moved to (ab|cd) once per contracted quartet with the binomial transfer relation.
+//
+// small_eri: one lane per quartet, every intermediate in registers (the register-resident
+//   design the paper uses for small classes, section 3, Algorithm 2).
+// team_eri:  a workgroup per batch of QB quartets. For each chunk of primitive quartets the
+//   lanes compute the 2D integrals of every (quartet, primitive quartet, root, direction)
+//   into LDS; each lane then accumulates the [e0|f0] elements of one f component (and one
+//   slice of e components) from LDS into registers. The transfer runs through a buffer in
+//   LDS (or global memory for the largest classes) and leaves (ab|cd) in that buffer.
+#pragma once
+#include "jk_device.h"
+
+namespace jk {
+
+// ================================================================== lane per quartet
+template <int LA, int LB, int LC, int LD>
+struct SmallCfg {
+  static constexpr int E = LA + LB, F = LC + LD, N = (E + F) / 2 + 1;
+  static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+  static constexpr int NE = range_count(LA, E), NF = range_count(LC, F);
+  static constexpr int REGS = NE * NF + 3 * (E + 1) * (F + 1);
+  static constexpr int NG = NA * NB * NC * ND;
+};
+
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, const PrimPair *__restrict__ pp,
+                                          double (&g)[SmallCfg<LA, LB, LC, LD>::NG]) {
+  using C = SmallCfg<LA, LB, LC, LD>;
+  constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
+  constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
+  constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
+  double acc[NE * NF];
+#pragma unroll
+  for (int i = 0; i < NE * NF; ++i) acc[i] = 0.0;
+
+  for (int ib = 0; ib < bra.npp; ++ib) {
+    const PrimPair pb = pp[bra.pp_off + ib];
+    const double hp = 0.5 / pb.p;
+    for (int ik = 0; ik < ket.npp; ++ik) {
+      const PrimPair pk = pp[ket.pp_off + ik];
+      PrimQuartet Q;
+      prim_quartet(pb, pk, bra.A, ket.A, Q);
+      const double hq = 0.5 / pk.p;
+      double u[N], w[N];
+      rys_roots<N>(Q.T, u, w);
+#pragma unroll
+      for (int n = 0; n < N; ++n) {
+        const double uq = u[n] * Q.pq_inv;
+        const double b00 = 0.5 * uq;
+        const double b10 = hp * (1.0 - uq * Q.q);
+        const double b01 = hq * (1.0 - uq * Q.p);
+        double Gx[E + 1][F + 1], Gy[E + 1][F + 1], Gz[E + 1][F + 1];
+        vrr2d<E, F>(Gx, 1.0, Q.PA[0] - uq * Q.q * Q.PQ[0], Q.QC[0] + uq * Q.p * Q.PQ[0], b10, b01, b00);
+        vrr2d<E, F>(Gy, 1.0, Q.PA[1] - uq * Q.q * Q.PQ[1], Q.QC[1] + uq * Q.p * Q.PQ[1], b10, b01, b00);
+        vrr2d<E, F>(Gz, w[n] * Q.pref, Q.PA[2] - uq * Q.q * Q.PQ[2], Q.QC[2] + uq * Q.p * Q.PQ[2], b10, b01, b00);
+#pragma unroll
+        for (int ie = 0; ie < NE; ++ie) {
+#pragma unroll
+          for (int jf = 0; jf < NF; ++jf) {
+            acc[ie * NF + jf] = fma(Gx[CT.x[E0 + ie]][CT.x[F0 + jf]] * Gy[CT.y[E0 + ie]][CT.y[F0 + jf]],
+                                    Gz[CT.z[E0 + ie]][CT.z[F0 + jf]], acc[ie * NF + jf]);
+          }
+        }
+      }
+    }
+  }
+
+  const double AB[3] = {bra.A[0] - bra.B[0], bra.A[1] - bra.B[1], bra.A[2] - bra.B[2]};
+  const double CD[3] = {ket.A[0] - ket.B[0], ket.A[1] - ket.B[1], ket.A[2] - ket.B[2]};
+  double abp[3][LB + 1], cdp[3][LD + 1];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    abp[d][0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= LB; ++k) abp[d][k] = abp[d][k - 1] * AB[d];
+    cdp[d][0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= LD; ++k) cdp[d][k] = cdp[d][k - 1] * CD[d];
+  }
+  double hb[NA * NB * NF];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      constexpr int A0 = CT.start[LA], B0 = CT.start[LB];
+      const int ax = CT.x[A0 + a], ay = CT.y[A0 + a], az = CT.z[A0 + a];
+      const int bx = CT.x[B0 + b], by = CT.y[B0 + b], bz = CT.z[B0 + b];
+#pragma unroll
+      for (int jf = 0; jf < NF; ++jf) hb[(a * NB + b) * NF + jf] = 0.0;
+#pragma unroll
+      for (int kx = 0; kx <= LB; ++kx) {
+        if (kx > bx) continue;
+#pragma unroll
+        for (int ky = 0; ky <= LB; ++ky) {
+          if (ky > by) continue;
+#pragma unroll
+          for (int kz = 0; kz <= LB; ++kz) {
+            if (kz > bz) continue;
+            const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * abp[0][bx - kx] *
+                              abp[1][by - ky] * abp[2][bz - kz];
+            const int ie = CT.idx[ax + kx][ay + ky][az + kz] - E0;
+#pragma unroll
+            for (int jf = 0; jf < NF; ++jf)
+              hb[(a * NB + b) * NF + jf] = fma(cf, acc[ie * NF + jf], hb[(a * NB + b) * NF + jf]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      constexpr int C0 = CT.start[LC], D0 = CT.start[LD];
+      const int cx = CT.x[C0 + c], cy = CT.y[C0 + c], cz = CT.z[C0 + c];
+      const int dx = CT.x[D0 + d], dy = CT.y[D0 + d], dz = CT.z[D0 + d];
+#pragma unroll
+      for (int ab = 0; ab < NA * NB; ++ab) g[ab * NC * ND + c * ND + d] = 0.0;
+#pragma unroll
+      for (int kx = 0; kx <= LD; ++kx) {
+        if (kx > dx) continue;
+#pragma unroll
+        for (int ky = 0; ky <= LD; ++ky) {
+          if (ky > dy) continue;
+#pragma unroll
+          for (int kz = 0; kz <= LD; ++kz) {
+            if (kz > dz) continue;
+            const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * cdp[0][dx - kx] *
+                              cdp[1][dy - ky] * cdp[2][dz - kz];
+            const int jf = CT.idx[cx + kx][cy + ky][cz + kz] - F0;
+#pragma unroll
+            for (int ab = 0; ab < NA * NB; ++ab)
+              g[ab * NC * ND + c * ND + d] = fma(cf, hb[ab * NF + jf], g[ab * NC * ND + c * ND + d]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ================================================================== workgroup per batch
+template <int LA, int LB, int LC, int LD>
+struct TeamCfg {
+  static constexpr int E = LA + LB, F = LC + LD, N = (E + F) / 2 + 1;
+  static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+  static constexpr int NE = range_count(LA, E), NF = range_count(LC, F);
+  static constexpr int GS1 = (E + 1) * (F + 1);          // one direction of one root
+  static constexpr int GS = 3 * GS1;
+  static constexpr int EMAXACC = 56;                     // accumulators per lane
+  static constexpr int NEP = (NE + EMAXACC - 1) / EMAXACC;
+  static constexpr int EPS = (NE + NEP - 1) / NEP;
+  static constexpr int FW = NEP > 1 ? ((NF + 63) / 64) * 64 : NF;
+  static constexpr int TPQ = NEP * FW;
+  static constexpr int BLOCK = TPQ > 256 ? ((TPQ + 63) / 64) * 64 : 256;
+  static constexpr int QB = BLOCK / TPQ;
+  static constexpr int PC0 = (40 * 1024) / (QB * N * GS * 8);
+  static constexpr int PC1 = BLOCK / (QB * N * 3);
+  static constexpr int PC = (PC0 < PC1 ? PC0 : PC1) < 1 ? 1 : (PC0 < PC1 ? PC0 : PC1);
+  static constexpr int XS = NE * NF, YS = NA * NB * NF, ZS = NA * NB * NC * ND;
+  static constexpr int R1 = XS > ZS ? XS : ZS;
+  static constexpr int BUF = QB * (R1 + YS);
+  static constexpr bool GLOBAL_BUF = BUF * 8 > 40 * 1024;
+  static constexpr int SG = QB * PC * N * GS;
+  // LDS carved by team_eri: 2D integrals, (buffer), geometry; descriptors are ints
+  static constexpr int LDS_DOUBLES = SG + (GLOBAL_BUF ? 0 : BUF) + QB * 12;
+  static constexpr int LDS_INTS = QB * 8 + 2;
+  static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
+};
+
+// Batch descriptor in LDS, filled by the caller before team_eri:
+//   qi[q*8 + 0..6] = bra pair, ket pair, bra pp_off, bra npp, ket pp_off, ket npp, valid
+//   geo[q*12 + 0..11] = A, B (bra centres), C, D (ket centres)
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void team_fill(int q, const Pair &b, const Pair &k, int bi, int ki, bool valid, int *qi,
+                                          double *geo) {
+  qi[q * 8 + 0] = bi; qi[q * 8 + 1] = ki;
+  qi[q * 8 + 2] = b.pp_off; qi[q * 8 + 3] = valid ? b.npp : 0;
+  qi[q * 8 + 4] = k.pp_off; qi[q * 8 + 5] = valid ? k.npp : 0;
+  qi[q * 8 + 6] = valid;
+  for (int d = 0; d < 3; ++d) {
+    geo[q * 12 + d] = b.A[d]; geo[q * 12 + 3 + d] = b.B[d];
+    geo[q * 12 + 6 + d] = k.A[d]; geo[q * 12 + 9 + d] = k.B[d];
+  }
+}
+
+// Product of one e-slice for one lane: elements e in [P0*EPS, min(NE,(P0+1)*EPS)).
+template <int LA, int LB, int LC, int LD, int P0>
+__device__ __forceinline__ void team_product(const double *__restrict__ base, int xo, int yo, int zo,
+                                             double (&acc)[TeamCfg<LA, LB, LC, LD>::EPS]) {
+  using C = TeamCfg<LA, LB, LC, LD>;
+  constexpr int E0 = CT.start[LA];
+  constexpr int LO = P0 * C::EPS;
+  constexpr int HI = (LO + C::EPS < C::NE) ? LO + C::EPS : C::NE;
+  constexpr int EX = C::E;
+  double gx[EX + 1], gy[EX + 1], gz[EX + 1];
+#pragma unroll
+  for (int e = 0; e <= EX; ++e) {
+    gx[e] = base[xo + e * (C::F + 1)];
+    gy[e] = base[yo + e * (C::F + 1)];
+    gz[e] = base[zo + e * (C::F + 1)];
+  }
+#pragma unroll
+  for (int i = LO; i < HI; ++i) acc[i - LO] = fma(gx[CT.x[E0 + i]] * gy[CT.y[E0 + i]], gz[CT.z[E0 + i]], acc[i - LO]);
+}
+
+template <int LA, int LB, int LC, int LD, int P0>
+__device__ __forceinline__ void team_product_dispatch(int part, const double *base, int xo, int yo, int zo,
+                                                      double (&acc)[TeamCfg<LA, LB, LC, LD>::EPS]) {
+  if constexpr (P0 < TeamCfg<LA, LB, LC, LD>::NEP) {
+    if (part == P0)
+      team_product<LA, LB, LC, LD, P0>(base, xo, yo, zo, acc);
+    else
+      team_product_dispatch<LA, LB, LC, LD, P0 + 1>(part, base, xo, yo, zo, acc);
+  }
+}
+
+// Computes (ab|cd) of the QB quartets described in qi/geo; on return Z[q*ZS + ab*NC*ND + cd]
+// (Z = buf) holds the contracted Cartesian blocks. Every thread of the block must call it;
+// it synchronises the block. sG: SG doubles of LDS; buf: BUF doubles (LDS or global).
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ pp, double *sG, double *buf,
+                                                  const int *qi, const double *geo, int *smax) {
+  using C = TeamCfg<LA, LB, LC, LD>;
+  constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
+  constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
+  constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GS1 = C::GS1, BLOCK = C::BLOCK;
+  constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
+  double *X = buf;                    // [QB][NE][NF]  (later Z: [QB][NA*NB][NC*ND])
+  double *Y = buf + QB * C::R1;       // [QB][NA*NB][NF]
+  const int tid = threadIdx.x;
+
+  const int pq_ = tid / C::TPQ;
+  const int pr = tid % C::TPQ;
+  const int part = pr / C::FW;
+  const int pf = pr % C::FW;
+  const bool prole = pq_ < QB && pf < NF;
+  int xo = 0, yo = 0, zo = 0;
+  if (prole) {
+    xo = CTD.x[F0 + pf];
+    yo = GS1 + CTD.y[F0 + pf];
+    zo = 2 * GS1 + CTD.z[F0 + pf];
+  }
+  if (tid == 0) {
+    int m = 0;
+    for (int q = 0; q < QB; ++q) m = max(m, qi[q * 8 + 3] * qi[q * 8 + 5]);
+    *smax = m;
+  }
+  __syncthreads();
+  const int kmax = *smax;
+
+  double acc[C::EPS];
+#pragma unroll
+  for (int i = 0; i < C::EPS; ++i) acc[i] = 0.0;
+
+  for (int c0 = 0; c0 < kmax; c0 += PC) {
+    for (int t = tid; t < QB * PC * N * 3; t += BLOCK) {
+      const int q = t / (PC * N * 3);
+      const int rem = t % (PC * N * 3);
+      const int pl = rem / (N * 3);
+      const int n = (rem % (N * 3)) / 3;
+      const int dir = rem % 3;
+      const int pidx = c0 + pl;
+      const int nk = qi[q * 8 + 5];
+      if (pidx < qi[q * 8 + 3] * nk) {
+        const PrimPair pb = pp[qi[q * 8 + 2] + pidx / nk];
+        const PrimPair pk = pp[qi[q * 8 + 4] + pidx % nk];
+        PrimQuartet Q;
+        prim_quartet(pb, pk, &geo[q * 12], &geo[q * 12 + 6], Q);
+        double u, w;
+        rys_root1<N>(Q.T, n, u, w);
+        const double uq = u * Q.pq_inv;
+        const double b00 = 0.5 * uq;
+        const double b10 = 0.5 / Q.p * (1.0 - uq * Q.q);
+        const double b01 = 0.5 / Q.q * (1.0 - uq * Q.p);
+        const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
+        const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
+        const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
+        double G[E + 1][F + 1];
+        vrr2d<E, F>(G, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
+        double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
+#pragma unroll
+        for (int e = 0; e <= E; ++e)
+#pragma unroll
+          for (int f = 0; f <= F; ++f) dst[e * (F + 1) + f] = G[e][f];
+      }
+    }
+    __syncthreads();
+    if (prole) {
+      const int npl = min(PC, qi[pq_ * 8 + 3] * qi[pq_ * 8 + 5] - c0);
+      for (int pl = 0; pl < npl; ++pl) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+          const double *base = sG + ((pq_ * PC + pl) * N + n) * GS;
+          team_product_dispatch<LA, LB, LC, LD, 0>(part, base, xo, yo, zo, acc);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (prole) {
+#pragma unroll
+    for (int i = 0; i < C::EPS; ++i) {
+      const int e = part * C::EPS + i;
+      if (e < NE) X[(pq_ * NE + e) * NF + pf] = acc[i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < QB * NA * NB * NF; t += BLOCK) {
+    const int q = t / (NA * NB * NF);
+    const int rem = t % (NA * NB * NF);
+    const int ab = rem / NF, f = rem % NF;
+    const int a = ab / NB, b = ab % NB;
+    const int ax = CTD.x[E0 + a], ay = CTD.y[E0 + a], az = CTD.z[E0 + a];
+    const int bx = CTD.x[CT.start[LB] + b], by = CTD.y[CT.start[LB] + b], bz = CTD.z[CT.start[LB] + b];
+    const double ABx = geo[q * 12 + 0] - geo[q * 12 + 3], ABy = geo[q * 12 + 1] - geo[q * 12 + 4],
+                 ABz = geo[q * 12 + 2] - geo[q * 12 + 5];
+    double v = 0.0, px = 1.0;
+    for (int kx = bx; kx >= 0; --kx) {
+      double py = 1.0;
+      for (int ky = by; ky >= 0; --ky) {
+        double pz = 1.0;
+        for (int kz = bz; kz >= 0; --kz) {
+          const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * px * py * pz;
+          const int ie = CTD.idx[ax + kx][ay + ky][az + kz] - E0;
+          v = fma(cf, X[(q * NE + ie) * NF + f], v);
+          pz *= ABz;
+        }
+        py *= ABy;
+      }
+      px *= ABx;
+    }
+    Y[(q * NA * NB + ab) * NF + f] = v;
+  }
+  __syncthreads();
+  double *Z = X;
+  for (int t = tid; t < QB * NA * NB * NC * ND; t += BLOCK) {
+    const int q = t / (NA * NB * NC * ND);
+    const int rem = t % (NA * NB * NC * ND);
+    const int ab = rem / (NC * ND), cd = rem % (NC * ND);
+    const int c = cd / ND, d = cd % ND;
+    const int cx = CTD.x[F0 + c], cy = CTD.y[F0 + c], cz = CTD.z[F0 + c];
+    const int dx = CTD.x[CT.start[LD] + d], dy = CTD.y[CT.start[LD] + d], dz = CTD.z[CT.start[LD] + d];
+    const double CDx = geo[q * 12 + 6] - geo[q * 12 + 9], CDy = geo[q * 12 + 7] - geo[q * 12 + 10],
+                 CDz = geo[q * 12 + 8] - geo[q * 12 + 11];
+    double v = 0.0, px = 1.0;
+    for (int kx = dx; kx >= 0; --kx) {
+      double py = 1.0;
+      for (int ky = dy; ky >= 0; --ky) {
+        double pz = 1.0;
+        for (int kz = dz; kz >= 0; --kz) {
+          const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * px * py * pz;
+          const int jf = CTD.idx[cx + kx][cy + ky][cz + kz] - F0;
+          v = fma(cf, Y[(q * NA * NB + ab) * NF + jf], v);
+          pz *= CDz;
+        }
+        py *= CDy;
+      }
+      px *= CDx;
+    }
+    Z[(q * NA * NB + ab) * NC * ND + cd] = v;   // region 1 is free: X was consumed by the pass above
+  }
+  __syncthreads();
+  return Z;
+}
+
+}  // namespace jk

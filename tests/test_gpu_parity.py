@@ -83,3 +83,39 @@ def test_properties_symmetry_linearity_repeat():
     assert maxabs(Jb, J1 + 0.5 * Ja) <= 1e-11 and maxabs(Kb, K1 + 0.5 * Ka) <= 1e-11
     (J0, K0), _ = gpu_jk(mol, thresh=0.0, D=np.zeros_like(mol.D))
     assert not J0.any() and not K0.any()
+
+
+def _sampled(mol, pairs, tag):
+    """Full-size build on the GPU; the oracle computes the J and K blocks of a few shell
+    pairs one by one (same screening predicate) and they are compared element-wise."""
+    import time
+    t = time.time()
+    (J, K), st = gpu_jk(mol)
+    say(f"[{tag}] GPU build nbf={mol.nbf} kept={st['kept_quartets']} in {time.time() - t:.1f}s (incl. plan)")
+    o = oracle.Oracle(mol)
+    I, P = o.screen_tables()
+    worst = 0.0
+    for si, sj in pairs:
+        t = time.time()
+        Jb, Kb = o.jk_block(si, sj, I=I, P=P)
+        sl_i = slice(o.off[si], o.off[si + 1])
+        sl_j = slice(o.off[sj], o.off[sj + 1])
+        dj, dk = maxabs(J[sl_i, sl_j], Jb), maxabs(K[sl_i, sl_j], Kb)
+        worst = max(worst, dj, dk)
+        say(f"[{tag}] block ({si},{sj}) l=({mol.shell_l[si]},{mol.shell_l[sj]}) |dJ|={dj:.2e} |dK|={dk:.2e} "
+            f"max|J|={np.max(np.abs(Jb)):.2e} oracle {time.time() - t:.1f}s")
+    assert worst <= TOL
+
+
+def test_cfg2_full_size_sampled():
+    mol = synth.make_config(2)
+    # shells per atom: s6 s1 s1 p3 p1 d1 -> shell index 6*atom + k
+    _sampled(mol, [(0, 0), (6 * 10 + 3, 6 * 2 + 0), (6 * 40 + 5, 6 * 40 + 4), (6 * 63 + 2, 6 * 17 + 1),
+                   (6 * 33 + 5, 6 * 5 + 5)], "cfg2 full")
+
+
+def test_cfg3_full_size_sampled():
+    mol = synth.make_config(3)
+    # shells per atom: s s s s p p p d d f g -> 11 per atom
+    _sampled(mol, [(0, 0), (11 * 7 + 4, 11 * 3 + 1), (11 * 20 + 7, 11 * 20 + 0), (11 * 31 + 9, 11 * 2 + 3)],
+             "cfg3 full")
