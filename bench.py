@@ -111,11 +111,11 @@ def main():
     class_ms = sum(v["ms"] for v in per_class.values()) / args.steps
     top = sorted(per_class.items(), key=lambda kv: -kv[1]["ms"])[:8]
     def cname(k):
-        return "(%d%d|**)" % k[:2] if k[2] < 0 else "(%d%d|%d%d)" % k
+        return "(%d%d|**) tier %d" % (k[0], k[1], k[3]) if k[2] < 0 else "(%d%d|%d%d)" % k
 
     def kname(k, v):
         if v["team"] == 2:
-            return "k_bra<%d,%d>" % k[:2]
+            return "k_bra<%d,%d,%d>" % (k[0], k[1], k[3])
         return "k_cls<%d,%d,%d,%d>" % k + (" team" if v["team"] else " lane")
 
     classes = [{"class": cname(k), "kernel": kname(k, v),

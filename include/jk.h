@@ -113,7 +113,8 @@ int jk_stats(const jk_plan_t *plan, jk_stats_t *out);
 
 /* Per-launch profile of the last jk_plan_execute of a plan created with JK_FLAG_PROFILE.
  * One entry per integral launch (kind 0): either one quartet class (lc, ld >= 0) or one
- * bra class fused over all its ket classes (lc = ld = -1, team = 2), plus the preparation launches
+ * register tier of a bra class fused over its ket classes (lc = -1, ld = tier, team = 2),
+ * plus the preparation launches
  * (kind 1: density transform, block maxima, screening) and the final symmetrise and
  * transform (kind 2). ms is the HIP-event time of the launch on the caller's stream;
  * flops is the algorithmic count of the class, prim_quartets * 3 N nc(a)nc(b)nc(c)nc(d)
@@ -123,7 +124,7 @@ int jk_stats(const jk_plan_t *plan, jk_stats_t *out);
  * Synchronises the plan's last stream. */
 typedef struct {
   int kind;                     /* 0 class kernel, 1 preparation, 2 finalisation */
-  int la, lb, lc, ld;           /* class (kind 0); lc = ld = -1 for a fused bra-class launch */
+  int la, lb, lc, ld;           /* class (kind 0); lc = -1, ld = tier for a fused launch */
   int team;                     /* 0 lane-per-quartet, 1 workgroup body, 2 fused bra-class launch */
   int nroots;                   /* Rys roots N of the class */
   long long quartets;           /* kept unique shell quartets */

@@ -198,6 +198,7 @@ void plan_free(jk_plan *p) {
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
 constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels
 constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
+constexpr int NFUSED = NPAIRCLASS * NTIERS;     // launch slots of the fused kernels
 
 int ensure_scratch(jk_plan *p, long long doubles) {
   if (doubles <= p->scratch_doubles) return JK_OK;
@@ -349,7 +350,7 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
   unsigned long long np[NQCLASS];
   HIPCHK(hipMemcpy(cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(np, p->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
-  const int NSLOT = NPAIRCLASS + NQCLASS;
+  const int NSLOT = NFUSED + NQCLASS;
   int n = 0;
   auto push = [&](const jk_profile_t &e) {
     if (n < max_entries) out[n] = e;
@@ -372,17 +373,19 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
   for (int slot : p->launched) {
     jk_profile_t r{};
     r.kind = 0;
-    if (slot < NPAIRCLASS) {                      // fused launch of a bra class over its ket classes
-      const BraInfo &bi = g_bras[slot];
-      r.la = bi.la; r.lb = bi.lb; r.lc = -1; r.ld = -1;
+    if (slot < NFUSED) {                          // fused launch of one tier of a bra class
+      const int cb = slot / NTIERS, tier = slot % NTIERS;
+      const BraInfo &bi = g_bras[cb];
+      r.la = bi.la; r.lb = bi.lb; r.lc = -1; r.ld = tier;
       r.team = 2;
-      for (int ck = 0; ck <= slot; ++ck) class_flops(qclass_index(slot, ck), r);
+      for (int ck = 0; ck <= cb; ++ck)
+        if ((bi.tier_mask[tier] >> ck) & 1) class_flops(qclass_index(cb, ck), r);
     } else {
-      const ClassInfo &ci = g_classes[slot - NPAIRCLASS];
+      const ClassInfo &ci = g_classes[slot - NFUSED];
       r.la = ci.la; r.lb = ci.lb; r.lc = ci.lc; r.ld = ci.ld;
       r.team = ci.team;
       r.nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
-      class_flops(slot - NPAIRCLASS, r);
+      class_flops(slot - NFUSED, r);
     }
     HIPCHK(hipEventElapsedTime(&ms, p->events[2 * slot], p->events[2 * slot + 1]));
     r.ms = ms;
@@ -590,10 +593,10 @@ int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const j
       (rc = dalloc(&p->d_Pblk, (size_t)ns * ns)) || (rc = dalloc(&p->d_gmax, 1)) ||
       (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
       (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
-      (rc = dalloc(&p->d_next, NPAIRCLASS + NQCLASS)))
+      (rc = dalloc(&p->d_next, NFUSED + NQCLASS)))
     return cleanup(rc);
   if (p->flags & JK_FLAG_PROFILE) {
-    p->events.resize(2 * (NPAIRCLASS + NQCLASS) + 4, nullptr);
+    p->events.resize(2 * (NFUSED + NQCLASS) + 4, nullptr);
     for (auto &e : p->events)
       if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(JK_EDEVICE, "hipEventCreate failed"));
   }
@@ -613,7 +616,7 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   hipStream_t st = (hipStream_t)stream;
   const size_t nc2 = (size_t)p->nc * p->nc;
   const bool prof = (p->flags & JK_FLAG_PROFILE) != 0;
-  const int NSLOT = NPAIRCLASS + NQCLASS;
+  const int NSLOT = NFUSED + NQCLASS;
   p->last_stream = st;
   p->launched.clear();
   if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT], st));
@@ -683,45 +686,50 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   J_.nc = p->nc;
   for (int cb = 0; cb < NPAIRCLASS; ++cb) {
     const int nb = p->cls_beg[cb + 1] - p->cls_beg[cb];
-    bool any = false;
-    for (int ck = 0; ck <= cb; ++ck) any = any || cap[qclass_index(cb, ck)] > 0;
-    if (!nb || !any) continue;
+    if (!nb) continue;
     J_.bra_beg = p->cls_beg[cb];
     J_.bra_end = p->cls_beg[cb + 1];
     const BraInfo &bi = g_bras[cb];
     const int na = ncart(bi.la), nbb = ncart(bi.lb);
-    const size_t fused_lds = ((size_t)(na + nbb) * p->nc + ((na * nbb + 1) & ~1)) * 8 + (size_t)bi.pool_bytes;
     const int grid = std::min(nb, GRID_TEAM_MAX);
-    if (bi.fusable && fused_lds <= FUSED_LDS_MAX) {
-      if (bi.scratch_per_wg > 0) {
-        int rc = ensure_scratch(p, bi.scratch_per_wg * (long long)grid);
-        if (rc) return rc;
-      }
-      J_.scratch = p->d_scratch;
-      J_.scratch_per_wg = bi.scratch_per_wg;
-      J_.next = p->d_next + cb;
-      if (prof) HIPCHK(hipEventRecord(p->events[2 * cb], st));
-      HIPCHK(bi.launch_bra(J_, grid, fused_lds, st));
-      if (prof) HIPCHK(hipEventRecord(p->events[2 * cb + 1], st));
-      p->launched.push_back(cb);
-    } else {
-      for (int ck = 0; ck <= cb; ++ck) {
-        const int qc = qclass_index(cb, ck);
-        if (!cap[qc]) continue;
-        const ClassInfo &ci = g_classes[qc];
-        if (ci.scratch_per_wg > 0) {
-          int rc = ensure_scratch(p, ci.scratch_per_wg * (long long)grid);
+    for (int tier = 0; tier < NTIERS; ++tier) {
+      bool any = false;
+      for (int ck = 0; ck <= cb; ++ck) any = any || (((bi.tier_mask[tier] >> ck) & 1) && cap[qclass_index(cb, ck)] > 0);
+      if (!any) continue;
+      const size_t fused_lds =
+          ((size_t)(na + nbb) * p->nc + ((na * nbb + 1) & ~1)) * 8 + (size_t)bi.pool_bytes[tier];
+      if (bi.fusable[tier] && fused_lds <= FUSED_LDS_MAX) {
+        if (bi.scratch_per_wg[tier] > 0) {
+          int rc = ensure_scratch(p, bi.scratch_per_wg[tier] * (long long)grid);
           if (rc) return rc;
         }
         J_.scratch = p->d_scratch;
-        J_.scratch_per_wg = ci.scratch_per_wg;
-        J_.next = p->d_next + NPAIRCLASS + qc;
-        const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
-        const int slot = NPAIRCLASS + qc;
+        J_.scratch_per_wg = bi.scratch_per_wg[tier];
+        const int slot = cb * NTIERS + tier;
+        J_.next = p->d_next + slot;
         if (prof) HIPCHK(hipEventRecord(p->events[2 * slot], st));
-        HIPCHK(ci.launch_cls(J_, grid, lds, st));
+        HIPCHK(bi.launch_bra[tier](J_, grid, fused_lds, st));
         if (prof) HIPCHK(hipEventRecord(p->events[2 * slot + 1], st));
         p->launched.push_back(slot);
+      } else {
+        for (int ck = 0; ck <= cb; ++ck) {
+          const int qc = qclass_index(cb, ck);
+          if (!((bi.tier_mask[tier] >> ck) & 1) || !cap[qc]) continue;
+          const ClassInfo &ci = g_classes[qc];
+          if (ci.scratch_per_wg > 0) {
+            int rc = ensure_scratch(p, ci.scratch_per_wg * (long long)grid);
+            if (rc) return rc;
+          }
+          J_.scratch = p->d_scratch;
+          J_.scratch_per_wg = ci.scratch_per_wg;
+          const int slot = NFUSED + qc;
+          J_.next = p->d_next + slot;
+          const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
+          if (prof) HIPCHK(hipEventRecord(p->events[2 * slot], st));
+          HIPCHK(ci.launch_cls(J_, grid, lds, st));
+          if (prof) HIPCHK(hipEventRecord(p->events[2 * slot + 1], st));
+          p->launched.push_back(slot);
+        }
       }
     }
   }

@@ -21,12 +21,15 @@ struct ClassInfo {           // one quartet class (la lb | lc ld)
   mode_launch_fn launch_mode[3];
 };
 
-struct BraInfo {             // one bra class (la lb)
+constexpr int NTIERS = 3;    // register tiers of the fused kernels
+
+struct BraInfo {             // one bra class (la lb), per register tier
   int la, lb;
-  int fusable;               // k_bra can run every ket class with 256 lanes
-  int pool_bytes;            // team LDS of k_bra
-  long long scratch_per_wg;  // doubles of global team buffer per workgroup
-  jk_launch_fn launch_bra;   // k_bra (null if not fusable)
+  int tier_mask[NTIERS];     // ket classes of each tier (bit ck)
+  int fusable[NTIERS];       // k_bra can run every ket class of the tier with 256 lanes
+  int pool_bytes[NTIERS];    // team LDS of k_bra
+  long long scratch_per_wg[NTIERS];  // doubles of global team buffer per workgroup
+  jk_launch_fn launch_bra[NTIERS];   // k_bra (null if not fusable)
 };
 
 #define JK_DECL_BRA(LA, LB) void register_bra_##LA##LB(ClassInfo *classes, BraInfo *bras);

@@ -22,19 +22,21 @@ hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stre
 
 template <int LA, int LB, int LC, int LD, int MODE>
 hipError_t launch_mode(const ModeArgs &args, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL((k_mode<LA, LB, LC, LD, MODE>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), 0, stream, args);
+  constexpr int block = use_team<LA, LB, LC, LD>() ? TeamCfg<LA, LB, LC, LD>::BLOCK : 256;
+  hipLaunchKernelGGL((k_mode<LA, LB, LC, LD, MODE>), dim3(grid), dim3(block), 0, stream, args);
   return hipGetLastError();
 }
 
-template <int LA, int LB>
+template <int LA, int LB, int TIER>
 hipError_t launch_bra(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_bra<LA, LB>, hipFuncAttributeMaxDynamicSharedMemorySize, DYN_LDS_MAX);
+    (void)hipFuncSetAttribute((const void *)k_bra<LA, LB, TIER>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              DYN_LDS_MAX);
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL((k_bra<LA, LB>), dim3(grid), dim3(256), lds, stream, args);
+  hipLaunchKernelGGL((k_bra<LA, LB, TIER>), dim3(grid), dim3(256), lds, stream, args);
   return hipGetLastError();
 }
 
@@ -43,11 +45,11 @@ void register_one(ClassInfo *table) {
   ClassInfo &ci = table[qclass_index(pair_class(LA, LB), pair_class(LC, LD))];
   ci.la = LA; ci.lb = LB; ci.lc = LC; ci.ld = LD;
   if constexpr (use_team<LA, LB, LC, LD>()) {
-    using C = TeamCfg<LA, LB, LC, LD>;
+    using C = TeamCfg<LA, LB, LC, LD>;   // k_mode (Schwarz / ERI tensor) always uses this body
     ci.team = 1;
     ci.block = C::BLOCK;
     ci.per_block = C::QB;
-    ci.team_lds = C::LDS_BYTES;
+    ci.team_lds = team_lds_bytes<LA, LB, LC, LD>();
     ci.scratch_per_wg = C::GLOBAL_BUF ? (long long)C::BUF : 0;
   } else {
     ci.team = 0;
@@ -70,18 +72,26 @@ void register_kets(ClassInfo *table) {
   }
 }
 
+template <int LA, int LB, int TIER>
+void register_tier(BraInfo &b) {
+  b.tier_mask[TIER] = tier_mask<LA, LB, TIER>();
+  b.fusable[TIER] = bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0;
+  b.pool_bytes[TIER] = bra_pool_bytes<LA, LB, TIER>();
+  b.scratch_per_wg[TIER] = bra_scratch_doubles<LA, LB, TIER>();
+  if constexpr (bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0)
+    b.launch_bra[TIER] = launch_bra<LA, LB, TIER>;
+  else
+    b.launch_bra[TIER] = nullptr;
+}
+
 template <int LA, int LB>
 void register_bra(ClassInfo *classes, BraInfo *bras) {
   register_kets<LA, LB>(classes);
   BraInfo &b = bras[pair_class(LA, LB)];
   b.la = LA; b.lb = LB;
-  b.fusable = bra_fusable<LA, LB>();
-  b.pool_bytes = bra_pool_bytes<LA, LB>();
-  b.scratch_per_wg = bra_scratch_doubles<LA, LB>();
-  if constexpr (bra_fusable<LA, LB>())
-    b.launch_bra = launch_bra<LA, LB>;
-  else
-    b.launch_bra = nullptr;
+  register_tier<LA, LB, 0>(b);
+  register_tier<LA, LB, 1>(b);
+  register_tier<LA, LB, 2>(b);
 }
 
 }  // namespace jk

@@ -157,14 +157,20 @@ struct TeamCfg {
   static constexpr int FW = NEP > 1 ? ((NF + 63) / 64) * 64 : NF;
   static constexpr int TPQ = NEP * FW;
   static constexpr int BLOCK = TPQ > 256 ? ((TPQ + 63) / 64) * 64 : 256;
-  static constexpr int QB = BLOCK / TPQ;
+  static constexpr int QB0 = BLOCK / TPQ;
+  static constexpr int QBL = (40 * 1024) / (N * GS * 8);       // one primitive chunk of 2D integrals in 40 KB
+  static constexpr int R1_ = (NE * NF > NA * NB * NC * ND) ? NE * NF : NA * NB * NC * ND;
+  static constexpr int QBB = (48 * 1024) / ((R1_ + NA * NB * NF) * 8);   // transfer buffers in 48 KB of LDS
+  static constexpr int QB1 = QB0 < QBL ? QB0 : QBL;
+  static constexpr int QB2 = QB1 < QBB ? QB1 : QBB;
+  static constexpr int QB = QB2 < 1 ? 1 : QB2;
   static constexpr int PC0 = (40 * 1024) / (QB * N * GS * 8);
   static constexpr int PC1 = BLOCK / (QB * N * 3);
   static constexpr int PC = (PC0 < PC1 ? PC0 : PC1) < 1 ? 1 : (PC0 < PC1 ? PC0 : PC1);
   static constexpr int XS = NE * NF, YS = NA * NB * NF, ZS = NA * NB * NC * ND;
   static constexpr int R1 = XS > ZS ? XS : ZS;
   static constexpr int BUF = QB * (R1 + YS);
-  static constexpr bool GLOBAL_BUF = BUF * 8 > 40 * 1024;
+  static constexpr bool GLOBAL_BUF = BUF * 8 > 48 * 1024;
   static constexpr int SG = QB * PC * N * GS;
   // LDS carved by team_eri: 2D integrals, (buffer), geometry; descriptors are ints
   static constexpr int LDS_DOUBLES = SG + (GLOBAL_BUF ? 0 : BUF) + QB * 12;
@@ -367,6 +373,196 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   }
   __syncthreads();
   return Z;
+}
+
+}  // namespace jk
+
+namespace jk {
+
+// ================================================================== workgroup per batch, one LDS stage
+// For classes whose e components fit in one lane (NE <= 56): lane (q, f) accumulates the
+// [e0|f0] column of one f component for all e, applies the bra transfer in registers
+// (compile-time indices) and stores (ab|f) in LDS; the ket transfer is then done per
+// (quartet, cd) from LDS by the caller (team2_ket).
+template <int LA, int LB, int LC, int LD>
+struct Team2Cfg {
+  static constexpr int E = LA + LB, F = LC + LD, N = (E + F) / 2 + 1;
+  static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+  static constexpr int NE = range_count(LA, E), NF = range_count(LC, F);
+  static constexpr int GS1 = (E + 1) * (F + 1);
+  static constexpr int GS = 3 * GS1;
+  static constexpr bool OK = NE <= 56 && NF <= 256;
+  static constexpr int YS = NA * NB * NF;
+  static constexpr int QB0 = 256 / NF;
+  static constexpr int BUDGET = 48 * 1024 / 8;                   // doubles of LDS for G + Y
+  static constexpr int QB1 = BUDGET / (YS + N * GS);             // at least one primitive chunk
+  static constexpr int QB = (QB0 < QB1 ? QB0 : QB1) < 1 ? 1 : (QB0 < QB1 ? QB0 : QB1);
+  static constexpr int PCB = (BUDGET - QB * YS) / (QB * N * GS);
+  static constexpr int PCT = 256 / (QB * N * 3);                 // VRR items in one pass of the block
+  static constexpr int PC0 = PCB < PCT ? PCB : PCT;
+  static constexpr int PC = PC0 < 1 ? 1 : (PC0 > 4 ? 4 : PC0);
+  static constexpr int SG = QB * PC * N * GS;
+  static constexpr int LDS_DOUBLES = SG + QB * YS + QB * 12;
+  static constexpr int LDS_INTS = QB * 8 + 2;
+  static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
+};
+
+// Fills Y[q][ab][f] = (ab|f0) of the QB quartets described in qi/geo (same layout as team_eri).
+// Every thread of the block calls it; it synchronises the block. Returns Y.
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ pp, double *sG, double *Y,
+                                                   const int *qi, const double *geo, int *smax) {
+  using C = Team2Cfg<LA, LB, LC, LD>;
+  constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
+  constexpr int NA = C::NA, NB = C::NB;
+  constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GS1 = C::GS1;
+  constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
+  const int tid = threadIdx.x;
+  const int pq_ = tid / NF;
+  const int pf = tid % NF;
+  const bool prole = pq_ < QB;
+  int xo = 0, yo = 0, zo = 0;
+  if (prole) {
+    xo = CTD.x[F0 + pf];
+    yo = GS1 + CTD.y[F0 + pf];
+    zo = 2 * GS1 + CTD.z[F0 + pf];
+  }
+  if (tid == 0) {
+    int m = 0;
+    for (int q = 0; q < QB; ++q) m = max(m, qi[q * 8 + 3] * qi[q * 8 + 5]);
+    *smax = m;
+  }
+  __syncthreads();
+  const int kmax = *smax;
+  double acc[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) acc[i] = 0.0;
+  for (int c0 = 0; c0 < kmax; c0 += PC) {
+    for (int t = tid; t < QB * PC * N * 3; t += blockDim.x) {
+      const int q = t / (PC * N * 3);
+      const int rem = t % (PC * N * 3);
+      const int pl = rem / (N * 3);
+      const int n = (rem % (N * 3)) / 3;
+      const int dir = rem % 3;
+      const int pidx = c0 + pl;
+      const int nk = qi[q * 8 + 5];
+      if (pidx < qi[q * 8 + 3] * nk) {
+        const PrimPair pb = pp[qi[q * 8 + 2] + pidx / nk];
+        const PrimPair pk = pp[qi[q * 8 + 4] + pidx % nk];
+        PrimQuartet Q;
+        prim_quartet(pb, pk, &geo[q * 12], &geo[q * 12 + 6], Q);
+        double u, w;
+        rys_root1<N>(Q.T, n, u, w);
+        const double uq = u * Q.pq_inv;
+        const double b00 = 0.5 * uq;
+        const double b10 = 0.5 / Q.p * (1.0 - uq * Q.q);
+        const double b01 = 0.5 / Q.q * (1.0 - uq * Q.p);
+        const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
+        const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
+        const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
+        double G[E + 1][F + 1];
+        vrr2d<E, F>(G, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
+        double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
+#pragma unroll
+        for (int e = 0; e <= E; ++e)
+#pragma unroll
+          for (int f = 0; f <= F; ++f) dst[e * (F + 1) + f] = G[e][f];
+      }
+    }
+    __syncthreads();
+    if (prole) {
+      const int npl = min(PC, qi[pq_ * 8 + 3] * qi[pq_ * 8 + 5] - c0);
+      for (int pl = 0; pl < npl; ++pl) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+          const double *base = sG + ((pq_ * PC + pl) * N + n) * GS;
+          double gx[E + 1], gy[E + 1], gz[E + 1];
+#pragma unroll
+          for (int e = 0; e <= E; ++e) {
+            gx[e] = base[xo + e * (F + 1)];
+            gy[e] = base[yo + e * (F + 1)];
+            gz[e] = base[zo + e * (F + 1)];
+          }
+#pragma unroll
+          for (int i = 0; i < NE; ++i)
+            acc[i] = fma(gx[CT.x[E0 + i]] * gy[CT.y[E0 + i]], gz[CT.z[E0 + i]], acc[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (prole) {
+    const double AB[3] = {geo[pq_ * 12 + 0] - geo[pq_ * 12 + 3], geo[pq_ * 12 + 1] - geo[pq_ * 12 + 4],
+                          geo[pq_ * 12 + 2] - geo[pq_ * 12 + 5]};
+    double abp[3][LB + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      abp[d][0] = 1.0;
+#pragma unroll
+      for (int k = 1; k <= LB; ++k) abp[d][k] = abp[d][k - 1] * AB[d];
+    }
+    constexpr int A0 = CT.start[LA], B0 = CT.start[LB];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int ax = CT.x[A0 + a], ay = CT.y[A0 + a], az = CT.z[A0 + a];
+        const int bx = CT.x[B0 + b], by = CT.y[B0 + b], bz = CT.z[B0 + b];
+        double v = 0.0;
+#pragma unroll
+        for (int kx = 0; kx <= LB; ++kx) {
+          if (kx > bx) continue;
+#pragma unroll
+          for (int ky = 0; ky <= LB; ++ky) {
+            if (ky > by) continue;
+#pragma unroll
+            for (int kz = 0; kz <= LB; ++kz) {
+              if (kz > bz) continue;
+              const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * abp[0][bx - kx] *
+                                abp[1][by - ky] * abp[2][bz - kz];
+              v = fma(cf, acc[CT.idx[ax + kx][ay + ky][az + kz] - E0], v);
+            }
+          }
+        }
+        Y[(pq_ * NA * NB + a * NB + b) * NF + pf] = v;
+      }
+    }
+  }
+  __syncthreads();
+  return Y;
+}
+
+// (ab|cd) for one quartet q and one ket component pair cd, all ab, from Y (ket transfer).
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void team2_ket(const double *Y, const double *geo, int q, int cd,
+                                          double (&g)[ncart(LA) * ncart(LB)]) {
+  using C = Team2Cfg<LA, LB, LC, LD>;
+  constexpr int NA = C::NA, NB = C::NB, ND = C::ND, NF = C::NF;
+  constexpr int F0 = CT.start[LC];
+  const int c = cd / ND, d = cd % ND;
+  const int cx = CTD.x[F0 + c], cy = CTD.y[F0 + c], cz = CTD.z[F0 + c];
+  const int dx = CTD.x[CT.start[LD] + d], dy = CTD.y[CT.start[LD] + d], dz = CTD.z[CT.start[LD] + d];
+  const double CDx = geo[q * 12 + 6] - geo[q * 12 + 9], CDy = geo[q * 12 + 7] - geo[q * 12 + 10],
+               CDz = geo[q * 12 + 8] - geo[q * 12 + 11];
+#pragma unroll
+  for (int ab = 0; ab < NA * NB; ++ab) g[ab] = 0.0;
+  const double *Yq = Y + (size_t)q * NA * NB * NF;
+  double px = 1.0;
+  for (int kx = dx; kx >= 0; --kx) {
+    double py = 1.0;
+    for (int ky = dy; ky >= 0; --ky) {
+      double pz = 1.0;
+      for (int kz = dz; kz >= 0; --kz) {
+        const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * px * py * pz;
+        const int jf = CTD.idx[cx + kx][cy + ky][cz + kz] - F0;
+#pragma unroll
+        for (int ab = 0; ab < NA * NB; ++ab) g[ab] = fma(cf, Yq[ab * NF + jf], g[ab]);
+        pz *= CDz;
+      }
+      py *= CDy;
+    }
+    px *= CDx;
+  }
 }
 
 }  // namespace jk

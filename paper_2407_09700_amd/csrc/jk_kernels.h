@@ -24,13 +24,23 @@
 
 namespace jk {
 
-constexpr int SMALL_REG_LIMIT = 100;   // lane per quartet when [e0|f0] accumulators + one root's 2D integrals fit
-constexpr int SMALL_OUT_LIMIT = 100;   // ... and the contracted block + the bra Coulomb partials fit
+constexpr int SMALL_REG_LIMIT = 320;   // lane per quartet when [e0|f0] accumulators + one root's 2D integrals fit
+constexpr int SMALL_OUT_LIMIT = 400;   // ... and the contracted block + the bra Coulomb partials fit
 
 template <int LA, int LB, int LC, int LD>
 constexpr bool use_team() {
   using C = SmallCfg<LA, LB, LC, LD>;
   return C::REGS > SMALL_REG_LIMIT || C::NG + C::NA * C::NB > SMALL_OUT_LIMIT;
+}
+
+// Register tiers of the fused kernels: 0 light lane bodies, 1 heavy lane bodies, 2 team bodies.
+// Each tier is its own launch so that the heaviest body does not set the occupancy of all.
+constexpr int NTIER = 3;
+template <int LA, int LB, int LC, int LD>
+constexpr int tier_of() {
+  using C = SmallCfg<LA, LB, LC, LD>;
+  if (use_team<LA, LB, LC, LD>()) return 2;
+  return (C::REGS <= 100 && C::NG + C::NA * C::NB <= 100) ? 0 : 1;
 }
 
 constexpr int pc_la(int c) { int l = 0; while ((l + 1) * (l + 2) / 2 <= c) ++l; return l; }
@@ -246,10 +256,100 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   }
 }
 
+// ------------------------------------------------------------------ workgroup body, one LDS stage
+// pool: Team2Cfg::LDS_BYTES of LDS. The bra Coulomb partials accumulate in jab (registers).
+template <int LA, int LB, int LC, int LD, bool KLDS>
+__device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
+                                              double *pool, double (&jab)[ncart(LA) * ncart(LB)]) {
+  using C = Team2Cfg<LA, LB, LC, LD>;
+  constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, QB = C::QB;
+  constexpr int ck = pair_class(LC, LD);
+  double *sG = pool;
+  double *Y = pool + C::SG;
+  double *geo = Y + QB * C::YS;
+  int *qi = reinterpret_cast<int *>(geo + QB * 12);
+  int *smax = qi + QB * 8;
+  const Pair bra = A.pairs[bi];
+  const int tid = threadIdx.x;
+  const int nc = A.nc;
+  const double *Dm = A.Dc;
+  const int oa = bra.ca, ob = bra.cb;
+  for (int k0 = 0; k0 < cnt; k0 += QB) {
+    if (tid < QB) {
+      const int k = k0 + tid;
+      const bool valid = k < cnt;
+      const int ki = kl[valid ? k : k0];
+      team_fill<LA, LB, LC, LD>(tid, bra, A.pairs[ki], bi, ki, valid, qi, geo);
+    }
+    __syncthreads();
+    team2_eri<LA, LB, LC, LD>(A.pp, sG, Y, qi, geo, smax);
+    for (int t = tid; t < QB * NC * ND; t += blockDim.x) {
+      const int q = t / (NC * ND), cd = t % (NC * ND);
+      if (!qi[q * 8 + 6]) continue;
+      const int ki = qi[q * 8 + 1];
+      const Pair &ket = A.pairs[ki];
+      const double s = sym_factor(bra, ket, bi, ki);
+      double g[NA * NB];
+      team2_ket<LA, LB, LC, LD>(Y, geo, q, cd, g);
+      const int c = cd / ND, d = cd % ND;
+      const int cc = ket.ca + c, dd = ket.cb + d;
+      const double dcd = Dm[(size_t)cc * nc + dd];
+      double vj = 0.0;
+#pragma unroll
+      for (int ab = 0; ab < NA * NB; ++ab) {
+        jab[ab] = fma(2.0 * s * dcd, g[ab], jab[ab]);
+        vj = fma(g[ab], Dm[(size_t)(oa + ab / NB) * nc + ob + ab % NB], vj);
+      }
+      atomic_add(jp_elem(A, ck, ki, cd), 2.0 * s * vj);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        double kc = 0.0, kd = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          kc = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + dd], kc);
+          kd = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + cc], kd);
+        }
+        k_update<KLDS>(A, Krow, a, oa + a, cc, s * kc);
+        k_update<KLDS>(A, Krow, a, oa + a, dd, s * kd);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        double kc = 0.0, kd = 0.0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          kc = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + dd], kc);
+          kd = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + cc], kd);
+        }
+        k_update<KLDS>(A, Krow, NA + b, ob + b, cc, s * kc);
+        k_update<KLDS>(A, Krow, NA + b, ob + b, dd, s * kd);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int LA, int LB, int LC, int LD>
+constexpr bool use_team2() { return use_team<LA, LB, LC, LD>() && Team2Cfg<LA, LB, LC, LD>::OK; }
+
+template <int LA, int LB, int LC, int LD>
+constexpr int team_lds_bytes() {
+  if constexpr (!use_team<LA, LB, LC, LD>()) return 0;
+  else if constexpr (use_team2<LA, LB, LC, LD>()) return Team2Cfg<LA, LB, LC, LD>::LDS_BYTES;
+  else return TeamCfg<LA, LB, LC, LD>::LDS_BYTES;
+}
+
+template <int LA, int LB, int LC, int LD>
+constexpr int team_block() {
+  if constexpr (use_team<LA, LB, LC, LD>() && !use_team2<LA, LB, LC, LD>()) return TeamCfg<LA, LB, LC, LD>::BLOCK;
+  else return 256;
+}
+
 template <int LA, int LB, int LC, int LD, bool KLDS>
 __device__ __forceinline__ void jk_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow, double *jab_s,
                                         double *pool, double (&jab)[ncart(LA) * ncart(LB)]) {
-  if constexpr (use_team<LA, LB, LC, LD>())
+  if constexpr (use_team2<LA, LB, LC, LD>())
+    jk_team2_body<LA, LB, LC, LD, KLDS>(A, bi, kl, cnt, Krow, pool, jab);
+  else if constexpr (use_team<LA, LB, LC, LD>())
     jk_team_body<LA, LB, LC, LD, KLDS>(A, bi, kl, cnt, Krow, jab_s, pool);
   else
     jk_small_body<LA, LB, LC, LD, KLDS>(A, bi, kl, cnt, Krow, jab);
@@ -267,56 +367,70 @@ __device__ __forceinline__ void jab_reduce(double (&jab)[NAB], double *jab_s) {
   }
 }
 
-template <int LA, int LB, int P>
+template <int LA, int LB, int TIER, int P>
 __device__ __forceinline__ void ket_dispatch(int ck, const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                              double *jab_s, double *pool, double (&jab)[ncart(LA) * ncart(LB)]) {
   if constexpr (P <= pair_class(LA, LB)) {
-    if (ck == P)
-      jk_body<LA, LB, pc_la(P), pc_lb(P), true>(A, bi, kl, cnt, Krow, jab_s, pool, jab);
-    else
-      ket_dispatch<LA, LB, P + 1>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
+    if constexpr (tier_of<LA, LB, pc_la(P), pc_lb(P)>() == TIER) {
+      if (ck == P) {
+        jk_body<LA, LB, pc_la(P), pc_lb(P), true>(A, bi, kl, cnt, Krow, jab_s, pool, jab);
+        return;
+      }
+    }
+    ket_dispatch<LA, LB, TIER, P + 1>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
   }
 }
 
-// Largest team LDS over the ket classes of a bra class (pool of k_bra), in bytes.
-template <int LA, int LB, int P = 0>
+// Ket classes of a bra class that belong to a tier (bit P set for ket class P).
+template <int LA, int LB, int TIER, int P = 0>
+constexpr int tier_mask() {
+  if constexpr (P > pair_class(LA, LB)) return 0;
+  else return ((tier_of<LA, LB, pc_la(P), pc_lb(P)>() == TIER) ? (1 << P) : 0) | tier_mask<LA, LB, TIER, P + 1>();
+}
+
+// Largest team LDS over the ket classes of a tier (pool of k_bra), in bytes.
+template <int LA, int LB, int TIER, int P = 0>
 constexpr int bra_pool_bytes() {
   if constexpr (P > pair_class(LA, LB)) {
     return 0;
   } else {
-    constexpr int here = use_team<LA, LB, pc_la(P), pc_lb(P)>() ? TeamCfg<LA, LB, pc_la(P), pc_lb(P)>::LDS_BYTES : 0;
-    constexpr int rest = bra_pool_bytes<LA, LB, P + 1>();
+    constexpr bool mine = tier_of<LA, LB, pc_la(P), pc_lb(P)>() == TIER;
+    constexpr int here = mine ? team_lds_bytes<LA, LB, pc_la(P), pc_lb(P)>() : 0;
+    constexpr int rest = bra_pool_bytes<LA, LB, TIER, P + 1>();
     return here > rest ? here : rest;
   }
 }
 
-// True when every team body of the bra class runs with 256 lanes (k_bra's block).
-template <int LA, int LB, int P = 0>
+// True when every team body of the tier runs with 256 lanes (k_bra's block).
+template <int LA, int LB, int TIER, int P = 0>
 constexpr bool bra_fusable() {
   if constexpr (P > pair_class(LA, LB)) {
     return true;
   } else {
-    constexpr bool ok = !use_team<LA, LB, pc_la(P), pc_lb(P)>() || TeamCfg<LA, LB, pc_la(P), pc_lb(P)>::BLOCK == 256;
-    return ok && bra_fusable<LA, LB, P + 1>();
+    constexpr bool mine = tier_of<LA, LB, pc_la(P), pc_lb(P)>() == TIER;
+    constexpr bool ok = !mine || team_block<LA, LB, pc_la(P), pc_lb(P)>() == 256;
+    return ok && bra_fusable<LA, LB, TIER, P + 1>();
   }
 }
 
-// Largest global team buffer (doubles per workgroup) over the ket classes of a bra class.
-template <int LA, int LB, int P = 0>
+// Largest global team buffer (doubles per workgroup) over the ket classes of a tier.
+template <int LA, int LB, int TIER, int P = 0>
 constexpr long long bra_scratch_doubles() {
   if constexpr (P > pair_class(LA, LB)) {
     return 0;
   } else {
     using C = TeamCfg<LA, LB, pc_la(P), pc_lb(P)>;
-    constexpr long long here = (use_team<LA, LB, pc_la(P), pc_lb(P)>() && C::GLOBAL_BUF) ? C::BUF : 0;
-    constexpr long long rest = bra_scratch_doubles<LA, LB, P + 1>();
+    constexpr bool mine = tier_of<LA, LB, pc_la(P), pc_lb(P)>() == TIER && use_team<LA, LB, pc_la(P), pc_lb(P)>() &&
+                          !use_team2<LA, LB, pc_la(P), pc_lb(P)>();
+    constexpr long long here = (mine && C::GLOBAL_BUF) ? C::BUF : 0;
+    constexpr long long rest = bra_scratch_doubles<LA, LB, TIER, P + 1>();
     return here > rest ? here : rest;
   }
 }
 
 // ------------------------------------------------------------------ fused kernel: one bra pair, every ket class
 // Dynamic LDS: Krow (NA+NB) x nc | jab_s NA*NB (padded to even) | team pool.
-template <int LA, int LB>
+template <int LA, int LB, int TIER>
 __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB);
   extern __shared__ double smem[];
@@ -338,11 +452,13 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
     double jab[NA * NB];
 #pragma unroll
     for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
+    constexpr int mask = tier_mask<LA, LB, TIER>();
     for (int ck = 0; ck <= cb; ++ck) {
+      if (!((mask >> ck) & 1)) continue;
       const int cnt = A.segcnt[(size_t)bi * NPAIRCLASS + ck];
       if (cnt == 0) continue;
       const int *kl = A.kets + A.class_off[qclass_index(cb, ck)] + A.segoff[(size_t)bi * NPAIRCLASS + ck];
-      ket_dispatch<LA, LB, 0>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
+      ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
     }
     jab_reduce<NA * NB>(jab, jab_s);
     __syncthreads();
@@ -363,10 +479,7 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
 
 // ------------------------------------------------------------------ per-class kernel (exchange to global memory)
 template <int LA, int LB, int LC, int LD>
-constexpr int cls_block() {
-  if constexpr (use_team<LA, LB, LC, LD>()) return TeamCfg<LA, LB, LC, LD>::BLOCK;
-  else return 256;
-}
+constexpr int cls_block() { return team_block<LA, LB, LC, LD>(); }
 
 // Dynamic LDS: jab_s NA*NB (padded to even) | team pool (team classes).
 template <int LA, int LB, int LC, int LD>
@@ -388,7 +501,7 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
     const int cnt = A.segcnt[(size_t)bi * NPAIRCLASS + ck];
     if (cnt > 0) {
       const int *kl = A.kets + A.class_off[qclass_index(cb, ck)] + A.segoff[(size_t)bi * NPAIRCLASS + ck];
-      if constexpr (use_team<LA, LB, LC, LD>()) {
+      if constexpr (use_team<LA, LB, LC, LD>() && !use_team2<LA, LB, LC, LD>()) {
         double jab[1];
         jk_team_body<LA, LB, LC, LD, false>(A, bi, kl, cnt, nullptr, jab_s, pool);
         (void)jab;
@@ -396,7 +509,7 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
         double jab[NA * NB];
 #pragma unroll
         for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
-        jk_small_body<LA, LB, LC, LD, false>(A, bi, kl, cnt, nullptr, jab);
+        jk_body<LA, LB, LC, LD, false>(A, bi, kl, cnt, nullptr, jab_s, pool, jab);
         jab_reduce<NA * NB>(jab, jab_s);
       }
       __syncthreads();
@@ -430,8 +543,11 @@ __device__ __forceinline__ void eri_store8(double *out, size_t nc, size_t i, siz
   out[((l * nc + k) * nc + j) * nc + i] = v;
 }
 
+template <int LA, int LB, int LC, int LD>
+constexpr int mode_block() { return use_team<LA, LB, LC, LD>() ? TeamCfg<LA, LB, LC, LD>::BLOCK : 256; }
+
 template <int LA, int LB, int LC, int LD, int MODE>
-__global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_mode(ModeArgs M) {
+__global__ __launch_bounds__((mode_block<LA, LB, LC, LD>())) void k_mode(ModeArgs M) {
   constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
   if constexpr (use_team<LA, LB, LC, LD>()) {
     using C = TeamCfg<LA, LB, LC, LD>;
