@@ -51,7 +51,11 @@ extern "C" {
 #define JK_FP64 0
 #define JK_MIXED 1
 
-#define JK_FLAG_PROFILE 1     /* jk_opts_t.flags: time every kernel launch of jk_plan_execute */
+#define JK_FLAG_PROFILE 1     /* jk_opts_t.flags: time every kernel launch of an execute */
+#define JK_FLAG_GRAPH 2       /* jk_opts_t.flags: record the build in a HIP graph on the first
+                                 execute and replay it afterwards (no host round trip inside) */
+#define JK_FLAG_TUNE 4        /* jk_opts_t.flags: pick the workgroup count of every integral
+                                 launch by timing candidates on the first execute */
 
 typedef struct {
   int nshell;
@@ -69,10 +73,13 @@ typedef struct {
   double thresh;         /* tau: quartet kept iff I_ab > tau, I_cd > tau, I_ab I_cd P >= tau */
   int precision;         /* JK_FP64 (default) or JK_MIXED */
   double fp32_cutoff;    /* JK_MIXED: quartets with I_ab I_cd P below this run in FP32 */
-  int flags;             /* JK_FLAG_PROFILE or 0 */
+  int flags;             /* OR of JK_FLAG_* (0: none) */
+  const char *tune_cache; /* JK_FLAG_TUNE: HOST path of a text file that keeps the choices
+                             between runs (read if present, written after tuning); NULL: none */
 } jk_opts_t;
 
 typedef struct jk_plan jk_plan_t;
+typedef struct jk_batch jk_batch_t;
 
 typedef struct {
   long long kept_quartets;      /* unique shell quartets that passed the screen (last execute) */
@@ -146,6 +153,47 @@ int jk_schwarz(const jk_plan_t *plan, double *out);
 /* Host-only helper: the library's Cartesian -> real-solid-harmonic matrix for l
  * (HOST out, (2l+1) x (l+1)(l+2)/2, row-major). Needs no device. l in 2..4. */
 int jk_sph_matrix(int l, double *out);
+
+/* Host-only test hook: the closed-form Rys rule the kernels use for 1 or 2 roots (Boys
+ * moments F_0..F_(2N-1)(T) from a series or erf/exp, then the N-point Gauss rule), compiled
+ * for the host from the same source. u, w: HOST arrays of nroots entries (u = t^2). */
+int jk_rys_closed(int nroots, double T, double *u, double *w);
+
+/* ---- Batched build: many independent molecules in one pass.
+ * The shell pairs of all molecules share the class work lists and the persistent
+ * integral launches (one launch per class group for the whole batch, not per molecule);
+ * each molecule keeps its own density and outputs. This extends the paper's per-class
+ * batching of shell quartets (section 3) across molecules. */
+
+/* Create a batch of nmol molecules: basis[m], coords[m] (HOST, natom[m] x 3) as for
+ * jk_plan_create. opts (may be NULL) applies to every molecule. With JK_FLAG_GRAPH the
+ * first execute runs eagerly, then records the whole build (density transform, screen,
+ * integral launches, finalisation) in a HIP graph that later executes replay. */
+int jk_batch_create(int nmol, const jk_basis_t *const *basis, const double *const *coords, const int *natom,
+                    const jk_opts_t *opts, jk_batch_t **out);
+
+/* Packed layout of a batch: molecule m's nao[m] x nao[m] block starts at element off[m]
+ * of the packed D, J and K arrays (off has nmol+1 entries; off[nmol] = total length).
+ * off and nao are HOST arrays; either may be NULL. */
+int jk_batch_offsets(const jk_batch_t *batch, long long *off, int *nao);
+
+/* J and K of every molecule (DEVICE, packed as jk_batch_offsets says, overwritten) for the
+ * packed densities D (DEVICE). Work is enqueued on `stream`. Without JK_FLAG_GRAPH this
+ * behaves as jk_plan_execute (one mid-build read of the work-list sizes). With it, a replay
+ * runs with the work-list capacity fixed at recording time (the first execute's need plus
+ * headroom); the call then waits for the stream and checks a device flag: if a density
+ * needed more room, the build is redone eagerly with larger lists and the graph is
+ * recorded again, so the outputs are always complete when the call returns. */
+int jk_batch_execute(jk_batch_t *batch, const double *D, double *J, double *K, void *stream);
+
+/* Statistics of the batch and its last execute, summed over the molecules. */
+int jk_batch_stats(const jk_batch_t *batch, jk_stats_t *out);
+
+/* Graph status: *recorded = 1 once a graph exists, *replays = executes served by it,
+ * *rerecords = times a capacity overflow forced a new recording. HOST ints, may be NULL. */
+int jk_batch_graph_info(const jk_batch_t *batch, int *recorded, long long *replays, int *rerecords);
+
+void jk_batch_destroy(jk_batch_t *batch);
 
 /* Thread-local message of the last failure (never NULL). */
 const char *jk_last_error(void);

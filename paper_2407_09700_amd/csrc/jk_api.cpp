@@ -141,37 +141,48 @@ void dfree(T *&p) {
 }  // namespace
 
 struct jk_plan {
-  int nshell = 0, natom = 0, nao = 0, nc = 0;
+  int nmol = 0, nshell = 0, nao = 0, nc = 0, nc_max = 0;
   double tau = 1e-12;
   int precision = JK_FP64;
   double fp32_cutoff = 1e-6;
-  std::vector<int> l, pure, atom, cart_off, ao_off;
-  std::vector<double> coords;
-  std::vector<double> schwarz;         // nshell x nshell
+  int flags = 0;
+  std::string tune_cache;
+  std::vector<int> l, pure, cart_off, ao_off;    // per shell of the batch (offsets inside its molecule)
+  std::vector<int> sbase, cbase, abase;          // [nmol+1] first shell / Cartesian AO / AO of each molecule
+  std::vector<long long> mc_off, mf_off, ps_off; // [nmol+1] first element of each molecule's nc^2 / nao^2 / ns^2 block
+  std::vector<int> mnc;                          // [nmol] Cartesian AO count of each molecule
+  std::vector<double> schwarz;                   // per molecule ns x ns, at ps_off
   int npairs = 0;
-  std::vector<int> cls_beg;            // 16
-  std::vector<Pair> pairs;             // kept pairs (host copy)
+  std::vector<int> cls_beg;                      // [16] first kept pair of each pair class
+  std::vector<int> cm_beg;                       // [15 (nmol+1)] first kept pair of each (class, molecule)
+  std::vector<char> possible;                    // [120] class can hold quartets (both pair classes in one molecule)
   // device
   Pair *d_pairs = nullptr;
   PrimPair *d_pp = nullptr;
   double *d_pairI = nullptr;
   int *d_pair_cls = nullptr, *d_pair_sa = nullptr, *d_pair_sb = nullptr, *d_cls_beg = nullptr;
+  int *d_pair_mol = nullptr, *d_cm_beg = nullptr;
   int *d_l = nullptr, *d_pure = nullptr, *d_cart_off = nullptr, *d_ao_off = nullptr;
   int *d_cart2shell = nullptr, *d_ao2shell = nullptr;
+  int *d_sbase = nullptr, *d_cbase = nullptr, *d_abase = nullptr, *d_mnc = nullptr;
+  long long *d_mc_off = nullptr, *d_mf_off = nullptr, *d_ps_off = nullptr;
   double *d_tsph = nullptr;
   double *d_Dc = nullptr, *d_Jc = nullptr, *d_Kc = nullptr, *d_Pblk = nullptr, *d_gmax = nullptr;
   unsigned long long *d_cap = nullptr, *d_nprim = nullptr;
   int *d_count = nullptr, *d_pair_npp = nullptr;
   int *d_pair_ca = nullptr, *d_pair_cb = nullptr, *d_pair_la = nullptr, *d_pair_lb = nullptr;
   int *d_segoff = nullptr, *d_segcnt = nullptr, *d_next = nullptr;
-  long long *d_class_off = nullptr, *d_jp_off = nullptr;
+  long long *d_class_off = nullptr, *d_jp_off = nullptr, *d_room = nullptr;
+  int *d_overflow = nullptr;
+  int *h_overflow = nullptr;                     // pinned host copy of the overflow flag
   double *d_Jpair = nullptr;
   long long jp_total = 0;
-  std::vector<long long> jp_off;       // 15
-  int flags = 0;
+  std::vector<long long> jp_off;                 // [15]
   hipStream_t last_stream = nullptr;
-  std::vector<hipEvent_t> events;      // profiling: 2 per launch slot (15 fused + 120 per class) + prep + tail
-  std::vector<int> launched;           // launch slots used by the last execute
+  std::vector<hipEvent_t> events;      // 2 per launch slot (15 x 3 fused + 120 per class) + prep + tail
+  std::vector<int> launched;           // launch slots used by the last eager execute
+  std::vector<int> grid;               // per launch slot: workgroups (0 = default)
+  bool tuned = false;
   int *d_kets = nullptr;
   long long list_capacity = 0;
   double *d_scratch = nullptr;
@@ -179,45 +190,74 @@ struct jk_plan {
   ShellInfo S{};
   jk_stats_t stats{};
   int device = 0;
+  // graph replay
+  hipStream_t rec_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const double *gD = nullptr;
+  double *gJ = nullptr, *gK = nullptr;
+  bool graph_stale = false;
+  long long replays = 0;
+  int rerecords = 0;
+};
+
+struct jk_batch {
+  jk_plan *p = nullptr;
 };
 
 namespace {
 
+void graph_free(jk_plan *p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+}
+
 void plan_free(jk_plan *p) {
+  graph_free(p);
+  if (p->rec_stream) (void)hipStreamDestroy(p->rec_stream);
+  p->rec_stream = nullptr;
+  if (p->h_overflow) (void)hipHostFree(p->h_overflow);
+  p->h_overflow = nullptr;
   dfree(p->d_pairs); dfree(p->d_pp); dfree(p->d_pairI); dfree(p->d_pair_cls); dfree(p->d_pair_sa);
-  dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_l); dfree(p->d_pure); dfree(p->d_cart_off);
-  dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell); dfree(p->d_tsph); dfree(p->d_Dc);
+  dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_pair_mol); dfree(p->d_cm_beg); dfree(p->d_l);
+  dfree(p->d_pure); dfree(p->d_cart_off); dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell);
+  dfree(p->d_sbase); dfree(p->d_cbase); dfree(p->d_abase); dfree(p->d_mnc); dfree(p->d_mc_off);
+  dfree(p->d_mf_off); dfree(p->d_ps_off); dfree(p->d_tsph); dfree(p->d_Dc);
   dfree(p->d_Jc); dfree(p->d_Kc); dfree(p->d_Pblk); dfree(p->d_gmax); dfree(p->d_cap); dfree(p->d_count);
   dfree(p->d_kets); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
   dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
   dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair);
+  dfree(p->d_room); dfree(p->d_overflow);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
 }
 
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
-constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels
+constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels (default)
 constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
 constexpr int NFUSED = NPAIRCLASS * NTIERS;     // launch slots of the fused kernels
+constexpr int NSLOT = NFUSED + NQCLASS;
+const int TUNE_GRIDS[] = {256, 512, 1024, 2048};   // candidates of the grid tuner
 
 int ensure_scratch(jk_plan *p, long long doubles) {
   if (doubles <= p->scratch_doubles) return JK_OK;
   dfree(p->d_scratch);
   p->scratch_doubles = 0;
+  p->graph_stale = true;
   int rc = dalloc(&p->d_scratch, (size_t)doubles);
   if (rc) return rc;
   p->scratch_doubles = doubles;
   return JK_OK;
 }
 
-// Build primitive pairs and pair records for every shell pair i >= j (canonical order
-// l_a >= l_b inside the pair).
-void build_pairs(const jk_basis_t *B, const double *coords, const std::vector<int> &cart_off,
+// Primitive pairs and pair records of every shell pair i >= j of one molecule (canonical
+// order l_a >= l_b inside the pair). s0: first shell of the molecule in the batch; shell
+// indices of the records are batch-wide, Cartesian offsets are inside the molecule.
+void build_pairs(const jk_basis_t *B, const double *coords, const int *cart_off, int s0, int mol,
                  std::vector<Pair> &pairs, std::vector<PrimPair> &pps) {
   const int ns = B->nshell;
-  pairs.clear();
-  pps.clear();
-  pairs.reserve((size_t)ns * (ns + 1) / 2);
   for (int i = 0; i < ns; ++i)
     for (int j = 0; j <= i; ++j) {
       int a = i, b = j;
@@ -230,12 +270,12 @@ void build_pairs(const jk_basis_t *B, const double *coords, const std::vector<in
         P.B[d] = Bc[d];
         ab2 += (A[d] - Bc[d]) * (A[d] - Bc[d]);
       }
-      P.sa = a; P.sb = b;
+      P.sa = s0 + a; P.sb = s0 + b;
       P.ca = cart_off[a]; P.cb = cart_off[b];
       P.pp_off = (int)pps.size();
       P.npp = B->nprim[a] * B->nprim[b];
       P.cls = pair_class(B->l[a], B->l[b]);
-      P.I = 0.f;
+      P.mol = mol;
       for (int ka = 0; ka < B->nprim[a]; ++ka)
         for (int kb = 0; kb < B->nprim[b]; ++kb) {
           const double ea = B->exps[B->prim_off[a] + ka], eb = B->exps[B->prim_off[b] + kb];
@@ -251,7 +291,6 @@ void build_pairs(const jk_basis_t *B, const double *coords, const std::vector<in
       pairs.push_back(P);
     }
 }
-
 int validate(const jk_basis_t *B, const double *coords, int natom) {
   if (!B) return fail(JK_EINVAL, "basis is NULL");
   if (!coords) return fail(JK_EINVAL, "coords is NULL");
@@ -298,33 +337,593 @@ int launch_mode_list(jk_plan *p, int qc, int mode, const int2 *list, int count, 
   m.out = out;
   m.scratch = p->d_scratch;
   m.scratch_per_wg = ci.scratch_per_wg;
-  m.nc = p->nc;
+  m.nc = p->nc;   // ERI tensor: single-molecule plans only
   HIPCHK(ci.launch_mode[mode](m, grid, st));
   return JK_OK;
 }
 
-}  // namespace
 
-extern "C" {
-
-const char *jk_last_error(void) { return g_err.c_str(); }
-
-int jk_sph_matrix(int l, double *out) {
-  if (!out) return fail(JK_EINVAL, "out is NULL");
-  if (l < 2 || l > LMAX) return fail(JK_EINVAL, "l must be in 2..4 (got %d)", l);
-  solid_harmonics(l, out);
+int parse_opts(const jk_opts_t *opts, jk_plan *p) {
+  p->tau = 1e-12;
+  p->precision = JK_FP64;
+  p->fp32_cutoff = 1e-6;
+  p->flags = 0;
+  if (!opts) return JK_OK;
+  if (!(opts->thresh >= 0.0) || !std::isfinite(opts->thresh)) return fail(JK_EINVAL, "thresh must be finite and >= 0");
+  if (opts->precision != JK_FP64 && opts->precision != JK_MIXED)
+    return fail(JK_EINVAL, "unknown precision %d", opts->precision);
+  if (opts->precision == JK_MIXED) return fail(JK_EUNSUPPORTED, "mixed precision is not built yet");
+  if (opts->flags & ~(JK_FLAG_PROFILE | JK_FLAG_GRAPH | JK_FLAG_TUNE)) return fail(JK_EINVAL, "unknown flags 0x%x", opts->flags);
+  p->tau = opts->thresh;
+  p->precision = opts->precision;
+  p->fp32_cutoff = opts->fp32_cutoff;
+  p->flags = opts->flags;
+  if (opts->tune_cache) p->tune_cache = opts->tune_cache;
   return JK_OK;
 }
 
-int jk_plan_sizes(const jk_plan_t *plan, int *nao, int *nao_cart) {
-  if (!plan) return fail(JK_EINVAL, "plan is NULL");
-  if (nao) *nao = plan->nao;
-  if (nao_cart) *nao_cart = plan->nc;
+// Plan of nmol molecules (a single-molecule plan is the batch of one).
+int plan_create(int nmol, const jk_basis_t *const *Bs, const double *const *coords, const int *natom,
+                const jk_opts_t *opts, jk_plan **out) {
+  *out = nullptr;
+  if (nmol <= 0) return fail(JK_EINVAL, "nmol must be positive (got %d)", nmol);
+  if (!Bs || !coords || !natom) return fail(JK_EINVAL, "basis, coords and natom arrays must not be NULL");
+  for (int m = 0; m < nmol; ++m) {
+    int rc = validate(Bs[m], coords[m], natom[m]);
+    if (rc) {
+      if (nmol > 1) g_err = "molecule " + std::to_string(m) + ": " + g_err;
+      return rc;
+    }
+  }
+  jk_plan tmp;
+  int rc = parse_opts(opts, &tmp);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(JK_ENODEV, "no HIP device");
+  ensure_classes();
+  const auto t0 = std::chrono::steady_clock::now();
+
+  jk_plan *p = new jk_plan();
+  p->tau = tmp.tau;
+  p->precision = tmp.precision;
+  p->fp32_cutoff = tmp.fp32_cutoff;
+  p->flags = tmp.flags;
+  p->tune_cache = tmp.tune_cache;
+  p->nmol = nmol;
+  (void)hipGetDevice(&p->device);
+  auto cleanup = [&](int code) {
+    plan_free(p);
+    delete p;
+    return code;
+  };
+
+  // per-molecule layout
+  p->sbase.assign(nmol + 1, 0); p->cbase.assign(nmol + 1, 0); p->abase.assign(nmol + 1, 0);
+  p->mc_off.assign(nmol + 1, 0); p->mf_off.assign(nmol + 1, 0); p->ps_off.assign(nmol + 1, 0);
+  p->mnc.assign(nmol, 0);
+  for (int m = 0; m < nmol; ++m) {
+    const jk_basis_t *B = Bs[m];
+    int nc = 0, na = 0;
+    for (int s = 0; s < B->nshell; ++s) {
+      const int l = B->l[s];
+      p->l.push_back(l);
+      p->pure.push_back(B->pure[s]);
+      p->cart_off.push_back(nc);
+      p->ao_off.push_back(na);
+      nc += ncart(l);
+      na += (B->pure[s] && l >= 2) ? 2 * l + 1 : ncart(l);
+    }
+    p->sbase[m + 1] = p->sbase[m] + B->nshell;
+    p->cbase[m + 1] = p->cbase[m] + nc;
+    p->abase[m + 1] = p->abase[m] + na;
+    p->mnc[m] = nc;
+    p->nc_max = std::max(p->nc_max, nc);
+    p->mc_off[m + 1] = p->mc_off[m] + (long long)nc * nc;
+    p->mf_off[m + 1] = p->mf_off[m] + (long long)na * na;
+    p->ps_off[m + 1] = p->ps_off[m] + (long long)B->nshell * B->nshell;
+  }
+  const int ns = p->nshell = p->sbase[nmol];
+  p->nc = p->cbase[nmol];
+  p->nao = p->abase[nmol];
+
+  // shell tables
+  std::vector<int> c2s(p->nc), a2s(p->nao);
+  for (int m = 0; m < nmol; ++m)
+    for (int s = p->sbase[m]; s < p->sbase[m + 1]; ++s) {
+      const int l = p->l[s];
+      const int nf = (p->pure[s] && l >= 2) ? 2 * l + 1 : ncart(l);
+      for (int k = 0; k < ncart(l); ++k) c2s[p->cbase[m] + p->cart_off[s] + k] = s;
+      for (int k = 0; k < nf; ++k) a2s[p->abase[m] + p->ao_off[s] + k] = s;
+    }
+  std::vector<double> tsph(5 * 6 + 7 * 10 + 9 * 15);
+  solid_harmonics(2, tsph.data());
+  solid_harmonics(3, tsph.data() + 30);
+  solid_harmonics(4, tsph.data() + 100);
+  if ((rc = dupload(&p->d_l, p->l)) || (rc = dupload(&p->d_pure, p->pure)) ||
+      (rc = dupload(&p->d_cart_off, p->cart_off)) || (rc = dupload(&p->d_ao_off, p->ao_off)) ||
+      (rc = dupload(&p->d_cart2shell, c2s)) || (rc = dupload(&p->d_ao2shell, a2s)) ||
+      (rc = dupload(&p->d_tsph, tsph)) || (rc = dupload(&p->d_sbase, p->sbase)) ||
+      (rc = dupload(&p->d_cbase, p->cbase)) || (rc = dupload(&p->d_abase, p->abase)) ||
+      (rc = dupload(&p->d_mnc, p->mnc)) || (rc = dupload(&p->d_mc_off, p->mc_off)) ||
+      (rc = dupload(&p->d_mf_off, p->mf_off)) || (rc = dupload(&p->d_ps_off, p->ps_off)))
+    return cleanup(rc);
+  ShellInfo &S = p->S;
+  S.l = p->d_l; S.pure = p->d_pure; S.cart_off = p->d_cart_off; S.ao_off = p->d_ao_off;
+  S.cart2shell = p->d_cart2shell; S.ao2shell = p->d_ao2shell; S.tsph = p->d_tsph;
+  S.mc_off = p->d_mc_off; S.mf_off = p->d_mf_off; S.ps_off = p->d_ps_off;
+  S.cbase = p->d_cbase; S.abase = p->d_abase; S.sbase = p->d_sbase;
+  S.toff[0] = S.toff[1] = 0; S.toff[2] = 0; S.toff[3] = 30; S.toff[4] = 100;
+  S.nmol = nmol;
+  S.nc2_tot = p->mc_off[nmol]; S.nf2_tot = p->mf_off[nmol]; S.ns2_tot = p->ps_off[nmol];
+
+  // all shell pairs of every molecule
+  std::vector<Pair> all;
+  std::vector<PrimPair> pps;
+  for (int m = 0; m < nmol; ++m)
+    build_pairs(Bs[m], coords[m], p->cart_off.data() + p->sbase[m], p->sbase[m], m, all, pps);
+  const int nall = (int)all.size();
+  if (pps.size() > 0x7fffffffULL) return cleanup(fail(JK_EUNSUPPORTED, "more than 2^31 primitive pairs"));
+  if ((rc = dupload(&p->d_pairs, all)) || (rc = dupload(&p->d_pp, pps))) return cleanup(rc);
+
+  // Cauchy-Schwarz factors: the diagonal quartets (ab|ab), one class launch per pair class
+  std::vector<double> smax(nall);
+  {
+    double *d_smax = nullptr;
+    int2 *d_diag = nullptr;
+    if ((rc = dalloc(&d_smax, nall)) || (rc = dalloc(&d_diag, nall))) {
+      dfree(d_smax);
+      return cleanup(rc);
+    }
+    std::vector<int2> diag(nall);
+    std::vector<int> cnt(NPAIRCLASS, 0), beg(NPAIRCLASS + 1, 0);
+    for (int i = 0; i < nall; ++i) cnt[all[i].cls]++;
+    for (int c = 0; c < NPAIRCLASS; ++c) beg[c + 1] = beg[c] + cnt[c];
+    std::vector<int> fillp(beg.begin(), beg.end() - 1);
+    for (int i = 0; i < nall; ++i) diag[fillp[all[i].cls]++] = make_int2(i, i);
+    hipError_t e = hipMemcpy(d_diag, diag.data(), sizeof(int2) * nall, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_smax, 0, sizeof(double) * nall);
+    if (e != hipSuccess) {
+      dfree(d_smax); dfree(d_diag);
+      return cleanup(fail(JK_EDEVICE, "Schwarz setup: %s", hipGetErrorString(e)));
+    }
+    for (int c = 0; c < NPAIRCLASS && !rc; ++c) {
+      if (!cnt[c]) continue;
+      rc = launch_mode_list(p, qclass_index(c, c), MODE_SCHWARZ, d_diag + beg[c], cnt[c], d_smax, 0);
+    }
+    if (!rc) {
+      e = hipDeviceSynchronize();
+      if (e == hipSuccess) e = hipMemcpy(smax.data(), d_smax, sizeof(double) * nall, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) rc = fail(JK_EDEVICE, "Schwarz pass: %s", hipGetErrorString(e));
+    }
+    dfree(d_smax); dfree(d_diag);
+    if (rc) return cleanup(rc);
+  }
+  p->schwarz.assign((size_t)p->ps_off[nmol], 0.0);
+  for (int i = 0; i < nall; ++i) {
+    const int m = all[i].mol;
+    const int nsm = p->sbase[m + 1] - p->sbase[m];
+    const int a = all[i].sa - p->sbase[m], b = all[i].sb - p->sbase[m];
+    const double I = std::sqrt(smax[i]);
+    p->schwarz[(size_t)p->ps_off[m] + (size_t)a * nsm + b] = I;
+    p->schwarz[(size_t)p->ps_off[m] + (size_t)b * nsm + a] = I;
+  }
+
+  // keep pairs with I > tau, sorted by class, then molecule, then I descending (stable)
+  std::vector<int> order;
+  order.reserve(nall);
+  for (int i = 0; i < nall; ++i)
+    if (std::sqrt(smax[i]) > p->tau) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (all[x].cls != all[y].cls) return all[x].cls < all[y].cls;
+    if (all[x].mol != all[y].mol) return all[x].mol < all[y].mol;
+    return smax[x] > smax[y];
+  });
+  p->npairs = (int)order.size();
+  std::vector<Pair> kept(p->npairs);
+  std::vector<PrimPair> kpp;
+  std::vector<double> kI(p->npairs);
+  std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs), knpp(p->npairs), kca(p->npairs),
+      kcb(p->npairs), kla(p->npairs), klb(p->npairs), kmol(p->npairs);
+  p->cls_beg.assign(NPAIRCLASS + 1, 0);
+  p->cm_beg.assign((size_t)NPAIRCLASS * (nmol + 1), 0);
+  std::vector<long long> cmcnt((size_t)NPAIRCLASS * nmol, 0);
+  for (int k = 0; k < p->npairs; ++k) {
+    Pair P = all[order[k]];
+    const int off = (int)kpp.size();
+    for (int q = 0; q < P.npp; ++q) kpp.push_back(pps[P.pp_off + q]);
+    P.pp_off = off;
+    kept[k] = P;
+    kI[k] = std::sqrt(smax[order[k]]);
+    kcls[k] = P.cls; ksa[k] = P.sa; ksb[k] = P.sb; knpp[k] = P.npp;
+    kca[k] = P.ca; kcb[k] = P.cb; kla[k] = p->l[P.sa]; klb[k] = p->l[P.sb]; kmol[k] = P.mol;
+    p->cls_beg[P.cls + 1]++;
+    cmcnt[(size_t)P.cls * nmol + P.mol]++;
+  }
+  for (int c = 0; c < NPAIRCLASS; ++c) p->cls_beg[c + 1] += p->cls_beg[c];
+  for (int c = 0; c < NPAIRCLASS; ++c) {
+    int *cm = p->cm_beg.data() + (size_t)c * (nmol + 1);
+    cm[0] = p->cls_beg[c];
+    for (int m = 0; m < nmol; ++m) cm[m + 1] = cm[m] + (int)cmcnt[(size_t)c * nmol + m];
+  }
+  p->possible.assign(NQCLASS, 0);
+  for (int cb = 0; cb < NPAIRCLASS; ++cb)
+    for (int ck = 0; ck <= cb; ++ck)
+      for (int m = 0; m < nmol; ++m)
+        if (cmcnt[(size_t)cb * nmol + m] && cmcnt[(size_t)ck * nmol + m]) {
+          p->possible[qclass_index(cb, ck)] = 1;
+          break;
+        }
+  dfree(p->d_pairs);
+  dfree(p->d_pp);
+  if ((rc = dupload(&p->d_pairs, kept)) || (rc = dupload(&p->d_pp, kpp)) || (rc = dupload(&p->d_pairI, kI)) ||
+      (rc = dupload(&p->d_pair_cls, kcls)) || (rc = dupload(&p->d_pair_sa, ksa)) ||
+      (rc = dupload(&p->d_pair_sb, ksb)) || (rc = dupload(&p->d_cls_beg, p->cls_beg)) ||
+      (rc = dupload(&p->d_pair_npp, knpp)) || (rc = dupload(&p->d_pair_ca, kca)) ||
+      (rc = dupload(&p->d_pair_cb, kcb)) || (rc = dupload(&p->d_pair_la, kla)) ||
+      (rc = dupload(&p->d_pair_lb, klb)) || (rc = dupload(&p->d_pair_mol, kmol)) ||
+      (rc = dupload(&p->d_cm_beg, p->cm_beg)))
+    return cleanup(rc);
+  // Coulomb pair buffer: per pair class, element-major over the pairs of the class
+  p->jp_off.assign(NPAIRCLASS, 0);
+  long long jt = 0;
+  for (int c = 0; c < NPAIRCLASS; ++c) {
+    p->jp_off[c] = jt;
+    jt += (long long)(p->cls_beg[c + 1] - p->cls_beg[c]) * ncart(pc_la(c)) * ncart(pc_lb(c));
+  }
+  p->jp_total = jt;
+  if ((rc = dupload(&p->d_jp_off, p->jp_off)) || (rc = dalloc(&p->d_Jpair, (size_t)std::max(1LL, jt))) ||
+      (rc = dalloc(&p->d_segoff, (size_t)p->npairs * NPAIRCLASS)) ||
+      (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)))
+    return cleanup(rc);
+
+  // build workspace
+  const size_t nc2 = (size_t)p->mc_off[nmol];
+  if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
+      (rc = dalloc(&p->d_Pblk, (size_t)p->ps_off[nmol])) || (rc = dalloc(&p->d_gmax, 1)) ||
+      (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
+      (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
+      (rc = dalloc(&p->d_room, NQCLASS)) || (rc = dalloc(&p->d_overflow, 1)) ||
+      (rc = dalloc(&p->d_next, NSLOT)))
+    return cleanup(rc);
+  if (hipHostMalloc((void **)&p->h_overflow, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    p->h_overflow = nullptr;
+    return cleanup(fail(JK_ENOMEM, "hipHostMalloc of the overflow flag failed"));
+  }
+  *p->h_overflow = 0;
+  p->grid.assign(NSLOT, 0);
+  if (p->flags & (JK_FLAG_PROFILE | JK_FLAG_TUNE)) {
+    p->events.resize(2 * NSLOT + 4, nullptr);
+    for (auto &e : p->events)
+      if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(JK_EDEVICE, "hipEventCreate failed"));
+  }
+  if (p->flags & JK_FLAG_GRAPH) {
+    if (hipStreamCreateWithFlags(&p->rec_stream, hipStreamNonBlocking) != hipSuccess) {
+      p->rec_stream = nullptr;
+      return cleanup(fail(JK_EDEVICE, "hipStreamCreate failed"));
+    }
+  }
+  HIPCHK(hipDeviceSynchronize());
+  p->stats.npairs_kept = p->npairs;
+  p->stats.nao = p->nao;
+  p->stats.nao_cart = p->nc;
+  p->stats.nshell = ns;
+  p->stats.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = p;
   return JK_OK;
 }
 
-int jk_stats(const jk_plan_t *plan, jk_stats_t *out) {
-  if (!plan || !out) return fail(JK_EINVAL, "NULL argument");
+// ------------------------------------------------------------------ the integral launches
+struct Launch {
+  int slot;          // profile/work-counter slot: cb * NTIERS + tier (fused) or NFUSED + qc
+  int cb;            // bra pair class
+  int tier;          // fused: register tier; per class: -1
+  int qc;            // per class: quartet class; fused: -1
+  size_t lds;        // dynamic LDS bytes
+  long long scratch_per_wg;
+};
+
+// Launches of one build. active[qc]: the class has work (eager) or may have work (recording).
+void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &out) {
+  out.clear();
+  for (int cb = 0; cb < NPAIRCLASS; ++cb) {
+    if (p->cls_beg[cb + 1] == p->cls_beg[cb]) continue;
+    const BraInfo &bi = g_bras[cb];
+    const int na = ncart(bi.la), nbb = ncart(bi.lb);
+    for (int tier = 0; tier < NTIERS; ++tier) {
+      bool any = false;
+      for (int ck = 0; ck <= cb; ++ck) any = any || (((bi.tier_mask[tier] >> ck) & 1) && active[qclass_index(cb, ck)]);
+      if (!any) continue;
+      const size_t fused_lds =
+          ((size_t)(na + nbb) * p->nc_max + ((na * nbb + 1) & ~1)) * 8 + (size_t)bi.pool_bytes[tier];
+      if (bi.fusable[tier] && fused_lds <= FUSED_LDS_MAX) {
+        out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, fused_lds, bi.scratch_per_wg[tier]});
+      } else {
+        for (int ck = 0; ck <= cb; ++ck) {
+          const int qc = qclass_index(cb, ck);
+          if (!((bi.tier_mask[tier] >> ck) & 1) || !active[qc]) continue;
+          const ClassInfo &ci = g_classes[qc];
+          const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
+          out.push_back(Launch{NFUSED + qc, cb, -1, qc, lds, ci.scratch_per_wg});
+        }
+      }
+    }
+  }
+}
+
+int launch_grid(const jk_plan *p, const Launch &L) {
+  const int nb = p->cls_beg[L.cb + 1] - p->cls_beg[L.cb];
+  const int g = p->grid[L.slot] > 0 ? p->grid[L.slot] : GRID_TEAM_MAX;
+  return std::max(1, std::min(nb, g));
+}
+
+// Enqueue one build on `st`. Eager (record = false): reads the class capacities back to size
+// the work list, launches the classes that have work, records profile events. Recording
+// (record = true): no host round trip, the list keeps its size (overflow flag instead),
+// every class that may have work is launched; nothing here allocates.
+int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t st, bool record) {
+  const size_t nc2 = (size_t)p->mc_off[p->nmol];
+  const bool prof = !record && !p->events.empty();
+  if (!record) {
+    p->last_stream = st;
+    p->launched.clear();
+  }
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT], st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jc, (long long)nc2, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Kc, (long long)nc2, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jpair, p->jp_total, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_nprim, NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
+  HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
+  HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
+  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+  HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+
+  ScreenArgs A{};
+  A.pairI = p->d_pairI;
+  A.pair_cls = p->d_pair_cls;
+  A.pair_sa = p->d_pair_sa;
+  A.pair_sb = p->d_pair_sb;
+  A.pair_npp = p->d_pair_npp;
+  A.pair_mol = p->d_pair_mol;
+  A.cm_beg = p->d_cm_beg;
+  A.Pblk = p->d_Pblk;
+  A.ps_off = p->d_ps_off;
+  A.sbase = p->d_sbase;
+  A.gmax = p->d_gmax;
+  A.cap = p->d_cap;
+  A.segoff = p->d_segoff;
+  A.segcnt = p->d_segcnt;
+  A.count = p->d_count;
+  A.nprim = p->d_nprim;
+  A.class_off = p->d_class_off;
+  A.room = p->d_room;
+  A.tau = p->tau;
+  A.npairs = p->npairs;
+  A.nmol = p->nmol;
+  if (p->npairs > 0) HIPCHK(launch_capacity(A, st));
+  bool active[NQCLASS];
+  if (!record) {
+    unsigned long long cap[NQCLASS];
+    HIPCHK(hipMemcpyAsync(cap, p->d_cap, sizeof(cap), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    long long total = 0;
+    for (int c = 0; c < NQCLASS; ++c) {
+      if (cap[c] > 0x7fffffffULL) return fail(JK_EUNSUPPORTED, "class %d: %llu candidate quartets exceed 2^31", c, cap[c]);
+      total += (long long)cap[c];
+      active[c] = cap[c] > 0;
+    }
+    if (total > p->list_capacity || !p->d_kets) {
+      // graph replays reuse this list: leave room for densities that keep a few more quartets
+      const long long want = (p->flags & JK_FLAG_GRAPH) ? total + total / 4 + 4096 : total;
+      dfree(p->d_kets);
+      p->list_capacity = 0;
+      p->graph_stale = true;
+      int rc = dalloc(&p->d_kets, (size_t)want + 1);
+      if (rc) return rc;
+      p->list_capacity = want;
+    }
+    p->stats.candidate_quartets = total;
+  } else {
+    for (int c = 0; c < NQCLASS; ++c) active[c] = p->possible[c] != 0;
+  }
+  HIPCHK(launch_class_off(p->d_cap, p->d_class_off, p->d_room, p->list_capacity, p->d_overflow, st));
+  A.kets = p->d_kets;
+  if (p->npairs > 0) HIPCHK(launch_screen(A, st));
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 1], st));
+
+  std::vector<Launch> launches;
+  plan_launches(p, active, launches);
+  if (!record) {
+    long long need = 0;
+    for (const Launch &L : launches) need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
+    if (need > 0) {
+      int rc = ensure_scratch(p, need);
+      if (rc) return rc;
+    }
+  }
+  JKArgs J_{};
+  J_.pairs = p->d_pairs;
+  J_.pp = p->d_pp;
+  J_.kets = p->d_kets;
+  J_.class_off = p->d_class_off;
+  J_.segoff = p->d_segoff;
+  J_.segcnt = p->d_segcnt;
+  J_.Dc = p->d_Dc;
+  J_.Kc = p->d_Kc;
+  J_.mbase = p->d_mc_off;
+  J_.mnc = p->d_mnc;
+  J_.Jpair = p->d_Jpair;
+  J_.jp_off = p->d_jp_off;
+  J_.cls_beg = p->d_cls_beg;
+  J_.nc_max = p->nc_max;
+  J_.scratch = p->d_scratch;
+  for (const Launch &L : launches) {
+    const int grid = launch_grid(p, L);
+    if (L.scratch_per_wg * (long long)grid > p->scratch_doubles)
+      return fail(JK_EDEVICE, "internal: team scratch not sized for launch slot %d", L.slot);
+    J_.bra_beg = p->cls_beg[L.cb];
+    J_.bra_end = p->cls_beg[L.cb + 1];
+    J_.scratch_per_wg = L.scratch_per_wg;
+    J_.next = p->d_next + L.slot;
+    if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot], st));
+    if (L.qc < 0)
+      HIPCHK(g_bras[L.cb].launch_bra[L.tier](J_, grid, L.lds, st));
+    else
+      HIPCHK(g_classes[L.qc].launch_cls(J_, grid, L.lds, st));
+    if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot + 1], st));
+    if (!record) p->launched.push_back(L.slot);
+  }
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 2], st));
+  FoldArgs F{};
+  F.pair_cls = p->d_pair_cls;
+  F.pair_ca = p->d_pair_ca;
+  F.pair_cb = p->d_pair_cb;
+  F.pair_la = p->d_pair_la;
+  F.pair_lb = p->d_pair_lb;
+  F.pair_mol = p->d_pair_mol;
+  F.cls_beg = p->d_cls_beg;
+  F.jp_off = p->d_jp_off;
+  F.mc_off = p->d_mc_off;
+  F.cbase = p->d_cbase;
+  F.Jpair = p->d_Jpair;
+  F.Jc = p->d_Jc;
+  F.npairs = p->npairs;
+  if (p->npairs > 0) HIPCHK(launch_fold(F, st));
+  HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, J, K, st));
+  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 3], st));
+  return JK_OK;
+}
+
+// Record the build into a HIP graph (on the plan's own stream: the caller's may be the
+// legacy default stream, which cannot be recorded). The list and scratch buffers must
+// already have the sizes the replay will use.
+int record_graph(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
+  HIPCHK(hipStreamSynchronize(st));
+  bool active[NQCLASS];
+  for (int c = 0; c < NQCLASS; ++c) active[c] = p->possible[c] != 0;
+  std::vector<Launch> launches;
+  plan_launches(p, active, launches);
+  long long need = 0;
+  for (const Launch &L : launches) need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
+  int rc = ensure_scratch(p, need);
+  if (rc) return rc;
+  graph_free(p);
+  HIPCHK(hipStreamBeginCapture(p->rec_stream, hipStreamCaptureModeThreadLocal));
+  rc = enqueue_build(p, D, J, K, p->rec_stream, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->rec_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(JK_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  p->graph = g;
+  const hipError_t e2 = hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    p->gexec = nullptr;
+    graph_free(p);
+    return fail(JK_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  }
+  p->gD = D;
+  p->gJ = J;
+  p->gK = K;
+  p->graph_stale = false;
+  return JK_OK;
+}
+
+// ------------------------------------------------------------------ grid tuner
+std::string slot_name(int slot) {
+  char buf[64];
+  if (slot < NFUSED) {
+    const BraInfo &bi = g_bras[slot / NTIERS];
+    snprintf(buf, sizeof(buf), "k_bra<%d,%d,%d>", bi.la, bi.lb, slot % NTIERS);
+  } else {
+    const ClassInfo &ci = g_classes[slot - NFUSED];
+    snprintf(buf, sizeof(buf), "k_cls<%d,%d,%d,%d>", ci.la, ci.lb, ci.lc, ci.ld);
+  }
+  return buf;
+}
+
+bool load_tune_cache(jk_plan *p) {
+  if (p->tune_cache.empty()) return false;
+  FILE *f = fopen(p->tune_cache.c_str(), "r");
+  if (!f) return false;
+  char name[64];
+  int g = 0, n = 0;
+  while (fscanf(f, "%63s %d", name, &g) == 2) {
+    for (int s = 0; s < NSLOT; ++s)
+      if (slot_name(s) == name && g > 0 && g <= 65536) {
+        p->grid[s] = g;
+        ++n;
+      }
+  }
+  fclose(f);
+  return n > 0;
+}
+
+void save_tune_cache(const jk_plan *p) {
+  if (p->tune_cache.empty()) return;
+  FILE *f = fopen(p->tune_cache.c_str(), "w");
+  if (!f) return;
+  for (int s = 0; s < NSLOT; ++s)
+    if (p->grid[s] > 0) fprintf(f, "%s %d\n", slot_name(s).c_str(), p->grid[s]);
+  fclose(f);
+}
+
+// Time every launch slot at each candidate workgroup count (one full build per candidate,
+// per-launch HIP events) and keep the fastest count per slot.
+int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
+  std::vector<float> best(NSLOT, 1e30f);
+  std::vector<int> pick(NSLOT, 0);
+  for (int g : TUNE_GRIDS) {
+    std::fill(p->grid.begin(), p->grid.end(), g);
+    int rc = enqueue_build(p, D, J, K, st, false);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    for (int slot : p->launched) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, p->events[2 * slot], p->events[2 * slot + 1]));
+      if (ms < best[slot]) {
+        best[slot] = ms;
+        pick[slot] = g;
+      }
+    }
+  }
+  p->grid = pick;
+  save_tune_cache(p);
+  return JK_OK;
+}
+
+int plan_run(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
+  if (!D || !J || !K) return fail(JK_EINVAL, "D, J and K must be device pointers");
+  if ((p->flags & JK_FLAG_TUNE) && !p->tuned) {
+    if (!load_tune_cache(p)) {
+      int rc = tune_grids(p, D, J, K, st);
+      if (rc) return rc;
+    }
+    p->tuned = true;
+    p->graph_stale = true;
+  }
+  if (!(p->flags & JK_FLAG_GRAPH)) return enqueue_build(p, D, J, K, st, false);
+  if (p->gexec && !p->graph_stale && D == p->gD && J == p->gJ && K == p->gK) {
+    HIPCHK(hipGraphLaunch(p->gexec, st));
+    HIPCHK(hipMemcpyAsync(p->h_overflow, p->d_overflow, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    p->last_stream = st;
+    if (!*p->h_overflow) {
+      ++p->replays;
+      return JK_OK;
+    }
+    ++p->rerecords;   // the density needed a longer work list: redo eagerly, then record again
+  }
+  int rc = enqueue_build(p, D, J, K, st, false);
+  if (rc) return rc;
+  return record_graph(p, D, J, K, st);
+}
+
+int plan_stats(const jk_plan *plan, jk_stats_t *out) {
   *out = plan->stats;
   if (plan->d_count) {
     int cnt[NQCLASS];
@@ -342,15 +941,57 @@ int jk_stats(const jk_plan_t *plan, jk_stats_t *out) {
   return JK_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+const char *jk_last_error(void) { return g_err.c_str(); }
+
+int jk_rys_closed(int nroots, double T, double *u, double *w) {
+  if (!u || !w) return fail(JK_EINVAL, "NULL argument");
+  if (!(T >= 0.0) || !std::isfinite(T)) return fail(JK_EINVAL, "T must be finite and >= 0");
+  if (nroots == 1) {
+    double uu[1], ww[1];
+    rys_closed<1>(T, uu, ww);
+    u[0] = uu[0]; w[0] = ww[0];
+  } else if (nroots == 2) {
+    double uu[2], ww[2];
+    rys_closed<2>(T, uu, ww);
+    u[0] = uu[0]; u[1] = uu[1]; w[0] = ww[0]; w[1] = ww[1];
+  } else {
+    return fail(JK_EINVAL, "closed-form roots exist for 1 or 2 roots only");
+  }
+  return JK_OK;
+}
+
+int jk_sph_matrix(int l, double *out) {
+  if (!out) return fail(JK_EINVAL, "out is NULL");
+  if (l < 2 || l > LMAX) return fail(JK_EINVAL, "l must be in 2..4 (got %d)", l);
+  solid_harmonics(l, out);
+  return JK_OK;
+}
+
+int jk_plan_sizes(const jk_plan_t *plan, int *nao, int *nao_cart) {
+  if (!plan) return fail(JK_EINVAL, "plan is NULL");
+  if (nao) *nao = plan->nao;
+  if (nao_cart) *nao_cart = plan->nc;
+  return JK_OK;
+}
+
+int jk_stats(const jk_plan_t *plan, jk_stats_t *out) {
+  if (!plan || !out) return fail(JK_EINVAL, "NULL argument");
+  return plan_stats(plan, out);
+}
+
 int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries) {
   if (!p || !out || !n_entries) return fail(JK_EINVAL, "NULL argument");
   if (!(p->flags & JK_FLAG_PROFILE)) return fail(JK_EINVAL, "plan was not created with JK_FLAG_PROFILE");
+  if (p->launched.empty() && p->replays > 0) return fail(JK_EINVAL, "graph replays are not profiled");
   HIPCHK(hipStreamSynchronize(p->last_stream));
   int cnt[NQCLASS];
   unsigned long long np[NQCLASS];
   HIPCHK(hipMemcpy(cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(np, p->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
-  const int NSLOT = NFUSED + NQCLASS;
   int n = 0;
   auto push = [&](const jk_profile_t &e) {
     if (n < max_entries) out[n] = e;
@@ -415,342 +1056,12 @@ void jk_plan_destroy(jk_plan_t *plan) {
 int jk_plan_create(const jk_basis_t *B, const double *coords, int natom, const jk_opts_t *opts, jk_plan_t **out) {
   if (!out) return fail(JK_EINVAL, "out is NULL");
   *out = nullptr;
-  int rc = validate(B, coords, natom);
-  if (rc) return rc;
-  double tau = 1e-12;
-  int precision = JK_FP64;
-  double fp32_cutoff = 1e-6;
-  if (opts) {
-    tau = opts->thresh;
-    precision = opts->precision;
-    fp32_cutoff = opts->fp32_cutoff;
-    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(JK_EINVAL, "thresh must be finite and >= 0");
-    if (precision != JK_FP64 && precision != JK_MIXED) return fail(JK_EINVAL, "unknown precision %d", precision);
-    if (precision == JK_MIXED) return fail(JK_EUNSUPPORTED, "mixed precision is not built yet");
-  }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(JK_ENODEV, "no HIP device");
-  ensure_classes();
-  const auto t0 = std::chrono::steady_clock::now();
-
-  jk_plan *p = new jk_plan();
-  p->nshell = B->nshell;
-  p->natom = natom;
-  p->tau = tau;
-  p->precision = precision;
-  p->fp32_cutoff = fp32_cutoff;
-  p->flags = opts ? opts->flags : 0;
-  (void)hipGetDevice(&p->device);
-  const int ns = B->nshell;
-  p->l.assign(B->l, B->l + ns);
-  p->pure.assign(B->pure, B->pure + ns);
-  p->atom.assign(B->atom, B->atom + ns);
-  p->coords.assign(coords, coords + 3 * natom);
-  p->cart_off.resize(ns + 1);
-  p->ao_off.resize(ns + 1);
-  p->cart_off[0] = p->ao_off[0] = 0;
-  for (int s = 0; s < ns; ++s) {
-    const int l = B->l[s];
-    p->cart_off[s + 1] = p->cart_off[s] + ncart(l);
-    p->ao_off[s + 1] = p->ao_off[s] + ((B->pure[s] && l >= 2) ? 2 * l + 1 : ncart(l));
-  }
-  p->nc = p->cart_off[ns];
-  p->nao = p->ao_off[ns];
-
-  auto cleanup = [&](int code) {
-    plan_free(p);
-    delete p;
-    return code;
-  };
-
-  // shell tables
-  std::vector<int> c2s(p->nc), a2s(p->nao);
-  for (int s = 0; s < ns; ++s) {
-    for (int k = p->cart_off[s]; k < p->cart_off[s + 1]; ++k) c2s[k] = s;
-    for (int k = p->ao_off[s]; k < p->ao_off[s + 1]; ++k) a2s[k] = s;
-  }
-  std::vector<double> tsph(5 * 6 + 7 * 10 + 9 * 15);
-  solid_harmonics(2, tsph.data());
-  solid_harmonics(3, tsph.data() + 30);
-  solid_harmonics(4, tsph.data() + 100);
-  if ((rc = dupload(&p->d_l, p->l)) || (rc = dupload(&p->d_pure, p->pure)) ||
-      (rc = dupload(&p->d_cart_off, p->cart_off)) || (rc = dupload(&p->d_ao_off, p->ao_off)) ||
-      (rc = dupload(&p->d_cart2shell, c2s)) || (rc = dupload(&p->d_ao2shell, a2s)) ||
-      (rc = dupload(&p->d_tsph, tsph)))
-    return cleanup(rc);
-  p->S.l = p->d_l; p->S.pure = p->d_pure; p->S.cart_off = p->d_cart_off; p->S.ao_off = p->d_ao_off;
-  p->S.cart2shell = p->d_cart2shell; p->S.ao2shell = p->d_ao2shell; p->S.tsph = p->d_tsph;
-  p->S.toff[0] = p->S.toff[1] = 0; p->S.toff[2] = 0; p->S.toff[3] = 30; p->S.toff[4] = 100;
-  p->S.nshell = ns; p->S.nc = p->nc; p->S.nao = p->nao;
-
-  // all shell pairs
-  std::vector<Pair> all;
-  std::vector<PrimPair> pps;
-  build_pairs(B, coords, p->cart_off, all, pps);
-  const int nall = (int)all.size();
-  if ((rc = dupload(&p->d_pairs, all)) || (rc = dupload(&p->d_pp, pps))) return cleanup(rc);
-
-  // Cauchy-Schwarz factors: the diagonal quartets (ab|ab), one class launch per pair class
-  {
-    double *d_smax = nullptr;
-    int2 *d_diag = nullptr;
-    if ((rc = dalloc(&d_smax, nall)) || (rc = dalloc(&d_diag, nall))) {
-      dfree(d_smax);
-      return cleanup(rc);
-    }
-    std::vector<int2> diag(nall);
-    std::vector<int> cnt(NPAIRCLASS, 0), beg(NPAIRCLASS + 1, 0);
-    for (int i = 0; i < nall; ++i) cnt[all[i].cls]++;
-    for (int c = 0; c < NPAIRCLASS; ++c) beg[c + 1] = beg[c] + cnt[c];
-    std::vector<int> fillp(beg.begin(), beg.end() - 1);
-    for (int i = 0; i < nall; ++i) diag[fillp[all[i].cls]++] = make_int2(i, i);
-    hipError_t e = hipMemcpy(d_diag, diag.data(), sizeof(int2) * nall, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(d_smax, 0, sizeof(double) * nall);
-    if (e != hipSuccess) {
-      dfree(d_smax); dfree(d_diag);
-      return cleanup(fail(JK_EDEVICE, "Schwarz setup: %s", hipGetErrorString(e)));
-    }
-    for (int c = 0; c < NPAIRCLASS && !rc; ++c) {
-      if (!cnt[c]) continue;
-      rc = launch_mode_list(p, qclass_index(c, c), MODE_SCHWARZ, d_diag + beg[c], cnt[c], d_smax, 0);
-    }
-    std::vector<double> smax(nall);
-    if (!rc) {
-      e = hipDeviceSynchronize();
-      if (e == hipSuccess) e = hipMemcpy(smax.data(), d_smax, sizeof(double) * nall, hipMemcpyDeviceToHost);
-      if (e != hipSuccess) rc = fail(JK_EDEVICE, "Schwarz pass: %s", hipGetErrorString(e));
-    }
-    dfree(d_smax); dfree(d_diag);
-    if (rc) return cleanup(rc);
-    p->schwarz.assign((size_t)ns * ns, 0.0);
-    for (int i = 0; i < nall; ++i) {
-      const double I = std::sqrt(smax[i]);
-      p->schwarz[(size_t)all[i].sa * ns + all[i].sb] = I;
-      p->schwarz[(size_t)all[i].sb * ns + all[i].sa] = I;
-      all[i].I = (float)I;
-    }
-    // keep pairs with I > tau, sorted by class then I descending (stable)
-    std::vector<int> order;
-    order.reserve(nall);
-    for (int i = 0; i < nall; ++i)
-      if (std::sqrt(smax[i]) > tau) order.push_back(i);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-      if (all[x].cls != all[y].cls) return all[x].cls < all[y].cls;
-      return smax[x] > smax[y];
-    });
-    p->npairs = (int)order.size();
-    std::vector<Pair> kept(p->npairs);
-    std::vector<PrimPair> kpp;
-    std::vector<double> kI(p->npairs);
-    std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs), knpp(p->npairs), kca(p->npairs),
-        kcb(p->npairs), kla(p->npairs), klb(p->npairs);
-    p->cls_beg.assign(NPAIRCLASS + 1, 0);
-    for (int k = 0; k < p->npairs; ++k) {
-      Pair P = all[order[k]];
-      const int off = (int)kpp.size();
-      for (int q = 0; q < P.npp; ++q) kpp.push_back(pps[P.pp_off + q]);
-      P.pp_off = off;
-      kept[k] = P;
-      kI[k] = std::sqrt(smax[order[k]]);
-      kcls[k] = P.cls;
-      ksa[k] = P.sa;
-      ksb[k] = P.sb;
-      knpp[k] = P.npp;
-      kca[k] = P.ca;
-      kcb[k] = P.cb;
-      kla[k] = p->l[P.sa];
-      klb[k] = p->l[P.sb];
-      p->cls_beg[P.cls + 1]++;
-    }
-    for (int c = 0; c < NPAIRCLASS; ++c) p->cls_beg[c + 1] += p->cls_beg[c];
-    p->pairs = kept;
-    dfree(p->d_pairs);
-    dfree(p->d_pp);
-    if ((rc = dupload(&p->d_pairs, kept)) || (rc = dupload(&p->d_pp, kpp)) || (rc = dupload(&p->d_pairI, kI)) ||
-        (rc = dupload(&p->d_pair_cls, kcls)) || (rc = dupload(&p->d_pair_sa, ksa)) ||
-        (rc = dupload(&p->d_pair_sb, ksb)) || (rc = dupload(&p->d_cls_beg, p->cls_beg)) ||
-        (rc = dupload(&p->d_pair_npp, knpp)) || (rc = dupload(&p->d_pair_ca, kca)) ||
-        (rc = dupload(&p->d_pair_cb, kcb)) || (rc = dupload(&p->d_pair_la, kla)) || (rc = dupload(&p->d_pair_lb, klb)))
-      return cleanup(rc);
-    // Coulomb pair buffer: per pair class, element-major over the pairs of the class
-    p->jp_off.assign(NPAIRCLASS, 0);
-    long long jt = 0;
-    for (int c = 0; c < NPAIRCLASS; ++c) {
-      p->jp_off[c] = jt;
-      const int la = (int)((std::sqrt(8.0 * c + 1) - 1) / 2), lb = c - la * (la + 1) / 2;
-      jt += (long long)(p->cls_beg[c + 1] - p->cls_beg[c]) * ncart(la) * ncart(lb);
-    }
-    p->jp_total = jt;
-    if ((rc = dupload(&p->d_jp_off, p->jp_off)) || (rc = dalloc(&p->d_Jpair, (size_t)std::max(1LL, jt))) ||
-        (rc = dalloc(&p->d_segoff, (size_t)p->npairs * NPAIRCLASS)) ||
-        (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)))
-      return cleanup(rc);
-  }
-
-  // build workspace
-  const size_t nc2 = (size_t)p->nc * p->nc;
-  if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
-      (rc = dalloc(&p->d_Pblk, (size_t)ns * ns)) || (rc = dalloc(&p->d_gmax, 1)) ||
-      (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
-      (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
-      (rc = dalloc(&p->d_next, NFUSED + NQCLASS)))
-    return cleanup(rc);
-  if (p->flags & JK_FLAG_PROFILE) {
-    p->events.resize(2 * (NFUSED + NQCLASS) + 4, nullptr);
-    for (auto &e : p->events)
-      if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(JK_EDEVICE, "hipEventCreate failed"));
-  }
-  HIPCHK(hipDeviceSynchronize());
-  p->stats.npairs_kept = p->npairs;
-  p->stats.nao = p->nao;
-  p->stats.nao_cart = p->nc;
-  p->stats.nshell = ns;
-  p->stats.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  *out = p;
-  return JK_OK;
+  return plan_create(1, &B, &coords, &natom, opts, out);
 }
 
 int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *stream) {
   if (!p) return fail(JK_EINVAL, "plan is NULL");
-  if (!D || !J || !K) return fail(JK_EINVAL, "D, J and K must be device pointers");
-  hipStream_t st = (hipStream_t)stream;
-  const size_t nc2 = (size_t)p->nc * p->nc;
-  const bool prof = (p->flags & JK_FLAG_PROFILE) != 0;
-  const int NSLOT = NFUSED + NQCLASS;
-  p->last_stream = st;
-  p->launched.clear();
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT], st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jc, (long long)nc2, 0ull, st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Kc, (long long)nc2, 0ull, st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jpair, p->jp_total, 0ull, st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
-  HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
-  HIPCHK(launch_fill_u64(p->d_nprim, NQCLASS, 0ull, st));
-  HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
-  HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
-  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
-  HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
-
-  ScreenArgs A{};
-  A.pairI = p->d_pairI;
-  A.pair_cls = p->d_pair_cls;
-  A.pair_sa = p->d_pair_sa;
-  A.pair_sb = p->d_pair_sb;
-  A.pair_npp = p->d_pair_npp;
-  A.cls_beg = p->d_cls_beg;
-  A.Pblk = p->d_Pblk;
-  A.gmax = p->d_gmax;
-  A.cap = p->d_cap;
-  A.segoff = p->d_segoff;
-  A.segcnt = p->d_segcnt;
-  A.count = p->d_count;
-  A.nprim = p->d_nprim;
-  A.class_off = p->d_class_off;
-  A.tau = p->tau;
-  A.npairs = p->npairs;
-  A.nshell = p->nshell;
-  if (p->npairs > 0) HIPCHK(launch_capacity(A, st));
-  unsigned long long cap[NQCLASS];
-  HIPCHK(hipMemcpyAsync(cap, p->d_cap, sizeof(cap), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  long long off[NQCLASS], total = 0;
-  for (int c = 0; c < NQCLASS; ++c) {
-    if (cap[c] > 0x7fffffffULL) return fail(JK_EUNSUPPORTED, "class %d: %llu candidate quartets exceed 2^31", c, cap[c]);
-    off[c] = total;
-    total += (long long)cap[c];
-  }
-  if (total > p->list_capacity) {
-    dfree(p->d_kets);
-    p->list_capacity = 0;
-    int rc = dalloc(&p->d_kets, (size_t)total + 1);
-    if (rc) return rc;
-    p->list_capacity = total;
-  }
-  HIPCHK(hipMemcpyAsync(p->d_class_off, off, sizeof(off), hipMemcpyHostToDevice, st));
-  A.kets = p->d_kets;
-  if (p->npairs > 0) HIPCHK(launch_screen(A, st));
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 1], st));
-
-  JKArgs J_{};
-  J_.pairs = p->d_pairs;
-  J_.pp = p->d_pp;
-  J_.kets = p->d_kets;
-  J_.class_off = p->d_class_off;
-  J_.segoff = p->d_segoff;
-  J_.segcnt = p->d_segcnt;
-  J_.Dc = p->d_Dc;
-  J_.Kc = p->d_Kc;
-  J_.Jpair = p->d_Jpair;
-  J_.jp_off = p->d_jp_off;
-  J_.cls_beg = p->d_cls_beg;
-  J_.nc = p->nc;
-  for (int cb = 0; cb < NPAIRCLASS; ++cb) {
-    const int nb = p->cls_beg[cb + 1] - p->cls_beg[cb];
-    if (!nb) continue;
-    J_.bra_beg = p->cls_beg[cb];
-    J_.bra_end = p->cls_beg[cb + 1];
-    const BraInfo &bi = g_bras[cb];
-    const int na = ncart(bi.la), nbb = ncart(bi.lb);
-    const int grid = std::min(nb, GRID_TEAM_MAX);
-    for (int tier = 0; tier < NTIERS; ++tier) {
-      bool any = false;
-      for (int ck = 0; ck <= cb; ++ck) any = any || (((bi.tier_mask[tier] >> ck) & 1) && cap[qclass_index(cb, ck)] > 0);
-      if (!any) continue;
-      const size_t fused_lds =
-          ((size_t)(na + nbb) * p->nc + ((na * nbb + 1) & ~1)) * 8 + (size_t)bi.pool_bytes[tier];
-      if (bi.fusable[tier] && fused_lds <= FUSED_LDS_MAX) {
-        if (bi.scratch_per_wg[tier] > 0) {
-          int rc = ensure_scratch(p, bi.scratch_per_wg[tier] * (long long)grid);
-          if (rc) return rc;
-        }
-        J_.scratch = p->d_scratch;
-        J_.scratch_per_wg = bi.scratch_per_wg[tier];
-        const int slot = cb * NTIERS + tier;
-        J_.next = p->d_next + slot;
-        if (prof) HIPCHK(hipEventRecord(p->events[2 * slot], st));
-        HIPCHK(bi.launch_bra[tier](J_, grid, fused_lds, st));
-        if (prof) HIPCHK(hipEventRecord(p->events[2 * slot + 1], st));
-        p->launched.push_back(slot);
-      } else {
-        for (int ck = 0; ck <= cb; ++ck) {
-          const int qc = qclass_index(cb, ck);
-          if (!((bi.tier_mask[tier] >> ck) & 1) || !cap[qc]) continue;
-          const ClassInfo &ci = g_classes[qc];
-          if (ci.scratch_per_wg > 0) {
-            int rc = ensure_scratch(p, ci.scratch_per_wg * (long long)grid);
-            if (rc) return rc;
-          }
-          J_.scratch = p->d_scratch;
-          J_.scratch_per_wg = ci.scratch_per_wg;
-          const int slot = NFUSED + qc;
-          J_.next = p->d_next + slot;
-          const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
-          if (prof) HIPCHK(hipEventRecord(p->events[2 * slot], st));
-          HIPCHK(ci.launch_cls(J_, grid, lds, st));
-          if (prof) HIPCHK(hipEventRecord(p->events[2 * slot + 1], st));
-          p->launched.push_back(slot);
-        }
-      }
-    }
-  }
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 2], st));
-  FoldArgs F{};
-  F.pair_cls = p->d_pair_cls;
-  F.pair_ca = p->d_pair_ca;
-  F.pair_cb = p->d_pair_cb;
-  F.pair_la = p->d_pair_la;
-  F.pair_lb = p->d_pair_lb;
-  F.cls_beg = p->d_cls_beg;
-  F.jp_off = p->d_jp_off;
-  F.Jpair = p->d_Jpair;
-  F.Jc = p->d_Jc;
-  F.npairs = p->npairs;
-  F.nc = p->nc;
-  if (p->npairs > 0) HIPCHK(launch_fold(F, st));
-  HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, J, K, st));
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 3], st));
-  p->stats.candidate_quartets = total;
-  return JK_OK;
+  return plan_run(p, D, J, K, (hipStream_t)stream);
 }
 
 int jk_build(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh, double *J,
@@ -772,6 +1083,7 @@ int jk_build(const jk_basis_t *basis, const double *coords, int natom, const dou
 
 int jk_eri_tensor(jk_plan_t *p, double *eri, void *stream) {
   if (!p || !eri) return fail(JK_EINVAL, "NULL argument");
+  if (p->nmol != 1) return fail(JK_EINVAL, "the ERI tensor is defined for single-molecule plans");
   hipStream_t st = (hipStream_t)stream;
   // every (bra, ket) of kept pairs with bra class >= ket class (triangle inside a class)
   std::vector<int2> lst;
@@ -806,6 +1118,56 @@ int jk_eri_tensor(jk_plan_t *p, double *eri, void *stream) {
   }
   dfree(d_lst);
   return rc;
+}
+
+int jk_batch_create(int nmol, const jk_basis_t *const *basis, const double *const *coords, const int *natom,
+                    const jk_opts_t *opts, jk_batch_t **out) {
+  if (!out) return fail(JK_EINVAL, "out is NULL");
+  *out = nullptr;
+  jk_plan *p = nullptr;
+  int rc = plan_create(nmol, basis, coords, natom, opts, &p);
+  if (rc) return rc;
+  jk_batch *b = new jk_batch();
+  b->p = p;
+  *out = b;
+  return JK_OK;
+}
+
+int jk_batch_offsets(const jk_batch_t *b, long long *off, int *nao) {
+  if (!b || !b->p) return fail(JK_EINVAL, "batch is NULL");
+  const jk_plan *p = b->p;
+  for (int m = 0; m <= p->nmol; ++m) {
+    if (off) off[m] = p->mf_off[m];
+    if (nao && m < p->nmol) nao[m] = p->abase[m + 1] - p->abase[m];
+  }
+  return JK_OK;
+}
+
+int jk_batch_execute(jk_batch_t *b, const double *D, double *J, double *K, void *stream) {
+  if (!b || !b->p) return fail(JK_EINVAL, "batch is NULL");
+  return plan_run(b->p, D, J, K, (hipStream_t)stream);
+}
+
+int jk_batch_stats(const jk_batch_t *b, jk_stats_t *out) {
+  if (!b || !b->p || !out) return fail(JK_EINVAL, "NULL argument");
+  return plan_stats(b->p, out);
+}
+
+int jk_batch_graph_info(const jk_batch_t *b, int *recorded, long long *replays, int *rerecords) {
+  if (!b || !b->p) return fail(JK_EINVAL, "batch is NULL");
+  if (recorded) *recorded = b->p->gexec != nullptr;
+  if (replays) *replays = b->p->replays;
+  if (rerecords) *rerecords = b->p->rerecords;
+  return JK_OK;
+}
+
+void jk_batch_destroy(jk_batch_t *b) {
+  if (!b) return;
+  if (b->p) {
+    plan_free(b->p);
+    delete b->p;
+  }
+  delete b;
 }
 
 }  // extern "C"

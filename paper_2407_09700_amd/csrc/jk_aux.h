@@ -6,42 +6,56 @@
 
 namespace jk {
 
-struct ShellInfo {            // device pointers
-  const int *l, *pure, *cart_off, *ao_off;
-  const int *cart2shell, *ao2shell;
+struct ShellInfo {            // device pointers; molecules are stored one after another
+  const int *l, *pure;        // per shell (global shell index)
+  const int *cart_off, *ao_off;   // per shell, inside its molecule
+  const int *cart2shell;      // per concatenated Cartesian AO -> global shell
+  const int *ao2shell;        // per concatenated final AO -> global shell
+  const long long *mc_off;    // [nmol+1] first element of each molecule's nc_m x nc_m block
+  const long long *mf_off;    // [nmol+1] first element of each molecule's nao_m x nao_m block
+  const long long *ps_off;    // [nmol+1] first element of each molecule's shell-pair block
+  const int *cbase, *abase, *sbase;   // [nmol+1] first Cartesian AO / final AO / shell of each molecule
   const double *tsph;         // T2 | T3 | T4 row-major
   int toff[5];                // offset of T_l in tsph (l >= 2)
-  int nshell, nc, nao;
+  int nmol;
+  long long nc2_tot, nf2_tot, ns2_tot;
 };
 
 struct ScreenArgs {           // device pointers
-  const double *pairI;        // Schwarz factor per kept pair (sorted by class, then I descending)
-  const int *pair_cls, *pair_sa, *pair_sb, *pair_npp;
-  const int *cls_beg;         // [16] first pair of each pair class
-  const double *Pblk;         // nshell x nshell block maxima of |D_cart|
-  const double *gmax;         // global maximum
+  const double *pairI;        // Schwarz factor per kept pair (sorted by class, molecule, then I descending)
+  const int *pair_cls, *pair_sa, *pair_sb, *pair_npp, *pair_mol;
+  const int *cm_beg;          // [15 * (nmol+1)] first pair of each (class, molecule)
+  const double *Pblk;         // per molecule: nshell_m x nshell_m block maxima of |D_cart|
+  const long long *ps_off;    // [nmol+1] first element of each molecule's block in Pblk
+  const int *sbase;           // [nmol+1] first shell of each molecule
+  const double *gmax;         // global maximum of |D_cart|
   unsigned long long *cap;    // [120] size of each class region (k_capacity)
   int *segoff;                // [npairs * 15] segment offset in the class region (k_capacity)
   int *segcnt;                // [npairs * 15] kept kets of the segment (k_screen)
   int *count;                 // [120] kept quartets per class (k_screen)
   unsigned long long *nprim;  // [120] primitive quartets of the kept quartets (k_screen)
   const long long *class_off; // [120] first entry of each class region in kets
+  const long long *room;      // [120] entries available to each class region (k_class_off)
   int *kets;
   double tau;
-  int npairs, nshell;
+  int npairs, nmol;
 };
 
-struct FoldArgs {             // Coulomb pair buffer -> Cartesian Jt
-  const int *pair_cls, *pair_ca, *pair_cb, *pair_la, *pair_lb;
+struct FoldArgs {             // Coulomb pair buffer -> Cartesian Jt of each molecule
+  const int *pair_cls, *pair_ca, *pair_cb, *pair_la, *pair_lb, *pair_mol;
   const int *cls_beg;
   const long long *jp_off;
+  const long long *mc_off;
+  const int *cbase;
   const double *Jpair;
   double *Jc;
-  int npairs, nc;
+  int npairs;
 };
 
 hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, hipStream_t st);
 hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, double *gmax, hipStream_t st);
+hipError_t launch_class_off(const unsigned long long *cap, long long *class_off, long long *room, long long limit,
+                            int *overflow, hipStream_t st);
 hipError_t launch_capacity(const ScreenArgs &A, hipStream_t st);
 hipError_t launch_screen(const ScreenArgs &A, hipStream_t st);
 hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,

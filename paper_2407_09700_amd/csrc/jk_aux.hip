@@ -7,14 +7,27 @@
 
 namespace jk {
 
+// molecule of a flat element index, from the [nmol+1] prefix offsets (binary search)
+__device__ __forceinline__ int mol_of(const long long *off, int nmol, long long t) {
+  int lo = 0, hi = nmol - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // D_cart[a][b] = sum_{mu in shell(a), nu in shell(b)} T[mu][a] D[mu][nu] T[nu][b]
 // (T = identity for Cartesian shells): the density in the Cartesian components, so that
 // digestion in the Cartesian basis followed by J = T Jc T^T reproduces the spherical result.
 __global__ void k_dcart(ShellInfo S, const double *__restrict__ D, double *__restrict__ Dc) {
-  const long long n = (long long)S.nc * S.nc;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
-    const int a = (int)(t / S.nc), b = (int)(t % S.nc);
-    const int sa = S.cart2shell[a], sb = S.cart2shell[b];
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < S.nc2_tot;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int m = mol_of(S.mc_off, S.nmol, t);
+    const int nc = S.cbase[m + 1] - S.cbase[m], nao = S.abase[m + 1] - S.abase[m];
+    const long long r = t - S.mc_off[m];
+    const int a = (int)(r / nc), b = (int)(r % nc);
+    const int sa = S.cart2shell[S.cbase[m] + a], sb = S.cart2shell[S.cbase[m] + b];
     const int ia = a - S.cart_off[sa], ib = b - S.cart_off[sb];
     const int la = S.l[sa], lb = S.l[sb];
     const bool pa = S.pure[sa] && la >= 2, pb = S.pure[sb] && lb >= 2;
@@ -22,35 +35,40 @@ __global__ void k_dcart(ShellInfo S, const double *__restrict__ D, double *__res
     const double *Ta = pa ? S.tsph + S.toff[la] : nullptr;
     const double *Tb = pb ? S.tsph + S.toff[lb] : nullptr;
     const int na = ncart(la), nb = ncart(lb);
+    const double *Dm = D + S.mf_off[m];
     double v = 0.0;
-    for (int m = 0; m < ma; ++m) {
-      const int mu = S.ao_off[sa] + (pa ? m : ia);
-      const double ta = pa ? Ta[m * na + ia] : 1.0;
+    for (int i = 0; i < ma; ++i) {
+      const int mu = S.ao_off[sa] + (pa ? i : ia);
+      const double ta = pa ? Ta[i * na + ia] : 1.0;
       if (ta == 0.0) continue;
-      double r = 0.0;
+      double acc = 0.0;
       for (int k = 0; k < mb; ++k) {
         const int nu = S.ao_off[sb] + (pb ? k : ib);
         const double tb = pb ? Tb[k * nb + ib] : 1.0;
-        r = fma(D[(size_t)mu * S.nao + nu], tb, r);
+        acc = fma(Dm[(size_t)mu * nao + nu], tb, acc);
       }
-      v = fma(ta, r, v);
+      v = fma(ta, acc, v);
     }
     Dc[t] = v;
   }
 }
 
-// Pblk[i][j] = max |D_cart| over the block of shells i, j; *gmax = max over all blocks.
+// Pblk[i][j] = max |D_cart| over the block of shells i, j (per molecule); *gmax = overall max.
 __global__ void k_blockmax(ShellInfo S, const double *__restrict__ Dc, double *__restrict__ Pblk, double *gmax) {
-  const long long n = (long long)S.nshell * S.nshell;
   double local = 0.0;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(t / S.nshell), j = (int)(t % S.nshell);
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < S.ns2_tot;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int m = mol_of(S.ps_off, S.nmol, t);
+    const int ns = S.sbase[m + 1] - S.sbase[m], nc = S.cbase[m + 1] - S.cbase[m];
+    const long long r = t - S.ps_off[m];
+    const int i = S.sbase[m] + (int)(r / ns), j = S.sbase[m] + (int)(r % ns);
     const int na = ncart(S.l[i]), nb = ncart(S.l[j]);
-    double m = 0.0;
+    const double *Dm = Dc + S.mc_off[m];
+    double mx = 0.0;
     for (int a = 0; a < na; ++a)
-      for (int b = 0; b < nb; ++b) m = fmax(m, fabs(Dc[(size_t)(S.cart_off[i] + a) * S.nc + S.cart_off[j] + b]));
-    Pblk[t] = m;
-    local = fmax(local, m);
+      for (int b = 0; b < nb; ++b) mx = fmax(mx, fabs(Dm[(size_t)(S.cart_off[i] + a) * nc + S.cart_off[j] + b]));
+    Pblk[t] = mx;
+    local = fmax(local, mx);
   }
   atomic_max_nonneg(gmax, local);
 }
@@ -82,14 +100,16 @@ __global__ __launch_bounds__(256) void k_capacity(ScreenArgs A) {
   int cb = -1;
   if (i < A.npairs) {
     cb = A.pair_cls[i];
-    const int li = i - A.cls_beg[cb];
+    const int m = A.pair_mol[i];
+    const int li = i - A.cm_beg[cb * (A.nmol + 1) + m];
     const double Ib = A.pairI[i];
     const double pglob = *A.gmax;
     for (int ck = 0; ck < NPAIRCLASS; ++ck) {
       loc[ck] = 0;
       if (ck > cb) continue;
-      const int nk = A.cls_beg[ck + 1] - A.cls_beg[ck];
-      int n = ket_prefix(A.pairI + A.cls_beg[ck], nk, Ib, pglob, A.tau);
+      const int kb = A.cm_beg[ck * (A.nmol + 1) + m];
+      const int nk = A.cm_beg[ck * (A.nmol + 1) + m + 1] - kb;
+      int n = ket_prefix(A.pairI + kb, nk, Ib, pglob, A.tau);
       if (ck == cb) n = min(n, li + 1);
       if (n > 0) loc[ck] = (int)atomicAdd(&s_tot[qclass_index(cb, ck)], (unsigned long long)n);
     }
@@ -100,6 +120,24 @@ __global__ __launch_bounds__(256) void k_capacity(ScreenArgs A) {
   __syncthreads();
   if (i < A.npairs)
     for (int ck = 0; ck <= cb; ++ck) A.segoff[(size_t)i * NPAIRCLASS + ck] = (int)(s_base[qclass_index(cb, ck)] + loc[ck]);
+}
+
+// Class regions of the work list, laid out one after another in class order. The list has
+// `limit` entries; a class that does not fit keeps what room is left (possibly none) and
+// the overflow flag is raised (only graph replays, whose list was sized at recording
+// time, can see this: an eager build sizes the list from cap first).
+__global__ void k_class_off(const unsigned long long *cap, long long *class_off, long long *room, long long limit,
+                            int *overflow) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  long long off = 0;
+  for (int c = 0; c < NQCLASS; ++c) {
+    const long long n = (long long)cap[c];
+    class_off[c] = off < limit ? off : limit;
+    const long long left = limit - class_off[c];
+    room[c] = n < left ? n : left;
+    off += n;
+  }
+  if (off > limit) *overflow = 1;
 }
 
 // One wave per bra pair: tests the candidates of every ket class with the exact
@@ -116,20 +154,29 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
     const double tau = A.tau;
     const double pglob = *A.gmax;
     const int cb = A.pair_cls[i];
-    const int li = i - A.cls_beg[cb];
+    const int m = A.pair_mol[i];
+    const int li = i - A.cm_beg[cb * (A.nmol + 1) + m];
     const double Ib = A.pairI[i];
-    const int sa = A.pair_sa[i], sb = A.pair_sb[i];
-    const double *Pa = A.Pblk + (size_t)sa * A.nshell;
-    const double *Pb = A.Pblk + (size_t)sb * A.nshell;
+    const int sb0 = A.sbase[m];
+    const int ns = A.sbase[m + 1] - sb0;
+    const double *Pm = A.Pblk + A.ps_off[m];
+    const int sa = A.pair_sa[i] - sb0, sb = A.pair_sb[i] - sb0;
+    const double *Pa = Pm + (size_t)sa * ns;
+    const double *Pb = Pm + (size_t)sb * ns;
     const double pab = Pa[sb];
     const unsigned long long nppb = (unsigned long long)A.pair_npp[i];
     for (int ck = 0; ck <= cb; ++ck) {
-      const int kb = A.cls_beg[ck];
-      const int nk = A.cls_beg[ck + 1] - kb;
+      const int kb = A.cm_beg[ck * (A.nmol + 1) + m];
+      const int nk = A.cm_beg[ck * (A.nmol + 1) + m + 1] - kb;
       int n = ket_prefix(A.pairI + kb, nk, Ib, pglob, tau);
       if (ck == cb) n = min(n, li + 1);
       const int qc = qclass_index(cb, ck);
-      int *out = A.kets + A.class_off[qc] + A.segoff[(size_t)i * NPAIRCLASS + ck];
+      const long long so = A.segoff[(size_t)i * NPAIRCLASS + ck];
+      {                                       // never write past the class region
+        const long long left = A.room[qc] - so;
+        if (left < n) n = left > 0 ? (int)left : 0;
+      }
+      int *out = A.kets + A.class_off[qc] + so;
       int kept = 0;
       unsigned long long np = 0ull;
       for (int k0 = 0; k0 < n; k0 += 64) {
@@ -137,9 +184,9 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
         bool keep = false;
         if (k < n) {
           const int kg = kb + k;
-          const int sc = A.pair_sa[kg], sd = A.pair_sb[kg];
+          const int sc = A.pair_sa[kg] - sb0, sd = A.pair_sb[kg] - sb0;
           double p = pab;
-          p = fmax(p, A.Pblk[(size_t)sc * A.nshell + sd]);
+          p = fmax(p, Pm[(size_t)sc * ns + sd]);
           p = fmax(p, Pa[sc]);
           p = fmax(p, Pa[sd]);
           p = fmax(p, Pb[sc]);
@@ -170,25 +217,31 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
     }
 }
 
-// Jt[ca + a][cb + b] = Coulomb pair buffer (each shell pair owns its block of Jt).
+// Jt[ca + a][cb + b] = Coulomb pair buffer (each shell pair owns its block of its molecule's Jt).
 __global__ void k_fold(FoldArgs F) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < F.npairs; p += gridDim.x * blockDim.x) {
     const int c = F.pair_cls[p];
     const int beg = F.cls_beg[c], np = F.cls_beg[c + 1] - beg;
     const int na = ncart(F.pair_la[p]), nb = ncart(F.pair_lb[p]);
+    const int m = F.pair_mol[p];
+    const int nc = F.cbase[m + 1] - F.cbase[m];
+    double *Jm = F.Jc + F.mc_off[m];
     for (int a = 0; a < na; ++a)
       for (int b = 0; b < nb; ++b)
-        F.Jc[(size_t)(F.pair_ca[p] + a) * F.nc + F.pair_cb[p] + b] = F.Jpair[F.jp_off[c] + (long long)(a * nb + b) * np + (p - beg)];
+        Jm[(size_t)(F.pair_ca[p] + a) * nc + F.pair_cb[p] + b] = F.Jpair[F.jp_off[c] + (long long)(a * nb + b) * np + (p - beg)];
   }
 }
 
-// J[mu][nu] = sum_{a,b} T[mu][a] (Jc[a][b] + Jc[b][a]) T[nu][b], same for K.
+// J[mu][nu] = sum_{a,b} T[mu][a] (Jc[a][b] + Jc[b][a]) T[nu][b], same for K (per molecule).
 __global__ void k_finalize(ShellInfo S, const double *__restrict__ Jc, const double *__restrict__ Kc,
                            double *__restrict__ J, double *__restrict__ K) {
-  const long long n = (long long)S.nao * S.nao;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
-    const int mu = (int)(t / S.nao), nu = (int)(t % S.nao);
-    const int si = S.ao2shell[mu], sj = S.ao2shell[nu];
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < S.nf2_tot;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int m = mol_of(S.mf_off, S.nmol, t);
+    const int nao = S.abase[m + 1] - S.abase[m], nc = S.cbase[m + 1] - S.cbase[m];
+    const long long r = t - S.mf_off[m];
+    const int mu = (int)(r / nao), nu = (int)(r % nao);
+    const int si = S.ao2shell[S.abase[m] + mu], sj = S.ao2shell[S.abase[m] + nu];
     const int im = mu - S.ao_off[si], jn = nu - S.ao_off[sj];
     const int li = S.l[si], lj = S.l[sj];
     const bool pi = S.pure[si] && li >= 2, pj = S.pure[sj] && lj >= 2;
@@ -197,6 +250,7 @@ __global__ void k_finalize(ShellInfo S, const double *__restrict__ Jc, const dou
     const double *Tj = pj ? S.tsph + S.toff[lj] + jn * nj : nullptr;
     const int a0 = pi ? 0 : im, a1 = pi ? ni : im + 1;
     const int b0 = pj ? 0 : jn, b1 = pj ? nj : jn + 1;
+    const double *Jm = Jc + S.mc_off[m], *Km = Kc + S.mc_off[m];
     double vj = 0.0, vk = 0.0;
     for (int a = a0; a < a1; ++a) {
       const double ta = pi ? Ti[a] : 1.0;
@@ -206,8 +260,8 @@ __global__ void k_finalize(ShellInfo S, const double *__restrict__ Jc, const dou
       for (int b = b0; b < b1; ++b) {
         const double tb = pj ? Tj[b] : 1.0;
         const size_t rb = (size_t)(S.cart_off[sj] + b);
-        rj = fma(tb, Jc[ra * S.nc + rb] + Jc[rb * S.nc + ra], rj);
-        rk = fma(tb, Kc[ra * S.nc + rb] + Kc[rb * S.nc + ra], rk);
+        rj = fma(tb, Jm[ra * nc + rb] + Jm[rb * nc + ra], rj);
+        rk = fma(tb, Km[ra * nc + rb] + Km[rb * nc + ra], rk);
       }
       vj = fma(ta, rj, vj);
       vk = fma(ta, rk, vk);
@@ -235,12 +289,11 @@ static int grid_for(long long n, int block) {
 }
 
 hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, hipStream_t st) {
-  hipLaunchKernelGGL(k_dcart, dim3(grid_for((long long)S.nc * S.nc, 256)), dim3(256), 0, st, S, D, Dc);
+  hipLaunchKernelGGL(k_dcart, dim3(grid_for(S.nc2_tot, 256)), dim3(256), 0, st, S, D, Dc);
   return hipGetLastError();
 }
 hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, double *gmax, hipStream_t st) {
-  hipLaunchKernelGGL(k_blockmax, dim3(grid_for((long long)S.nshell * S.nshell, 256)), dim3(256), 0, st, S, Dc, Pblk,
-                     gmax);
+  hipLaunchKernelGGL(k_blockmax, dim3(grid_for(S.ns2_tot, 256)), dim3(256), 0, st, S, Dc, Pblk, gmax);
   return hipGetLastError();
 }
 hipError_t launch_capacity(const ScreenArgs &A, hipStream_t st) {
@@ -251,13 +304,18 @@ hipError_t launch_screen(const ScreenArgs &A, hipStream_t st) {
   hipLaunchKernelGGL(k_screen, dim3((A.npairs + 3) / 4), dim3(256), 0, st, A);
   return hipGetLastError();
 }
+hipError_t launch_class_off(const unsigned long long *cap, long long *class_off, long long *room, long long limit,
+                            int *overflow, hipStream_t st) {
+  hipLaunchKernelGGL(k_class_off, dim3(1), dim3(64), 0, st, cap, class_off, room, limit, overflow);
+  return hipGetLastError();
+}
 hipError_t launch_fold(const FoldArgs &F, hipStream_t st) {
   hipLaunchKernelGGL(k_fold, dim3(grid_for(F.npairs, 256)), dim3(256), 0, st, F);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(grid_for((long long)S.nao * S.nao, 256)), dim3(256), 0, st, S, Jc, Kc, J, K);
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(S.nf2_tot, 256)), dim3(256), 0, st, S, Jc, Kc, J, K);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t st) {

@@ -7,15 +7,16 @@ namespace jk {
 
 constexpr int DYN_LDS_MAX = 150 * 1024;   // dynamic LDS the J/K kernels may request (CU: 160 KB)
 
+// The dynamic-LDS attribute of every J/K kernel is set once at registration (before any
+// launch, so that no attribute call happens while a stream is being recorded into a graph).
+template <class F>
+void allow_dyn_lds(F *fn) {
+  (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, DYN_LDS_MAX);
+  (void)hipGetLastError();   // the attribute is a hint; do not leave its status for a launch check
+}
+
 template <int LA, int LB, int LC, int LD>
 hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_cls<LA, LB, LC, LD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              DYN_LDS_MAX);
-    (void)hipGetLastError();   // the attribute is a hint; do not leave its status for the launch check
-    attr = true;
-  }
   hipLaunchKernelGGL((k_cls<LA, LB, LC, LD>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), lds, stream, args);
   return hipGetLastError();
 }
@@ -29,13 +30,6 @@ hipError_t launch_mode(const ModeArgs &args, int grid, hipStream_t stream) {
 
 template <int LA, int LB, int TIER>
 hipError_t launch_bra(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_bra<LA, LB, TIER>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              DYN_LDS_MAX);
-    (void)hipGetLastError();
-    attr = true;
-  }
   hipLaunchKernelGGL((k_bra<LA, LB, TIER>), dim3(grid), dim3(256), lds, stream, args);
   return hipGetLastError();
 }
@@ -59,6 +53,7 @@ void register_one(ClassInfo *table) {
     ci.scratch_per_wg = 0;
   }
   ci.launch_cls = launch_cls<LA, LB, LC, LD>;
+  allow_dyn_lds(k_cls<LA, LB, LC, LD>);
   ci.launch_mode[MODE_JK] = nullptr;
   ci.launch_mode[MODE_SCHWARZ] = (LA == LC && LB == LD) ? launch_mode<LA, LB, LC, LD, MODE_SCHWARZ> : nullptr;
   ci.launch_mode[MODE_ERI] = launch_mode<LA, LB, LC, LD, MODE_ERI>;
@@ -78,9 +73,10 @@ void register_tier(BraInfo &b) {
   b.fusable[TIER] = bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0;
   b.pool_bytes[TIER] = bra_pool_bytes<LA, LB, TIER>();
   b.scratch_per_wg[TIER] = bra_scratch_doubles<LA, LB, TIER>();
-  if constexpr (bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0)
+  if constexpr (bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0) {
     b.launch_bra[TIER] = launch_bra<LA, LB, TIER>;
-  else
+    allow_dyn_lds(k_bra<LA, LB, TIER>);
+  } else
     b.launch_bra[TIER] = nullptr;
 }
 

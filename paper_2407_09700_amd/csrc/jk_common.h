@@ -17,9 +17,9 @@ constexpr __host__ __device__ int qclass_index(int cb, int ck) { return cb * (cb
 struct alignas(16) Pair {
   double A[3], B[3];     // centres of shell a and shell b
   int sa, sb;            // shell indices (for the symmetry factor)
-  int ca, cb;            // first Cartesian AO of shell a / shell b in the Cartesian matrices
+  int ca, cb;            // first Cartesian AO of shell a / shell b inside the molecule's Cartesian matrices
   int pp_off, npp;       // primitive-pair range in the PrimPair array
-  float I;               // Cauchy-Schwarz factor of the pair
+  int mol;              // molecule of the pair (index into the per-molecule tables)
   int cls;               // pair class (la, lb)
 };
 

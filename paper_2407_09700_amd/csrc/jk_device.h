@@ -69,7 +69,7 @@ constexpr double PI_2P5_X2 = 34.98683665524972;   // 2 pi^(5/2)
 // degree-RYS_DEG polynomial in s = 2(T - k) - 1 per root and weight; beyond RYS_TMAX[N]
 // the Gauss-Hermite limit u = s^2 / T, w = W / sqrt(T) holds to double precision.
 template <int N>
-__device__ __forceinline__ void rys_roots(double T, double (&u)[N], double (&w)[N]) {
+__device__ __forceinline__ void rys_roots_table(double T, double (&u)[N], double (&w)[N]) {
   if (T >= (double)RYS_TMAX[N]) {
     const double it = 1.0 / T;
     const double isq = sqrt(it);
@@ -98,7 +98,63 @@ __device__ __forceinline__ void rys_roots(double T, double (&u)[N], double (&w)[
   }
 }
 
-// One root n (run-time) of the N-point rule.
+// Boys function F_m(T) = int_0^1 t^(2m) exp(-T t^2) dt for m = 0..M (M <= 3), the moments of
+// the Rys weight. T < 1: F_M from its Taylor series in T, then the downward relation
+// F_(m-1) = (2T F_m + exp(-T)) / (2m-1); T >= 1: F_0 = sqrt(pi/T) erf(sqrt(T)) / 2 and the upward
+// relation F_(m+1) = ((2m+1) F_m - exp(-T)) / (2T), stable for T >= 1 and m <= 3.
+template <int M>
+__host__ __device__ __forceinline__ void boys_low(double T, double (&F)[M + 1]) {
+  if (T < 1.0) {
+    // F_M(T) = sum_k (-T)^k / (k! (2M+2k+1)); 19 terms reach 1e-17 at T = 1
+    double term = 1.0, s = 1.0 / (2 * M + 1);
+#pragma unroll
+    for (int k = 1; k <= 19; ++k) {
+      term *= -T / k;
+      s = fma(term, 1.0 / (2 * M + 2 * k + 1), s);
+    }
+    F[M] = s;
+    const double e = exp(-T);
+#pragma unroll
+    for (int m = M; m > 0; --m) F[m - 1] = (2.0 * T * F[m] + e) / (2 * m - 1);
+  } else {
+    const double st = sqrt(T);
+    const double e = exp(-T);
+    const double h = 0.5 / T;
+    F[0] = 0.88622692545275801365 / st * erf(st);        // sqrt(pi)/2
+#pragma unroll
+    for (int m = 0; m < M; ++m) F[m + 1] = ((2 * m + 1) * F[m] - e) * h;
+  }
+}
+
+// Closed-form Rys rules for N = 1, 2 from the moments F_0..F_(2N-1): the N-point Gauss rule
+// of the weight whose moments they are (N = 1: u = F1/F0, w = F0; N = 2: the two zeros of the
+// monic quadratic orthogonal to 1 and u, and the weights that reproduce F0 and F1).
+template <int N>
+__host__ __device__ __forceinline__ void rys_closed(double T, double (&u)[N], double (&w)[N]) {
+  static_assert(N == 1 || N == 2, "closed form only for one or two roots");
+  if constexpr (N == 1) {
+    double F[2];
+    boys_low<1>(T, F);
+    u[0] = F[1] / F[0];
+    w[0] = F[0];
+  } else {
+    double F[4];
+    boys_low<3>(T, F);
+    const double det = F[0] * F[2] - F[1] * F[1];
+    const double c1 = (F[1] * F[2] - F[0] * F[3]) / det;       // u^2 + c1 u + c0
+    const double c0 = (F[1] * F[3] - F[2] * F[2]) / det;
+    const double disc = sqrt(c1 * c1 - 4.0 * c0);
+    // stable pair of roots of u^2 + c1 u + c0 (c1 < 0)
+    const double big = 0.5 * (-c1 + disc);
+    const double small = c0 / big;
+    u[0] = small;
+    u[1] = big;
+    w[0] = (F[1] - big * F[0]) / (small - big);
+    w[1] = F[0] - w[0];
+  }
+}
+
+// One root n (run-time) of the N-point rule (table).
 template <int N>
 __device__ __forceinline__ void rys_root1(double T, int n, double &u, double &w) {
   if (T >= (double)RYS_TMAX[N]) {

@@ -46,18 +46,15 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
       PrimQuartet Q;
       prim_quartet(pb, pk, bra.A, ket.A, Q);
       const double hq = 0.5 / pk.p;
-      double u[N], w[N];
-      rys_roots<N>(Q.T, u, w);
-#pragma unroll
-      for (int n = 0; n < N; ++n) {
-        const double uq = u[n] * Q.pq_inv;
+      auto root = [&](double un, double wn) {
+        const double uq = un * Q.pq_inv;
         const double b00 = 0.5 * uq;
         const double b10 = hp * (1.0 - uq * Q.q);
         const double b01 = hq * (1.0 - uq * Q.p);
         double Gx[E + 1][F + 1], Gy[E + 1][F + 1], Gz[E + 1][F + 1];
         vrr2d<E, F>(Gx, 1.0, Q.PA[0] - uq * Q.q * Q.PQ[0], Q.QC[0] + uq * Q.p * Q.PQ[0], b10, b01, b00);
         vrr2d<E, F>(Gy, 1.0, Q.PA[1] - uq * Q.q * Q.PQ[1], Q.QC[1] + uq * Q.p * Q.PQ[1], b10, b01, b00);
-        vrr2d<E, F>(Gz, w[n] * Q.pref, Q.PA[2] - uq * Q.q * Q.PQ[2], Q.QC[2] + uq * Q.p * Q.PQ[2], b10, b01, b00);
+        vrr2d<E, F>(Gz, wn * Q.pref, Q.PA[2] - uq * Q.q * Q.PQ[2], Q.QC[2] + uq * Q.p * Q.PQ[2], b10, b01, b00);
 #pragma unroll
         for (int ie = 0; ie < NE; ++ie) {
 #pragma unroll
@@ -65,6 +62,19 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
             acc[ie * NF + jf] = fma(Gx[CT.x[E0 + ie]][CT.x[F0 + jf]] * Gy[CT.y[E0 + ie]][CT.y[F0 + jf]],
                                     Gz[CT.z[E0 + ie]][CT.z[F0 + jf]], acc[ie * NF + jf]);
           }
+        }
+      };
+      if constexpr (N <= 2) {
+        double u[N], w[N];
+        rys_closed<N>(Q.T, u, w);
+#pragma unroll
+        for (int n = 0; n < N; ++n) root(u[n], w[n]);
+      } else {
+#pragma unroll 1
+        for (int n = 0; n < N; ++n) {
+          double un, wn;
+          rys_root1<N>(Q.T, n, un, wn);
+          root(un, wn);
         }
       }
     }

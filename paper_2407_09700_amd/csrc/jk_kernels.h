@@ -53,12 +53,14 @@ struct JKArgs {
   const long long *class_off;   // [120] first entry of each class region in kets
   const int *segoff;            // [npairs * 15] segment offset inside the class region
   const int *segcnt;            // [npairs * 15] kept kets of the segment
-  const double *Dc;             // Cartesian density, nc x nc
-  double *Kc;                   // Cartesian exchange accumulator, nc x nc
+  const double *Dc;             // Cartesian densities, one nc_m x nc_m block per molecule
+  double *Kc;                   // Cartesian exchange accumulators, same layout
+  const long long *mbase;       // [nmol] first element of each molecule's block in Dc / Kc
+  const int *mnc;               // [nmol] Cartesian AO count of each molecule
   double *Jpair;                // Coulomb accumulator per shell pair
   const long long *jp_off;      // [15] first element of each pair class in Jpair
   const int *cls_beg;           // [16] first pair of each pair class
-  int nc;
+  int nc_max;                   // largest nc_m (row length of the LDS exchange rows)
   int bra_beg, bra_end;         // bra pairs of the launched bra class
   int *next;                    // work counter of the launch
   double *scratch;              // global buffers of the largest team classes
@@ -71,12 +73,13 @@ __device__ __forceinline__ double *jp_elem(const JKArgs &A, int cls, int pair, i
 }
 
 // exchange update into row `r` of the unit: LDS rows (KLDS; r < NA+NB) or the global matrix
+// Km: the molecule's exchange block in global memory; nc: its row length.
 template <bool KLDS>
-__device__ __forceinline__ void k_update(const JKArgs &A, double *Krow, int r, int grow, int col, double v) {
+__device__ __forceinline__ void k_update(double *Krow, double *Km, int nc, int r, int grow, int col, double v) {
   if constexpr (KLDS)
-    atomicAdd(&Krow[(size_t)r * A.nc + col], v);
+    atomicAdd(&Krow[(size_t)r * nc + col], v);
   else
-    atomic_add(&A.Kc[(size_t)grow * A.nc + col], v);
+    atomic_add(&Km[(size_t)grow * nc + col], v);
 }
 
 // ------------------------------------------------------------------ lane-per-quartet body
@@ -87,8 +90,9 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int ck = pair_class(LC, LD);
   const Pair bra = A.pairs[bi];
-  const int nc = A.nc;
-  const double *Dm = A.Dc;
+  const int nc = A.mnc[bra.mol];
+  const double *Dm = A.Dc + A.mbase[bra.mol];
+  double *Km = A.Kc + A.mbase[bra.mol];
   double Dab[NA * NB];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
@@ -130,7 +134,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + od + d], v);
-        k_update<KLDS>(A, Krow, a, bra.ca + a, oc + c, s * v);
+        k_update<KLDS>(Krow, Km, nc, a, bra.ca + a, oc + c, s * v);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -139,7 +143,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + oc + c], v);
-        k_update<KLDS>(A, Krow, a, bra.ca + a, od + d, s * v);
+        k_update<KLDS>(Krow, Km, nc, a, bra.ca + a, od + d, s * v);
       }
     }
 #pragma unroll
@@ -151,7 +155,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + od + d], v);
-        k_update<KLDS>(A, Krow, NA + b, bra.cb + b, oc + c, s * v);
+        k_update<KLDS>(Krow, Km, nc, NA + b, bra.cb + b, oc + c, s * v);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -160,7 +164,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + oc + c], v);
-        k_update<KLDS>(A, Krow, NA + b, bra.cb + b, od + d, s * v);
+        k_update<KLDS>(Krow, Km, nc, NA + b, bra.cb + b, od + d, s * v);
       }
     }
   }
@@ -182,8 +186,9 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   double *buf = C::GLOBAL_BUF ? A.scratch + (size_t)blockIdx.x * A.scratch_per_wg : lbuf;
   const Pair bra = A.pairs[bi];
   const int tid = threadIdx.x;
-  const int nc = A.nc;
-  const double *Dm = A.Dc;
+  const int nc = A.mnc[bra.mol];
+  const double *Dm = A.Dc + A.mbase[bra.mol];
+  double *Km = A.Kc + A.mbase[bra.mol];
   constexpr int T1 = NA * NB, T2 = NC * ND, T3 = NA * NC, T4 = NA * ND, T5 = NB * NC, T6 = NB * ND;
   constexpr int TOT = T1 + T2 + T3 + T4 + T5 + T6;
   for (int k0 = 0; k0 < cnt; k0 += QB) {
@@ -225,7 +230,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         const int a = r / NC, c = r % NC;
         for (int b = 0; b < NB; ++b)
           for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + od + d], v);
-        k_update<KLDS>(A, Krow, a, oa + a, oc + c, s * v);
+        k_update<KLDS>(Krow, Km, nc, a, oa + a, oc + c, s * v);
         continue;
       }
       r -= T3;
@@ -233,7 +238,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         const int a = r / ND, d = r % ND;
         for (int b = 0; b < NB; ++b)
           for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + oc + c], v);
-        k_update<KLDS>(A, Krow, a, oa + a, od + d, s * v);
+        k_update<KLDS>(Krow, Km, nc, a, oa + a, od + d, s * v);
         continue;
       }
       r -= T4;
@@ -241,7 +246,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         const int b = r / NC, c = r % NC;
         for (int a = 0; a < NA; ++a)
           for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + od + d], v);
-        k_update<KLDS>(A, Krow, NA + b, ob + b, oc + c, s * v);
+        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, oc + c, s * v);
         continue;
       }
       r -= T5;
@@ -249,7 +254,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         const int b = r / ND, d = r % ND;
         for (int a = 0; a < NA; ++a)
           for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + oc + c], v);
-        k_update<KLDS>(A, Krow, NA + b, ob + b, od + d, s * v);
+        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, od + d, s * v);
       }
     }
     __syncthreads();
@@ -271,8 +276,9 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
   int *smax = qi + QB * 8;
   const Pair bra = A.pairs[bi];
   const int tid = threadIdx.x;
-  const int nc = A.nc;
-  const double *Dm = A.Dc;
+  const int nc = A.mnc[bra.mol];
+  const double *Dm = A.Dc + A.mbase[bra.mol];
+  double *Km = A.Kc + A.mbase[bra.mol];
   const int oa = bra.ca, ob = bra.cb;
   for (int k0 = 0; k0 < cnt; k0 += QB) {
     if (tid < QB) {
@@ -309,8 +315,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
           kc = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + dd], kc);
           kd = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + cc], kd);
         }
-        k_update<KLDS>(A, Krow, a, oa + a, cc, s * kc);
-        k_update<KLDS>(A, Krow, a, oa + a, dd, s * kd);
+        k_update<KLDS>(Krow, Km, nc, a, oa + a, cc, s * kc);
+        k_update<KLDS>(Krow, Km, nc, a, oa + a, dd, s * kd);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -320,8 +326,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
           kc = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + dd], kc);
           kd = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + cc], kd);
         }
-        k_update<KLDS>(A, Krow, NA + b, ob + b, cc, s * kc);
-        k_update<KLDS>(A, Krow, NA + b, ob + b, dd, s * kd);
+        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, cc, s * kc);
+        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, dd, s * kd);
       }
     }
     __syncthreads();
@@ -435,20 +441,23 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB);
   extern __shared__ double smem[];
   __shared__ int s_unit;
-  const int nc = A.nc;
   double *Krow = smem;
-  double *jab_s = smem + (size_t)(NA + NB) * nc;
+  double *jab_s = smem + (size_t)(NA + NB) * A.nc_max;
   double *pool = jab_s + ((NA * NB + 1) & ~1);
   const int nunits = A.bra_end - A.bra_beg;
   const int tid = threadIdx.x;
+  // the rows start at zero; the flush of each unit puts back the zeros it reads
+  for (int t = tid; t < (NA + NB) * A.nc_max; t += blockDim.x) Krow[t] = 0.0;
   for (;;) {
     if (tid == 0) s_unit = atomicAdd(A.next, 1);
-    for (int t = tid; t < (NA + NB) * nc; t += blockDim.x) Krow[t] = 0.0;
     for (int t = tid; t < NA * NB; t += blockDim.x) jab_s[t] = 0.0;
     __syncthreads();
     const int u = s_unit;
     if (u >= nunits) break;
     const int bi = A.bra_beg + u;
+    const int mol = A.pairs[bi].mol;
+    const int nc = A.mnc[mol];
+    double *Km = A.Kc + A.mbase[mol];
     double jab[NA * NB];
 #pragma unroll
     for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
@@ -466,9 +475,10 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
     for (int t = tid; t < (NA + NB) * nc; t += blockDim.x) {
       const double v = Krow[t];
       if (v != 0.0) {
+        Krow[t] = 0.0;
         const int r = t / nc, col = t % nc;
         const int row = r < NA ? bra.ca + r : bra.cb + (r - NA);
-        atomic_add(&A.Kc[(size_t)row * nc + col], v);
+        atomic_add(&Km[(size_t)row * nc + col], v);
       }
     }
     for (int t = tid; t < NA * NB; t += blockDim.x)

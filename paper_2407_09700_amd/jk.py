@@ -18,8 +18,10 @@ JK_FP64, JK_MIXED = 0, 1
 
 # every symbol declared in include/jk.h
 EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_build", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
-           "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_last_error"]
-JK_FLAG_PROFILE = 1
+           "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_rys_closed", "jk_batch_create",
+           "jk_batch_offsets", "jk_batch_execute", "jk_batch_stats", "jk_batch_graph_info", "jk_batch_destroy",
+           "jk_last_error"]
+JK_FLAG_PROFILE, JK_FLAG_GRAPH, JK_FLAG_TUNE = 1, 2, 4
 
 
 class JKError(RuntimeError):
@@ -37,7 +39,7 @@ class Basis(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("thresh", ctypes.c_double), ("precision", ctypes.c_int), ("fp32_cutoff", ctypes.c_double),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -77,6 +79,18 @@ def lib():
         L.jk_eri_tensor.argtypes = [vp, vp, vp]
         L.jk_schwarz.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.jk_sph_matrix.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.jk_rys_closed.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+        L.jk_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.POINTER(Basis)),
+                                      ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.jk_batch_offsets.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]
+        L.jk_batch_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.jk_batch_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.jk_batch_graph_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong),
+                                          ctypes.POINTER(ctypes.c_int)]
+        L.jk_batch_destroy.argtypes = [vp]
+        L.jk_batch_destroy.restype = None
         L.jk_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -95,6 +109,14 @@ def sph_matrix(l: int) -> np.ndarray:
     out = np.zeros((2 * l + 1) * (l + 1) * (l + 2) // 2)
     check(lib().jk_sph_matrix(int(l), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out.reshape(2 * l + 1, (l + 1) * (l + 2) // 2)
+
+
+def rys_closed(nroots: int, T: float):
+    u = np.zeros(nroots)
+    w = np.zeros(nroots)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().jk_rys_closed(int(nroots), float(T), u.ctypes.data_as(dp), w.ctypes.data_as(dp)))
+    return u, w
 
 
 class BasisArrays:
@@ -117,6 +139,13 @@ class BasisArrays:
                    mol.prim_coef)
 
 
+def make_opts(thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6, profile=False, graph=False, tune=False,
+              tune_cache=None):
+    flags = (JK_FLAG_PROFILE if profile else 0) | (JK_FLAG_GRAPH if graph else 0) | (JK_FLAG_TUNE if tune else 0)
+    return Opts(float(thresh), int(precision), float(fp32_cutoff), flags,
+                None if tune_cache is None else os.fsencode(tune_cache))
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
@@ -131,10 +160,11 @@ def _stream(stream):
 class Plan:
     """A J/K plan for one molecule. D, J, K are torch float64 CUDA tensors (nao x nao)."""
 
-    def __init__(self, coords, basis: BasisArrays, thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6, profile=False):
+    def __init__(self, coords, basis: BasisArrays, thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6, profile=False,
+                 graph=False, tune=False, tune_cache=None):
         self.basis = basis
         self.coords = np.ascontiguousarray(coords, np.float64)
-        self.opts = Opts(float(thresh), int(precision), float(fp32_cutoff), JK_FLAG_PROFILE if profile else 0)
+        self.opts = make_opts(thresh, precision, fp32_cutoff, profile, graph, tune, tune_cache)
         h = ctypes.c_void_p()
         check(lib().jk_plan_create(ctypes.byref(basis.struct),
                                    self.coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -187,6 +217,75 @@ class Plan:
     def close(self):
         if getattr(self, "h", None):
             lib().jk_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batched J/K build over many molecules. D, J, K are packed 1-D torch float64 CUDA
+    tensors: molecule m's nao[m] x nao[m] block starts at offsets[m]."""
+
+    def __init__(self, mols, thresh=None, precision=JK_FP64, fp32_cutoff=1e-6, profile=False, graph=False,
+                 tune=False, tune_cache=None):
+        self.bases = [BasisArrays.from_molecule(m) for m in mols]
+        self.coords = [np.ascontiguousarray(m.coords, np.float64) for m in mols]
+        th = mols[0].thresh if thresh is None else thresh
+        self.opts = make_opts(th, precision, fp32_cutoff, profile, graph, tune, tune_cache)
+        n = len(mols)
+        bp = (ctypes.POINTER(Basis) * n)(*[ctypes.pointer(b.struct) for b in self.bases])
+        cp = (ctypes.POINTER(ctypes.c_double) * n)(*[c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                                      for c in self.coords])
+        na = (ctypes.c_int * n)(*[c.shape[0] for c in self.coords])
+        h = ctypes.c_void_p()
+        check(lib().jk_batch_create(n, bp, cp, na, ctypes.byref(self.opts), ctypes.byref(h)))
+        self.h = h
+        off = (ctypes.c_longlong * (n + 1))()
+        nao = (ctypes.c_int * n)()
+        check(lib().jk_batch_offsets(self.h, off, nao))
+        self.offsets = np.array(off[:], dtype=np.int64)
+        self.nao = np.array(nao[:], dtype=np.int64)
+        self.nmol = n
+
+    def pack(self, mats):
+        import torch
+        return torch.cat([torch.as_tensor(np.ascontiguousarray(m), dtype=torch.float64).reshape(-1)
+                          for m in mats]).cuda()
+
+    def unpack(self, flat):
+        return [flat[self.offsets[m]:self.offsets[m + 1]].reshape(int(self.nao[m]), int(self.nao[m]))
+                for m in range(self.nmol)]
+
+    def execute(self, D, J=None, K=None, stream=None):
+        import torch
+        tot = int(self.offsets[-1])
+        assert D.dtype == torch.float64 and D.is_cuda and D.is_contiguous() and D.numel() == tot
+        if J is None:
+            J = torch.empty_like(D)
+        if K is None:
+            K = torch.empty_like(D)
+        for t in (J, K):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() == tot
+        check(lib().jk_batch_execute(self.h, _ptr(D), _ptr(J), _ptr(K), _stream(stream)))
+        return J, K
+
+    def stats(self):
+        s = Stats()
+        check(lib().jk_batch_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def graph_info(self):
+        rec, rep, rr = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int()
+        check(lib().jk_batch_graph_info(self.h, ctypes.byref(rec), ctypes.byref(rep), ctypes.byref(rr)))
+        return {"recorded": bool(rec.value), "replays": rep.value, "rerecords": rr.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().jk_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

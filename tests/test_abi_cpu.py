@@ -75,3 +75,38 @@ def test_valid_input_reaches_device_check():
         assert rc == jk.JK_OK
     else:
         assert rc == jk.JK_ENODEV
+
+
+def _batch_create(mols, nmol=None, opts=None):
+    bases = [jk.BasisArrays.from_molecule(m) for m in mols]
+    coords = [np.ascontiguousarray(m.coords, np.float64) for m in mols]
+    n = len(mols) if nmol is None else nmol
+    bp = (ctypes.POINTER(jk.Basis) * len(mols))(*[ctypes.pointer(b.struct) for b in bases])
+    cp = (ctypes.POINTER(ctypes.c_double) * len(mols))(*[c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                                         for c in coords])
+    na = (ctypes.c_int * len(mols))(*[c.shape[0] for c in coords])
+    h = ctypes.c_void_p()
+    rc = jk.lib().jk_batch_create(n, bp, cp, na, None if opts is None else ctypes.byref(opts), ctypes.byref(h))
+    if rc == 0:
+        jk.lib().jk_batch_destroy(h)
+    return rc
+
+
+def test_batch_validation_errors_before_device():
+    good = synth.make_config(1, natom=2)
+    bad = synth.make_config(1, natom=3)
+    bad.shell_l = bad.shell_l.copy()
+    bad.shell_l[0] = 7
+    assert _batch_create([good, bad]) == jk.JK_EUNSUPPORTED
+    assert "molecule 1" in jk.last_error()
+    assert _batch_create([good], nmol=0) == jk.JK_EINVAL
+    assert jk.lib().jk_batch_create(1, None, None, None, None, None) == jk.JK_EINVAL
+    assert jk.lib().jk_batch_execute(None, None, None, None, None) == jk.JK_EINVAL
+    assert jk.lib().jk_batch_offsets(None, None, None) == jk.JK_EINVAL
+    jk.lib().jk_batch_destroy(None)          # no-op
+    opts = jk.make_opts(1e-12)
+    opts.flags = 64
+    assert _batch_create([good], opts=opts) == jk.JK_EINVAL
+    assert "flags" in jk.last_error()
+    opts = jk.make_opts(-1.0)
+    assert _batch_create([good], opts=opts) == jk.JK_EINVAL

@@ -1,0 +1,143 @@
+"""GPU: the batched build (many molecules through one set of launches), its HIP-graph
+replay with the overflow fallback, and the launch-grid tuner."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_09700_amd import synth
+
+from .gpu_util import gpu_jk, maxabs, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _run_batch(mols, Ds=None, **kw):
+    import torch
+    from paper_2407_09700_amd import jk
+    b = jk.Batch(mols, **kw)
+    D = b.pack([m.D for m in mols] if Ds is None else Ds)
+    J, K = b.execute(D)
+    torch.cuda.synchronize()
+    Js = [x.cpu().numpy() for x in b.unpack(J)]
+    Ks = [x.cpu().numpy() for x in b.unpack(K)]
+    return b, Js, Ks
+
+
+def test_batch_matches_oracle_small():
+    mols = synth.make_batch(5, 2, 5)
+    say(f"[batch small] atoms {[m.natom for m in mols]} nbf {[m.nbf for m in mols]}")
+    b, Js, Ks = _run_batch(mols)
+    st = b.stats()
+    b.close()
+    say(f"[batch small] stats {st}")
+    for i, m in enumerate(mols):
+        Jo, Ko = oracle.Oracle(m).jk(tau=m.thresh)
+        dj, dk = maxabs(Js[i], Jo), maxabs(Ks[i], Ko)
+        say(f"[batch small] mol {i}: |dJ|={dj:.2e} |dK|={dk:.2e}")
+        assert dj <= TOL and dk <= TOL
+
+
+def test_batch_equals_single_molecule_plans():
+    mols = synth.make_batch(4, 3, 9)
+    b, Js, Ks = _run_batch(mols)
+    b.close()
+    for i, m in enumerate(mols):
+        (J, K), _ = gpu_jk(m)
+        dj, dk = maxabs(Js[i], J), maxabs(Ks[i], K)
+        say(f"[batch vs single] mol {i} natom {m.natom}: |dJ|={dj:.2e} |dK|={dk:.2e}")
+        assert dj <= 1e-12 and dk <= 1e-12
+
+
+def test_graph_replay_and_overflow_rerecord():
+    import torch
+    from paper_2407_09700_amd import jk
+    mols = synth.make_batch(4, 3, 8)
+    g = jk.Batch(mols, graph=True)
+    e = jk.Batch(mols, graph=False)
+    D1 = g.pack([m.D for m in mols])
+    rng = np.random.default_rng(11)
+    # the graph is recorded for a tiny density (few quartets pass the density-weighted
+    # screen); the full density then needs a longer work list than the recorded one
+    D0 = D1 * 1e-7
+    D2 = g.pack([m.D + 0.1 * (lambda a: a + a.T)(rng.normal(size=m.D.shape)) for m in mols])
+    J = torch.empty_like(D1)
+    K = torch.empty_like(D1)
+    for step, D in enumerate([D0, D0, D1, D1, D2]):
+        g.execute(D, J, K)
+        Je, Ke = e.execute(D)
+        torch.cuda.synchronize()
+        scale = max(1.0, float(Je.abs().max()), float(Ke.abs().max()))
+        dj = float((J - Je).abs().max()) / scale
+        dk = float((K - Ke).abs().max()) / scale
+        info = g.graph_info()
+        say(f"[graph] step {step}: rel |dJ|={dj:.2e} rel |dK|={dk:.2e} {info}")
+        assert dj <= 1e-12 and dk <= 1e-12
+    info = g.graph_info()
+    assert info["recorded"] and info["replays"] >= 2 and info["rerecords"] >= 1
+    # new output buffers: the graph is recorded again for them
+    J2, K2 = g.execute(D2)
+    Je, Ke = e.execute(D2)
+    torch.cuda.synchronize()
+    assert float((J2 - Je).abs().max()) <= 1e-12 and float((K2 - Ke).abs().max()) <= 1e-12
+    g.close()
+    e.close()
+
+
+def test_tuner_cache_roundtrip(tmp_path):
+    import torch
+    from paper_2407_09700_amd import jk
+    mol = synth.make_config(2, natom=12)
+    path = str(tmp_path / "grids.txt")
+    Dt = torch.from_numpy(mol.D).cuda()
+    ref = jk.Plan.from_molecule(mol)
+    Jr, Kr = ref.execute(Dt)
+    t = jk.Plan.from_molecule(mol, tune=True, tune_cache=path)
+    J1, K1 = t.execute(Dt)
+    torch.cuda.synchronize()
+    lines = open(path).read().split()
+    say(f"[tune] cache: {' '.join(lines)}")
+    assert len(lines) >= 2 and all(int(x) > 0 for x in lines[1::2])
+    t2 = jk.Plan.from_molecule(mol, tune=True, tune_cache=path)   # reads the cache, no timing runs
+    J2, K2 = t2.execute(Dt)
+    torch.cuda.synchronize()
+    for J, K in ((J1, K1), (J2, K2)):
+        assert float((J - Jr).abs().max()) <= 1e-12 and float((K - Kr).abs().max()) <= 1e-12
+    for p in (ref, t, t2):
+        p.close()
+
+
+def test_cfg5_full_batch_sampled():
+    """The 64-molecule batch at full size: the smallest molecule against the oracle's full
+    build, the largest against oracle blocks and, with two middle ones, against
+    single-molecule plans."""
+    import time
+    mols = synth.make_batch()
+    say(f"[cfg5] {len(mols)} molecules, {sum(m.natom for m in mols)} atoms, {sum(m.nbf for m in mols)} AOs")
+    t = time.time()
+    b, Js, Ks = _run_batch(mols, graph=True)
+    st = b.stats()
+    b.close()
+    say(f"[cfg5] batched build incl. plan {time.time() - t:.1f}s stats {st}")
+    order = np.argsort([m.natom for m in mols])
+    small, big = int(order[0]), int(order[-1])
+    Jo, Ko = oracle.Oracle(mols[small]).jk(tau=mols[small].thresh)
+    dj, dk = maxabs(Js[small], Jo), maxabs(Ks[small], Ko)
+    say(f"[cfg5] smallest (mol {small}, {mols[small].natom} atoms) vs oracle |dJ|={dj:.2e} |dK|={dk:.2e}")
+    assert dj <= TOL and dk <= TOL
+    for i in (int(order[len(order) // 3]), int(order[2 * len(order) // 3]), big):
+        (J, K), _ = gpu_jk(mols[i])
+        dj, dk = maxabs(Js[i], J), maxabs(Ks[i], K)
+        say(f"[cfg5] mol {i} ({mols[i].natom} atoms) batched vs single plan |dJ|={dj:.2e} |dK|={dk:.2e}")
+        assert dj <= 1e-12 and dk <= 1e-12
+    m = mols[big]
+    o = oracle.Oracle(m)
+    I, P = o.screen_tables()
+    nsh = 7   # shells per atom: s s s p p d f
+    for si, sj in [(0, 0), (nsh * 50 + 6, nsh * 49 + 5), (nsh * 119 + 3, nsh * 7 + 6)]:
+        Jb, Kb = o.jk_block(si, sj, I=I, P=P)
+        sl_i = slice(o.off[si], o.off[si + 1])
+        sl_j = slice(o.off[sj], o.off[sj + 1])
+        dj, dk = maxabs(Js[big][sl_i, sl_j], Jb), maxabs(Ks[big][sl_i, sl_j], Kb)
+        say(f"[cfg5] largest block ({si},{sj}) |dJ|={dj:.2e} |dK|={dk:.2e}")
+        assert dj <= TOL and dk <= TOL

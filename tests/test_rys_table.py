@@ -84,3 +84,31 @@ def test_large_T_is_gauss_hermite(table, N):
     u, w = rys_eval(table, N, T)
     np.testing.assert_allclose(u * T, x[N:] ** 2, rtol=1e-13)
     np.testing.assert_allclose(w * np.sqrt(T), wh[N:], rtol=1e-13)
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_closed_form_roots_moment_identity(N):
+    """The kernels' closed-form rule for one or two roots (compiled for the host) against
+    the moment identity with scipy's incomplete gamma."""
+    from paper_2407_09700_amd import jk
+    rng = np.random.default_rng(40 + N)
+    Ts = np.concatenate([[0.0, 1e-12, 1e-6, 0.3, 0.999999, 1.0, 1.000001, 7.0, 35.0, 60.0, 300.0, 1e5],
+                         rng.uniform(0, 3, 40), rng.uniform(0, 80, 40)])
+    worst = 0.0
+    for T in Ts:
+        u, w = jk.rys_closed(N, float(T))
+        assert np.all(u > 0) and np.all(u < 1) and np.all(w > 0)
+        for m in range(2 * N):
+            ref = boys(m, float(T))
+            worst = max(worst, abs(np.sum(w * u ** m) - ref) / ref)
+    assert worst < 2e-14, worst
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_closed_form_matches_table(table, N):
+    from paper_2407_09700_amd import jk
+    for T in np.linspace(0.0, 60.0, 121):
+        u, w = jk.rys_closed(N, float(T))
+        ut, wt = rys_eval(table, N, float(T))
+        np.testing.assert_allclose(u, ut, rtol=2e-13)
+        np.testing.assert_allclose(w, wt, rtol=2e-13)
