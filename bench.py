@@ -47,6 +47,94 @@ def cpu_baseline(mol, target_s=12.0):
                       f"includes the oracle's own Schwarz/block-max setup)"}
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / steps
+
+
+def _energy(D, J, K):
+    return float((D * (J - 0.5 * K)).sum())
+
+
+def mixed_extra(steps=2, warmup=1):
+    """256-atom clustered 3s2p1d molecule: FP64 build vs mixed build (FP32 below 1e-6)."""
+    import torch
+    from paper_2407_09700_amd import jk, synth
+    mol = synth.make_config(4)
+    D = torch.from_numpy(mol.D).cuda()
+    out = {"workload": f"cfg4: {mol.natom}-atom clustered 3s2p1d, {mol.nbf} AOs, tau {mol.thresh:g}, "
+                       f"FP32 below bound 1e-6"}
+    res = {}
+    for name, prec in (("fp64", jk.JK_FP64), ("mixed", jk.JK_MIXED)):
+        plan = jk.Plan.from_molecule(mol, precision=prec, fp32_cutoff=1e-6)
+        J = torch.empty_like(D)
+        K = torch.empty_like(D)
+        ms = _timed(lambda: plan.execute(D, J, K), steps, warmup)
+        st = plan.stats()
+        res[name] = (ms, _energy(D, J, K), st)
+        plan.close()
+        log(f"cfg4 {name}: {ms:.1f} ms kept {st['kept_quartets']} fp32 {st['kept_fp32']}")
+    out.update({"fp64_ms": res["fp64"][0], "mixed_ms": res["mixed"][0],
+                "speedup": res["fp64"][0] / res["mixed"][0],
+                "fp32_fraction": res["mixed"][2]["kept_fp32"] / max(1, res["mixed"][2]["kept_quartets"]),
+                "kept_quartets": res["fp64"][2]["kept_quartets"],
+                "E_fp64": res["fp64"][1], "dE_mixed_vs_fp64": abs(res["mixed"][1] - res["fp64"][1])})
+    return out
+
+
+def batched_extra(steps=2, warmup=1):
+    """64 molecules of 10-120 atoms (3s2p1d1f): one batched graph-replayed build (FP64 and
+    mixed) vs 64 sequential single-molecule FP64 builds."""
+    import torch
+    from paper_2407_09700_amd import jk, synth
+    mols = synth.make_batch()
+    out = {"workload": f"cfg5: {len(mols)} molecules, {sum(m.natom for m in mols)} atoms, "
+                       f"{sum(m.nbf for m in mols)} AOs, 3s2p1d1f, tau 1e-12"}
+    t = time.perf_counter()
+    plans = [jk.Plan.from_molecule(m) for m in mols]
+    Ds = [torch.from_numpy(m.D).cuda() for m in mols]
+    Js = [torch.empty_like(d) for d in Ds]
+    Ks = [torch.empty_like(d) for d in Ds]
+    log(f"cfg5 sequential plans in {time.perf_counter() - t:.1f}s")
+
+    def seq():
+        for p, d, j, k in zip(plans, Ds, Js, Ks):
+            p.execute(d, j, k)
+    seq_ms = _timed(seq, steps, warmup)
+    kept = sum(p.stats()["kept_quartets"] for p in plans)
+    E_seq = sum(_energy(d, j, k) for d, j, k in zip(Ds, Js, Ks))
+    for p in plans:
+        p.close()
+    out["sequential_fp64_ms"] = seq_ms
+    out["kept_quartets"] = kept
+    log(f"cfg5 sequential: {seq_ms:.1f} ms, {kept} quartets")
+    for name, prec in (("fp64", jk.JK_FP64), ("mixed", jk.JK_MIXED)):
+        t = time.perf_counter()
+        b = jk.Batch(mols, precision=prec, graph=True, tune=True)
+        D = b.pack([m.D for m in mols])
+        J = torch.empty_like(D)
+        K = torch.empty_like(D)
+        ms = _timed(lambda: b.execute(D, J, K), steps, warmup + 1)   # +1: the first execute records the graph
+        E = _energy(D, J, K)
+        info = b.graph_info()
+        st = b.stats()
+        b.close()
+        log(f"cfg5 batched {name}: {ms:.1f} ms (setup {time.perf_counter() - t:.1f}s) graph {info} "
+            f"fp32 {st['kept_fp32']}")
+        out[f"batched_{name}_ms"] = ms
+        out[f"batched_{name}_speedup_vs_sequential"] = seq_ms / ms
+        out[f"dE_batched_{name}_vs_sequential"] = abs(E - E_seq)
+        out[f"graph_replays_{name}"] = info["replays"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +143,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--natom", type=int, default=None, help="smaller molecule of the same recipe (debug)")
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and batched measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); the J/K path "
@@ -138,9 +227,12 @@ def main():
                       "finalize_ms": fin_ms / args.steps, "all_classes_tflops": tot_flops / (class_ms * 1e-3) / 1e12,
                       "top_classes": classes},
     }
+    plan.close()
+    if not args.no_extras and args.natom is None:
+        out["mixed"] = mixed_extra()
+        out["batched"] = batched_extra()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mol)
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

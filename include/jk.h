@@ -72,7 +72,10 @@ typedef struct {
 typedef struct {
   double thresh;         /* tau: quartet kept iff I_ab > tau, I_cd > tau, I_ab I_cd P >= tau */
   int precision;         /* JK_FP64 (default) or JK_MIXED */
-  double fp32_cutoff;    /* JK_MIXED: quartets with I_ab I_cd P below this run in FP32 */
+  double fp32_cutoff;    /* JK_MIXED: kept quartets with I_ab I_cd P below this evaluate their
+                            2D integrals, products and transfer in FP32 (lane-per-quartet
+                            classes; the workgroup-body classes stay FP64); roots, weights and
+                            every J/K accumulation stay FP64. >= 0; 0 routes nothing to FP32 */
   int flags;             /* OR of JK_FLAG_* (0: none) */
   const char *tune_cache; /* JK_FLAG_TUNE: HOST path of a text file that keeps the choices
                              between runs (read if present, written after tuning); NULL: none */

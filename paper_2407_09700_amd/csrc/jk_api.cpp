@@ -151,6 +151,12 @@ struct jk_plan {
   std::vector<int> sbase, cbase, abase;          // [nmol+1] first shell / Cartesian AO / AO of each molecule
   std::vector<long long> mc_off, mf_off, ps_off; // [nmol+1] first element of each molecule's nc^2 / nao^2 / ns^2 block
   std::vector<int> mnc;                          // [nmol] Cartesian AO count of each molecule
+  // Molecules are kept in ascending Cartesian size (so that, inside a pair class, the pairs
+  // of the molecules whose exchange rows fit in LDS come first); perm[i] is the caller's
+  // index of molecule i, user_off/user_nao describe the caller's packed D, J, K.
+  std::vector<int> perm;
+  std::vector<long long> mf_user, user_off;
+  std::vector<int> user_nao;
   std::vector<double> schwarz;                   // per molecule ns x ns, at ps_off
   int npairs = 0;
   std::vector<int> cls_beg;                      // [16] first kept pair of each pair class
@@ -165,13 +171,14 @@ struct jk_plan {
   int *d_l = nullptr, *d_pure = nullptr, *d_cart_off = nullptr, *d_ao_off = nullptr;
   int *d_cart2shell = nullptr, *d_ao2shell = nullptr;
   int *d_sbase = nullptr, *d_cbase = nullptr, *d_abase = nullptr, *d_mnc = nullptr;
-  long long *d_mc_off = nullptr, *d_mf_off = nullptr, *d_ps_off = nullptr;
+  long long *d_mc_off = nullptr, *d_mf_off = nullptr, *d_ps_off = nullptr, *d_mf_user = nullptr;
   double *d_tsph = nullptr;
   double *d_Dc = nullptr, *d_Jc = nullptr, *d_Kc = nullptr, *d_Pblk = nullptr, *d_gmax = nullptr;
   unsigned long long *d_cap = nullptr, *d_nprim = nullptr;
   int *d_count = nullptr, *d_pair_npp = nullptr;
   int *d_pair_ca = nullptr, *d_pair_cb = nullptr, *d_pair_la = nullptr, *d_pair_lb = nullptr;
   int *d_segoff = nullptr, *d_segcnt = nullptr, *d_next = nullptr;
+  int *d_segoff32 = nullptr, *d_segcnt32 = nullptr, *d_count32 = nullptr;   // mixed precision
   long long *d_class_off = nullptr, *d_jp_off = nullptr, *d_room = nullptr;
   int *d_overflow = nullptr;
   int *h_overflow = nullptr;                     // pinned host copy of the overflow flag
@@ -224,12 +231,12 @@ void plan_free(jk_plan *p) {
   dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_pair_mol); dfree(p->d_cm_beg); dfree(p->d_l);
   dfree(p->d_pure); dfree(p->d_cart_off); dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell);
   dfree(p->d_sbase); dfree(p->d_cbase); dfree(p->d_abase); dfree(p->d_mnc); dfree(p->d_mc_off);
-  dfree(p->d_mf_off); dfree(p->d_ps_off); dfree(p->d_tsph); dfree(p->d_Dc);
+  dfree(p->d_mf_off); dfree(p->d_ps_off); dfree(p->d_mf_user); dfree(p->d_tsph); dfree(p->d_Dc);
   dfree(p->d_Jc); dfree(p->d_Kc); dfree(p->d_Pblk); dfree(p->d_gmax); dfree(p->d_cap); dfree(p->d_count);
   dfree(p->d_kets); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
   dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
   dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair);
-  dfree(p->d_room); dfree(p->d_overflow);
+  dfree(p->d_room); dfree(p->d_overflow); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
 }
@@ -352,7 +359,8 @@ int parse_opts(const jk_opts_t *opts, jk_plan *p) {
   if (!(opts->thresh >= 0.0) || !std::isfinite(opts->thresh)) return fail(JK_EINVAL, "thresh must be finite and >= 0");
   if (opts->precision != JK_FP64 && opts->precision != JK_MIXED)
     return fail(JK_EINVAL, "unknown precision %d", opts->precision);
-  if (opts->precision == JK_MIXED) return fail(JK_EUNSUPPORTED, "mixed precision is not built yet");
+  if (!(opts->fp32_cutoff >= 0.0) || !std::isfinite(opts->fp32_cutoff))
+    return fail(JK_EINVAL, "fp32_cutoff must be finite and >= 0");
   if (opts->flags & ~(JK_FLAG_PROFILE | JK_FLAG_GRAPH | JK_FLAG_TUNE)) return fail(JK_EINVAL, "unknown flags 0x%x", opts->flags);
   p->tau = opts->thresh;
   p->precision = opts->precision;
@@ -363,13 +371,13 @@ int parse_opts(const jk_opts_t *opts, jk_plan *p) {
 }
 
 // Plan of nmol molecules (a single-molecule plan is the batch of one).
-int plan_create(int nmol, const jk_basis_t *const *Bs, const double *const *coords, const int *natom,
+int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *coords_in, const int *natom,
                 const jk_opts_t *opts, jk_plan **out) {
   *out = nullptr;
   if (nmol <= 0) return fail(JK_EINVAL, "nmol must be positive (got %d)", nmol);
-  if (!Bs || !coords || !natom) return fail(JK_EINVAL, "basis, coords and natom arrays must not be NULL");
+  if (!Bs_in || !coords_in || !natom) return fail(JK_EINVAL, "basis, coords and natom arrays must not be NULL");
   for (int m = 0; m < nmol; ++m) {
-    int rc = validate(Bs[m], coords[m], natom[m]);
+    int rc = validate(Bs_in[m], coords_in[m], natom[m]);
     if (rc) {
       if (nmol > 1) g_err = "molecule " + std::to_string(m) + ": " + g_err;
       return rc;
@@ -396,6 +404,34 @@ int plan_create(int nmol, const jk_basis_t *const *Bs, const double *const *coor
     delete p;
     return code;
   };
+
+  // caller's packing, then the internal order (ascending Cartesian size, stable)
+  p->user_off.assign(nmol + 1, 0);
+  p->user_nao.assign(nmol, 0);
+  std::vector<int> ncu(nmol, 0);
+  for (int m = 0; m < nmol; ++m) {
+    int na = 0;
+    for (int s = 0; s < Bs_in[m]->nshell; ++s) {
+      const int l = Bs_in[m]->l[s];
+      ncu[m] += ncart(l);
+      na += (Bs_in[m]->pure[s] && l >= 2) ? 2 * l + 1 : ncart(l);
+    }
+    p->user_nao[m] = na;
+    p->user_off[m + 1] = p->user_off[m] + (long long)na * na;
+  }
+  p->perm.resize(nmol);
+  std::iota(p->perm.begin(), p->perm.end(), 0);
+  std::stable_sort(p->perm.begin(), p->perm.end(), [&](int x, int y) { return ncu[x] < ncu[y]; });
+  std::vector<const jk_basis_t *> Bv(nmol);
+  std::vector<const double *> Cv(nmol);
+  p->mf_user.resize(nmol);
+  for (int i = 0; i < nmol; ++i) {
+    Bv[i] = Bs_in[p->perm[i]];
+    Cv[i] = coords_in[p->perm[i]];
+    p->mf_user[i] = p->user_off[p->perm[i]];
+  }
+  const jk_basis_t *const *Bs = Bv.data();
+  const double *const *coords = Cv.data();
 
   // per-molecule layout
   p->sbase.assign(nmol + 1, 0); p->cbase.assign(nmol + 1, 0); p->abase.assign(nmol + 1, 0);
@@ -445,12 +481,13 @@ int plan_create(int nmol, const jk_basis_t *const *Bs, const double *const *coor
       (rc = dupload(&p->d_tsph, tsph)) || (rc = dupload(&p->d_sbase, p->sbase)) ||
       (rc = dupload(&p->d_cbase, p->cbase)) || (rc = dupload(&p->d_abase, p->abase)) ||
       (rc = dupload(&p->d_mnc, p->mnc)) || (rc = dupload(&p->d_mc_off, p->mc_off)) ||
-      (rc = dupload(&p->d_mf_off, p->mf_off)) || (rc = dupload(&p->d_ps_off, p->ps_off)))
+      (rc = dupload(&p->d_mf_off, p->mf_off)) || (rc = dupload(&p->d_ps_off, p->ps_off)) ||
+      (rc = dupload(&p->d_mf_user, p->mf_user)))
     return cleanup(rc);
   ShellInfo &S = p->S;
   S.l = p->d_l; S.pure = p->d_pure; S.cart_off = p->d_cart_off; S.ao_off = p->d_ao_off;
   S.cart2shell = p->d_cart2shell; S.ao2shell = p->d_ao2shell; S.tsph = p->d_tsph;
-  S.mc_off = p->d_mc_off; S.mf_off = p->d_mf_off; S.ps_off = p->d_ps_off;
+  S.mc_off = p->d_mc_off; S.mf_off = p->d_mf_off; S.ps_off = p->d_ps_off; S.mf_user = p->d_mf_user;
   S.cbase = p->d_cbase; S.abase = p->d_abase; S.sbase = p->d_sbase;
   S.toff[0] = S.toff[1] = 0; S.toff[2] = 0; S.toff[3] = 30; S.toff[4] = 100;
   S.nmol = nmol;
@@ -573,7 +610,10 @@ int plan_create(int nmol, const jk_basis_t *const *Bs, const double *const *coor
   p->jp_total = jt;
   if ((rc = dupload(&p->d_jp_off, p->jp_off)) || (rc = dalloc(&p->d_Jpair, (size_t)std::max(1LL, jt))) ||
       (rc = dalloc(&p->d_segoff, (size_t)p->npairs * NPAIRCLASS)) ||
-      (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)))
+      (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)) || (rc = dalloc(&p->d_count32, NQCLASS)))
+    return cleanup(rc);
+  if (p->precision == JK_MIXED && ((rc = dalloc(&p->d_segoff32, (size_t)p->npairs * NPAIRCLASS)) ||
+                                   (rc = dalloc(&p->d_segcnt32, (size_t)p->npairs * NPAIRCLASS))))
     return cleanup(rc);
 
   // build workspace
@@ -618,40 +658,55 @@ struct Launch {
   int cb;            // bra pair class
   int tier;          // fused: register tier; per class: -1
   int qc;            // per class: quartet class; fused: -1
+  int bra_beg, bra_end;   // bra pairs of the launch
+  int nc_max;        // fused: largest Cartesian size among the launch's molecules
   size_t lds;        // dynamic LDS bytes
   long long scratch_per_wg;
 };
 
 // Launches of one build. active[qc]: the class has work (eager) or may have work (recording).
+// Inside a pair class the pairs are ordered by molecule size, so the bra pairs of the
+// molecules whose two exchange rows fit in LDS form a prefix: that prefix runs in the fused
+// kernel, the rest in the per-class kernels.
 void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &out) {
   out.clear();
+  const int nmol = p->nmol;
   for (int cb = 0; cb < NPAIRCLASS; ++cb) {
-    if (p->cls_beg[cb + 1] == p->cls_beg[cb]) continue;
+    const int beg = p->cls_beg[cb], end = p->cls_beg[cb + 1];
+    if (beg == end) continue;
     const BraInfo &bi = g_bras[cb];
     const int na = ncart(bi.la), nbb = ncart(bi.lb);
     for (int tier = 0; tier < NTIERS; ++tier) {
       bool any = false;
       for (int ck = 0; ck <= cb; ++ck) any = any || (((bi.tier_mask[tier] >> ck) & 1) && active[qclass_index(cb, ck)]);
       if (!any) continue;
-      const size_t fused_lds =
-          ((size_t)(na + nbb) * p->nc_max + ((na * nbb + 1) & ~1)) * 8 + (size_t)bi.pool_bytes[tier];
-      if (bi.fusable[tier] && fused_lds <= FUSED_LDS_MAX) {
-        out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, fused_lds, bi.scratch_per_wg[tier]});
-      } else {
-        for (int ck = 0; ck <= cb; ++ck) {
-          const int qc = qclass_index(cb, ck);
-          if (!((bi.tier_mask[tier] >> ck) & 1) || !active[qc]) continue;
-          const ClassInfo &ci = g_classes[qc];
-          const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
-          out.push_back(Launch{NFUSED + qc, cb, -1, qc, lds, ci.scratch_per_wg});
+      int split = beg;
+      if (bi.fusable[tier]) {
+        const size_t fixed = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)bi.pool_bytes[tier];
+        const long long fit = fixed < FUSED_LDS_MAX ? (long long)((FUSED_LDS_MAX - fixed) / ((size_t)(na + nbb) * 8)) : 0;
+        int m = 0;
+        while (m < nmol && p->mnc[m] <= fit) ++m;      // molecules are in ascending size
+        split = p->cm_beg[(size_t)cb * (nmol + 1) + m];
+        if (split > beg) {
+          const int ncm = p->mnc[m - 1];
+          const size_t lds = (size_t)(na + nbb) * ncm * 8 + fixed;
+          out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, ncm, lds, bi.scratch_per_wg[tier]});
         }
+      }
+      if (split == end) continue;
+      for (int ck = 0; ck <= cb; ++ck) {
+        const int qc = qclass_index(cb, ck);
+        if (!((bi.tier_mask[tier] >> ck) & 1) || !active[qc]) continue;
+        const ClassInfo &ci = g_classes[qc];
+        const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
+        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 0, lds, ci.scratch_per_wg});
       }
     }
   }
 }
 
 int launch_grid(const jk_plan *p, const Launch &L) {
-  const int nb = p->cls_beg[L.cb + 1] - p->cls_beg[L.cb];
+  const int nb = L.bra_end - L.bra_beg;
   const int g = p->grid[L.slot] > 0 ? p->grid[L.slot] : GRID_TEAM_MAX;
   return std::max(1, std::min(nb, g));
 }
@@ -675,6 +730,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
   HIPCHK(launch_fill_u64(p->d_nprim, NQCLASS, 0ull, st));
   HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
+  HIPCHK(launch_fill_i32(p->d_count32, NQCLASS, 0, st));
   HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
   HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
   HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
@@ -695,7 +751,14 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   A.cap = p->d_cap;
   A.segoff = p->d_segoff;
   A.segcnt = p->d_segcnt;
+  A.segoff32 = p->d_segoff32;
+  A.segcnt32 = p->d_segcnt32;
   A.count = p->d_count;
+  A.count32 = p->d_count32;
+  A.fp32_cut = p->precision == JK_MIXED ? p->fp32_cutoff : 0.0;
+  A.f32_classes[0] = A.f32_classes[1] = 0ull;
+  for (int qc = 0; qc < NQCLASS; ++qc)   // FP32 bodies exist for the lane-per-quartet classes
+    if (!g_classes[qc].team) A.f32_classes[qc >> 6] |= 1ull << (qc & 63);
   A.nprim = p->d_nprim;
   A.class_off = p->d_class_off;
   A.room = p->d_room;
@@ -750,6 +813,8 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   J_.class_off = p->d_class_off;
   J_.segoff = p->d_segoff;
   J_.segcnt = p->d_segcnt;
+  J_.segoff32 = p->d_segoff32;
+  J_.segcnt32 = p->d_segcnt32;
   J_.Dc = p->d_Dc;
   J_.Kc = p->d_Kc;
   J_.mbase = p->d_mc_off;
@@ -757,14 +822,14 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   J_.Jpair = p->d_Jpair;
   J_.jp_off = p->d_jp_off;
   J_.cls_beg = p->d_cls_beg;
-  J_.nc_max = p->nc_max;
   J_.scratch = p->d_scratch;
   for (const Launch &L : launches) {
     const int grid = launch_grid(p, L);
     if (L.scratch_per_wg * (long long)grid > p->scratch_doubles)
       return fail(JK_EDEVICE, "internal: team scratch not sized for launch slot %d", L.slot);
-    J_.bra_beg = p->cls_beg[L.cb];
-    J_.bra_end = p->cls_beg[L.cb + 1];
+    J_.bra_beg = L.bra_beg;
+    J_.bra_end = L.bra_end;
+    J_.nc_max = L.nc_max;
     J_.scratch_per_wg = L.scratch_per_wg;
     J_.next = p->d_next + L.slot;
     if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot], st));
@@ -926,15 +991,18 @@ int plan_run(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) 
 int plan_stats(const jk_plan *plan, jk_stats_t *out) {
   *out = plan->stats;
   if (plan->d_count) {
-    int cnt[NQCLASS];
+    int cnt[NQCLASS], c32[NQCLASS];
     unsigned long long np[NQCLASS];
     HIPCHK(hipStreamSynchronize(plan->last_stream));
     HIPCHK(hipMemcpy(cnt, plan->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(c32, plan->d_count32, sizeof(c32), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(np, plan->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
     out->kept_quartets = 0;
+    out->kept_fp32 = 0;
     out->prim_quartets = 0;
     for (int c = 0; c < NQCLASS; ++c) {
       out->kept_quartets += cnt[c];
+      out->kept_fp32 += c32[c];
       out->prim_quartets += (long long)np[c];
     }
   }
@@ -1137,8 +1205,8 @@ int jk_batch_offsets(const jk_batch_t *b, long long *off, int *nao) {
   if (!b || !b->p) return fail(JK_EINVAL, "batch is NULL");
   const jk_plan *p = b->p;
   for (int m = 0; m <= p->nmol; ++m) {
-    if (off) off[m] = p->mf_off[m];
-    if (nao && m < p->nmol) nao[m] = p->abase[m + 1] - p->abase[m];
+    if (off) off[m] = p->user_off[m];
+    if (nao && m < p->nmol) nao[m] = p->user_nao[m];
   }
   return JK_OK;
 }

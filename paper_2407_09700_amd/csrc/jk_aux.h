@@ -12,7 +12,8 @@ struct ShellInfo {            // device pointers; molecules are stored one after
   const int *cart2shell;      // per concatenated Cartesian AO -> global shell
   const int *ao2shell;        // per concatenated final AO -> global shell
   const long long *mc_off;    // [nmol+1] first element of each molecule's nc_m x nc_m block
-  const long long *mf_off;    // [nmol+1] first element of each molecule's nao_m x nao_m block
+  const long long *mf_off;    // [nmol+1] prefix of the nao_m^2 block sizes (iteration order)
+  const long long *mf_user;   // [nmol] first element of each molecule's block in the caller's D, J, K
   const long long *ps_off;    // [nmol+1] first element of each molecule's shell-pair block
   const int *cbase, *abase, *sbase;   // [nmol+1] first Cartesian AO / final AO / shell of each molecule
   const double *tsph;         // T2 | T3 | T4 row-major
@@ -31,13 +32,17 @@ struct ScreenArgs {           // device pointers
   const double *gmax;         // global maximum of |D_cart|
   unsigned long long *cap;    // [120] size of each class region (k_capacity)
   int *segoff;                // [npairs * 15] segment offset in the class region (k_capacity)
-  int *segcnt;                // [npairs * 15] kept kets of the segment (k_screen)
+  int *segcnt;                // [npairs * 15] kept FP64 kets of the segment (k_screen)
+  int *segoff32, *segcnt32;   // [npairs * 15] FP32 part of the segment (mixed precision) or null
   int *count;                 // [120] kept quartets per class (k_screen)
+  int *count32;               // [120] of those, evaluated in FP32
   unsigned long long *nprim;  // [120] primitive quartets of the kept quartets (k_screen)
   const long long *class_off; // [120] first entry of each class region in kets
   const long long *room;      // [120] entries available to each class region (k_class_off)
   int *kets;
   double tau;
+  double fp32_cut;            // quartets with I_ab I_cd P below this go to FP32 (0: none) ...
+  unsigned long long f32_classes[2];   // ... if their class (bit qc) has an FP32 body
   int npairs, nmol;
 };
 

@@ -35,7 +35,7 @@ __global__ void k_dcart(ShellInfo S, const double *__restrict__ D, double *__res
     const double *Ta = pa ? S.tsph + S.toff[la] : nullptr;
     const double *Tb = pb ? S.tsph + S.toff[lb] : nullptr;
     const int na = ncart(la), nb = ncart(lb);
-    const double *Dm = D + S.mf_off[m];
+    const double *Dm = D + S.mf_user[m];
     double v = 0.0;
     for (int i = 0; i < ma; ++i) {
       const int mu = S.ao_off[sa] + (pa ? i : ia);
@@ -144,9 +144,9 @@ __global__ void k_class_off(const unsigned long long *cap, long long *class_off,
 // predicate I_ab I_cd P >= tau (P = max |D_cart| over the six shell-pair blocks), writes the
 // kept kets to the front of the (bra, class) segment and its count.
 __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
-  __shared__ int s_cnt[NQCLASS];
+  __shared__ int s_cnt[NQCLASS], s_c32[NQCLASS];
   __shared__ unsigned long long s_np[NQCLASS];
-  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) { s_cnt[t] = 0; s_np[t] = 0ull; }
+  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) { s_cnt[t] = 0; s_c32[t] = 0; s_np[t] = 0ull; }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -177,11 +177,12 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
         if (left < n) n = left > 0 ? (int)left : 0;
       }
       int *out = A.kets + A.class_off[qc] + so;
-      int kept = 0;
+      const double cut = ((A.f32_classes[qc >> 6] >> (qc & 63)) & 1ull) ? A.fp32_cut : 0.0;
+      int kept = 0, kept32 = 0;
       unsigned long long np = 0ull;
       for (int k0 = 0; k0 < n; k0 += 64) {
         const int k = k0 + lane;
-        bool keep = false;
+        bool keep = false, lo = false;
         if (k < n) {
           const int kg = kb + k;
           const int sc = A.pair_sa[kg] - sb0, sd = A.pair_sb[kg] - sb0;
@@ -191,21 +192,33 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
           p = fmax(p, Pa[sd]);
           p = fmax(p, Pb[sc]);
           p = fmax(p, Pb[sd]);
-          keep = Ib * A.pairI[kg] * p >= tau;
+          const double bound = Ib * A.pairI[kg] * p;
+          keep = bound >= tau;
+          lo = keep && bound < cut;            // mixed precision: evaluated in FP32
           if (keep) np += nppb * (unsigned long long)A.pair_npp[kg];
         }
-        const unsigned long long mask = __ballot(keep);
-        if (keep) out[kept + __popcll(mask & ((1ull << lane) - 1ull))] = kb + k;
-        kept += __popcll(mask);
+        // FP64 kets fill the segment from the front, FP32 kets from the back
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const unsigned long long m64 = __ballot(keep && !lo), m32 = __ballot(lo);
+        if (keep && !lo) out[kept + __popcll(m64 & below)] = kb + k;
+        if (lo) out[n - 1 - (kept32 + __popcll(m32 & below))] = kb + k;
+        kept += __popcll(m64);
+        kept32 += __popcll(m32);
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
       if (lane == 0) {
-        A.segcnt[(size_t)i * NPAIRCLASS + ck] = kept;
-        if (kept) {
-          atomicAdd(&s_cnt[qc], kept);
+        const size_t sg = (size_t)i * NPAIRCLASS + ck;
+        A.segcnt[sg] = kept;
+        if (A.segcnt32) {
+          A.segcnt32[sg] = kept32;
+          A.segoff32[sg] = (int)(so + n - kept32);
+        }
+        if (kept + kept32) {
+          atomicAdd(&s_cnt[qc], kept + kept32);
           atomicAdd(&s_np[qc], np);
         }
+        if (kept32) atomicAdd(&s_c32[qc], kept32);
       }
     }
   }
@@ -214,6 +227,7 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
     if (s_cnt[t]) {
       atomicAdd(&A.count[t], s_cnt[t]);
       atomicAdd(&A.nprim[t], s_np[t]);
+      if (s_c32[t]) atomicAdd(&A.count32[t], s_c32[t]);
     }
 }
 
@@ -266,8 +280,8 @@ __global__ void k_finalize(ShellInfo S, const double *__restrict__ Jc, const dou
       vj = fma(ta, rj, vj);
       vk = fma(ta, rk, vk);
     }
-    J[t] = vj;
-    K[t] = vk;
+    J[S.mf_user[m] + r] = vj;
+    K[S.mf_user[m] + r] = vk;
   }
 }
 

@@ -178,20 +178,19 @@ __device__ __forceinline__ void rys_root1(double T, int n, double &u, double &w)
 }
 
 // ------------------------------------------------------------------ 2D recurrence
-template <int E, int F>
-__device__ __forceinline__ void vrr2d(double (&G)[E + 1][F + 1], double g00, double c00, double c00p, double b10,
-                                      double b01, double b00) {
+template <int E, int F, typename R = double>
+__device__ __forceinline__ void vrr2d(R (&G)[E + 1][F + 1], R g00, R c00, R c00p, R b10, R b01, R b00) {
   G[0][0] = g00;
   if constexpr (E > 0) G[1][0] = c00 * g00;
 #pragma unroll
-  for (int e = 1; e < E; ++e) G[e + 1][0] = fma(c00, G[e][0], (double)e * b10 * G[e - 1][0]);
+  for (int e = 1; e < E; ++e) G[e + 1][0] = fma(c00, G[e][0], (R)e * b10 * G[e - 1][0]);
 #pragma unroll
   for (int f = 0; f < F; ++f) {
 #pragma unroll
     for (int e = 0; e <= E; ++e) {
-      double v = c00p * G[e][f];
-      if (f > 0) v = fma((double)f * b01, G[e][f - 1], v);
-      if (e > 0) v = fma((double)e * b00, G[e - 1][f], v);
+      R v = c00p * G[e][f];
+      if (f > 0) v = fma((R)f * b01, G[e][f - 1], v);
+      if (e > 0) v = fma((R)e * b00, G[e - 1][f], v);
       G[e][f + 1] = v;
     }
   }

@@ -27,16 +27,18 @@ struct SmallCfg {
   static constexpr int NG = NA * NB * NC * ND;
 };
 
-template <int LA, int LB, int LC, int LD>
+// R: type of the 2D integrals, their products and the transfer (double, or float for the
+// FP32 quartets of mixed precision; roots, weights and the per-primitive scalars stay double).
+template <int LA, int LB, int LC, int LD, typename R = double>
 __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, const PrimPair *__restrict__ pp,
-                                          double (&g)[SmallCfg<LA, LB, LC, LD>::NG]) {
+                                          R (&g)[SmallCfg<LA, LB, LC, LD>::NG]) {
   using C = SmallCfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
-  double acc[NE * NF];
+  R acc[NE * NF];
 #pragma unroll
-  for (int i = 0; i < NE * NF; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NE * NF; ++i) acc[i] = (R)0;
 
   for (int ib = 0; ib < bra.npp; ++ib) {
     const PrimPair pb = pp[bra.pp_off + ib];
@@ -48,13 +50,14 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
       const double hq = 0.5 / pk.p;
       auto root = [&](double un, double wn) {
         const double uq = un * Q.pq_inv;
-        const double b00 = 0.5 * uq;
-        const double b10 = hp * (1.0 - uq * Q.q);
-        const double b01 = hq * (1.0 - uq * Q.p);
-        double Gx[E + 1][F + 1], Gy[E + 1][F + 1], Gz[E + 1][F + 1];
-        vrr2d<E, F>(Gx, 1.0, Q.PA[0] - uq * Q.q * Q.PQ[0], Q.QC[0] + uq * Q.p * Q.PQ[0], b10, b01, b00);
-        vrr2d<E, F>(Gy, 1.0, Q.PA[1] - uq * Q.q * Q.PQ[1], Q.QC[1] + uq * Q.p * Q.PQ[1], b10, b01, b00);
-        vrr2d<E, F>(Gz, wn * Q.pref, Q.PA[2] - uq * Q.q * Q.PQ[2], Q.QC[2] + uq * Q.p * Q.PQ[2], b10, b01, b00);
+        const R b00 = (R)(0.5 * uq);
+        const R b10 = (R)(hp * (1.0 - uq * Q.q));
+        const R b01 = (R)(hq * (1.0 - uq * Q.p));
+        R Gx[E + 1][F + 1], Gy[E + 1][F + 1], Gz[E + 1][F + 1];
+        vrr2d<E, F, R>(Gx, (R)1, (R)(Q.PA[0] - uq * Q.q * Q.PQ[0]), (R)(Q.QC[0] + uq * Q.p * Q.PQ[0]), b10, b01, b00);
+        vrr2d<E, F, R>(Gy, (R)1, (R)(Q.PA[1] - uq * Q.q * Q.PQ[1]), (R)(Q.QC[1] + uq * Q.p * Q.PQ[1]), b10, b01, b00);
+        vrr2d<E, F, R>(Gz, (R)(wn * Q.pref), (R)(Q.PA[2] - uq * Q.q * Q.PQ[2]), (R)(Q.QC[2] + uq * Q.p * Q.PQ[2]), b10,
+                       b01, b00);
 #pragma unroll
         for (int ie = 0; ie < NE; ++ie) {
 #pragma unroll
@@ -80,19 +83,19 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
     }
   }
 
-  const double AB[3] = {bra.A[0] - bra.B[0], bra.A[1] - bra.B[1], bra.A[2] - bra.B[2]};
-  const double CD[3] = {ket.A[0] - ket.B[0], ket.A[1] - ket.B[1], ket.A[2] - ket.B[2]};
-  double abp[3][LB + 1], cdp[3][LD + 1];
+  const R AB[3] = {(R)(bra.A[0] - bra.B[0]), (R)(bra.A[1] - bra.B[1]), (R)(bra.A[2] - bra.B[2])};
+  const R CD[3] = {(R)(ket.A[0] - ket.B[0]), (R)(ket.A[1] - ket.B[1]), (R)(ket.A[2] - ket.B[2])};
+  R abp[3][LB + 1], cdp[3][LD + 1];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    abp[d][0] = 1.0;
+    abp[d][0] = (R)1;
 #pragma unroll
     for (int k = 1; k <= LB; ++k) abp[d][k] = abp[d][k - 1] * AB[d];
-    cdp[d][0] = 1.0;
+    cdp[d][0] = (R)1;
 #pragma unroll
     for (int k = 1; k <= LD; ++k) cdp[d][k] = cdp[d][k - 1] * CD[d];
   }
-  double hb[NA * NB * NF];
+  R hb[NA * NB * NF];
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
 #pragma unroll
@@ -101,7 +104,7 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
       const int ax = CT.x[A0 + a], ay = CT.y[A0 + a], az = CT.z[A0 + a];
       const int bx = CT.x[B0 + b], by = CT.y[B0 + b], bz = CT.z[B0 + b];
 #pragma unroll
-      for (int jf = 0; jf < NF; ++jf) hb[(a * NB + b) * NF + jf] = 0.0;
+      for (int jf = 0; jf < NF; ++jf) hb[(a * NB + b) * NF + jf] = (R)0;
 #pragma unroll
       for (int kx = 0; kx <= LB; ++kx) {
         if (kx > bx) continue;
@@ -111,8 +114,8 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 #pragma unroll
           for (int kz = 0; kz <= LB; ++kz) {
             if (kz > bz) continue;
-            const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * abp[0][bx - kx] *
-                              abp[1][by - ky] * abp[2][bz - kz];
+            const R cf = (R)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * abp[0][bx - kx] *
+                         abp[1][by - ky] * abp[2][bz - kz];
             const int ie = CT.idx[ax + kx][ay + ky][az + kz] - E0;
 #pragma unroll
             for (int jf = 0; jf < NF; ++jf)
@@ -130,7 +133,7 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
       const int cx = CT.x[C0 + c], cy = CT.y[C0 + c], cz = CT.z[C0 + c];
       const int dx = CT.x[D0 + d], dy = CT.y[D0 + d], dz = CT.z[D0 + d];
 #pragma unroll
-      for (int ab = 0; ab < NA * NB; ++ab) g[ab * NC * ND + c * ND + d] = 0.0;
+      for (int ab = 0; ab < NA * NB; ++ab) g[ab * NC * ND + c * ND + d] = (R)0;
 #pragma unroll
       for (int kx = 0; kx <= LD; ++kx) {
         if (kx > dx) continue;
@@ -140,8 +143,8 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 #pragma unroll
           for (int kz = 0; kz <= LD; ++kz) {
             if (kz > dz) continue;
-            const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * cdp[0][dx - kx] *
-                              cdp[1][dy - ky] * cdp[2][dz - kz];
+            const R cf = (R)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * cdp[0][dx - kx] *
+                         cdp[1][dy - ky] * cdp[2][dz - kz];
             const int jf = CT.idx[cx + kx][cy + ky][cz + kz] - F0;
 #pragma unroll
             for (int ab = 0; ab < NA * NB; ++ab)

@@ -52,7 +52,9 @@ struct JKArgs {
   const int *kets;              // segment storage (ket pair indices)
   const long long *class_off;   // [120] first entry of each class region in kets
   const int *segoff;            // [npairs * 15] segment offset inside the class region
-  const int *segcnt;            // [npairs * 15] kept kets of the segment
+  const int *segcnt;            // [npairs * 15] kept kets of the segment (FP64 part)
+  const int *segoff32;          // [npairs * 15] start of the FP32 part of the segment (mixed precision) or null
+  const int *segcnt32;          // [npairs * 15] kets of the FP32 part or null
   const double *Dc;             // Cartesian densities, one nc_m x nc_m block per molecule
   double *Kc;                   // Cartesian exchange accumulators, same layout
   const long long *mbase;       // [nmol] first element of each molecule's block in Dc / Kc
@@ -83,7 +85,9 @@ __device__ __forceinline__ void k_update(double *Krow, double *Km, int nc, int r
 }
 
 // ------------------------------------------------------------------ lane-per-quartet body
-template <int LA, int LB, int LC, int LD, bool KLDS>
+// R: arithmetic type of the integral evaluation (double, or float for the FP32 quartets of
+// mixed precision); the digestion always runs in double.
+template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double>
 __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                               double (&jab)[ncart(LA) * ncart(LB)]) {
   using C = SmallCfg<LA, LB, LC, LD>;
@@ -102,7 +106,14 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
     const int ki = kl[k];
     const Pair ket = A.pairs[ki];
     double g[C::NG];
-    small_eri<LA, LB, LC, LD>(bra, ket, A.pp, g);
+    if constexpr (sizeof(R) == sizeof(double)) {
+      small_eri<LA, LB, LC, LD>(bra, ket, A.pp, g);
+    } else {
+      R gr[C::NG];
+      small_eri<LA, LB, LC, LD, R>(bra, ket, A.pp, gr);
+#pragma unroll
+      for (int e = 0; e < C::NG; ++e) g[e] = (double)gr[e];
+    }
     const double s = sym_factor(bra, ket, bi, ki);
     const int oc = ket.ca, od = ket.cb;
     double Dcd[NC * ND];
@@ -350,7 +361,8 @@ constexpr int team_block() {
   else return 256;
 }
 
-template <int LA, int LB, int LC, int LD, bool KLDS>
+// R = float selects the FP32 lane body; the team bodies always evaluate in double.
+template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double>
 __device__ __forceinline__ void jk_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow, double *jab_s,
                                         double *pool, double (&jab)[ncart(LA) * ncart(LB)]) {
   if constexpr (use_team2<LA, LB, LC, LD>())
@@ -358,7 +370,7 @@ __device__ __forceinline__ void jk_body(const JKArgs &A, int bi, const int *kl, 
   else if constexpr (use_team<LA, LB, LC, LD>())
     jk_team_body<LA, LB, LC, LD, KLDS>(A, bi, kl, cnt, Krow, jab_s, pool);
   else
-    jk_small_body<LA, LB, LC, LD, KLDS>(A, bi, kl, cnt, Krow, jab);
+    jk_small_body<LA, LB, LC, LD, KLDS, R>(A, bi, kl, cnt, Krow, jab);
 }
 
 // adds the per-lane bra Coulomb partials into jab_s (LDS), one wave-reduced value per wave
@@ -373,17 +385,17 @@ __device__ __forceinline__ void jab_reduce(double (&jab)[NAB], double *jab_s) {
   }
 }
 
-template <int LA, int LB, int TIER, int P>
+template <int LA, int LB, int TIER, int P, typename R = double>
 __device__ __forceinline__ void ket_dispatch(int ck, const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                              double *jab_s, double *pool, double (&jab)[ncart(LA) * ncart(LB)]) {
   if constexpr (P <= pair_class(LA, LB)) {
     if constexpr (tier_of<LA, LB, pc_la(P), pc_lb(P)>() == TIER) {
       if (ck == P) {
-        jk_body<LA, LB, pc_la(P), pc_lb(P), true>(A, bi, kl, cnt, Krow, jab_s, pool, jab);
+        jk_body<LA, LB, pc_la(P), pc_lb(P), true, R>(A, bi, kl, cnt, Krow, jab_s, pool, jab);
         return;
       }
     }
-    ket_dispatch<LA, LB, TIER, P + 1>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
+    ket_dispatch<LA, LB, TIER, P + 1, R>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
   }
 }
 
@@ -464,10 +476,22 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
     constexpr int mask = tier_mask<LA, LB, TIER>();
     for (int ck = 0; ck <= cb; ++ck) {
       if (!((mask >> ck) & 1)) continue;
-      const int cnt = A.segcnt[(size_t)bi * NPAIRCLASS + ck];
-      if (cnt == 0) continue;
-      const int *kl = A.kets + A.class_off[qclass_index(cb, ck)] + A.segoff[(size_t)bi * NPAIRCLASS + ck];
-      ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
+      const size_t sg = (size_t)bi * NPAIRCLASS + ck;
+      const int *cls_kets = A.kets + A.class_off[qclass_index(cb, ck)];
+      const int cnt = A.segcnt[sg];
+      const int cnt32 = A.segcnt32 ? A.segcnt32[sg] : 0;
+      if constexpr (TIER == 2) {
+        // team bodies: the FP32 part of the segment is evaluated in double as well
+        for (int part = 0; part < 2; ++part) {
+          const int n = part ? cnt32 : cnt;
+          if (n) ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]), n, Krow,
+                                               jab_s, pool, jab);
+        }
+      } else {
+        if (cnt) ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, cls_kets + A.segoff[sg], cnt, Krow, jab_s, pool, jab);
+        if (cnt32)
+          ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, cls_kets + A.segoff32[sg], cnt32, Krow, jab_s, pool, jab);
+      }
     }
     jab_reduce<NA * NB>(jab, jab_s);
     __syncthreads();
@@ -508,18 +532,34 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
     const int u = s_unit;
     if (u >= nunits) break;
     const int bi = A.bra_beg + u;
-    const int cnt = A.segcnt[(size_t)bi * NPAIRCLASS + ck];
-    if (cnt > 0) {
-      const int *kl = A.kets + A.class_off[qclass_index(cb, ck)] + A.segoff[(size_t)bi * NPAIRCLASS + ck];
+    const size_t sg = (size_t)bi * NPAIRCLASS + ck;
+    const int cnt = A.segcnt[sg];
+    const int cnt32 = A.segcnt32 ? A.segcnt32[sg] : 0;
+    if (cnt + cnt32 > 0) {
+      const int *cls_kets = A.kets + A.class_off[qclass_index(cb, ck)];
       if constexpr (use_team<LA, LB, LC, LD>() && !use_team2<LA, LB, LC, LD>()) {
-        double jab[1];
-        jk_team_body<LA, LB, LC, LD, false>(A, bi, kl, cnt, nullptr, jab_s, pool);
-        (void)jab;
+        for (int part = 0; part < 2; ++part) {   // FP32 part in double as well
+          const int n = part ? cnt32 : cnt;
+          if (n) jk_team_body<LA, LB, LC, LD, false>(A, bi, cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]), n,
+                                                     nullptr, jab_s, pool);
+        }
+      } else if constexpr (use_team2<LA, LB, LC, LD>()) {
+        double jab[NA * NB];
+#pragma unroll
+        for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
+        for (int part = 0; part < 2; ++part) {
+          const int n = part ? cnt32 : cnt;
+          if (n) jk_body<LA, LB, LC, LD, false>(A, bi, cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]), n, nullptr,
+                                                jab_s, pool, jab);
+        }
+        jab_reduce<NA * NB>(jab, jab_s);
       } else {
         double jab[NA * NB];
 #pragma unroll
         for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
-        jk_body<LA, LB, LC, LD, false>(A, bi, kl, cnt, nullptr, jab_s, pool, jab);
+        if (cnt) jk_body<LA, LB, LC, LD, false>(A, bi, cls_kets + A.segoff[sg], cnt, nullptr, jab_s, pool, jab);
+        if (cnt32)
+          jk_body<LA, LB, LC, LD, false, float>(A, bi, cls_kets + A.segoff32[sg], cnt32, nullptr, jab_s, pool, jab);
         jab_reduce<NA * NB>(jab, jab_s);
       }
       __syncthreads();
