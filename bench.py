@@ -21,10 +21,59 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 METRIC = "J+K build ms and screened quartets/s; FP32-mixed & batched vs FP64 at stated dE"
+WORKLOAD_BASIS = {1: "uniform cube, 3s1p Cartesian", 2: "3-atom clusters, 3s2p1d (spherical d)",
+                  3: "uniform cube, 4s3p2d1f1g spherical", 4: "3-atom clusters, 3s2p1d (spherical d)"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE),
+# scaled by the same counters read for a plain copy of known size (bench.py --copy-probe).
+# Valid only for the kernel sources it was taken from: SOURCE_HASH is the hash of csrc/ then.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2407_09700_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """Bytes per launch of `kernel` from profiles/traffic.txt (lines 'key value'), or None
+    when the file is absent, names another kernel or was taken from other sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        parts = line.split()
+        if len(parts) == 2 and not line.startswith("#"):
+            kv[parts[0]] = parts[1]
+    if kv.get("kernel") != kernel or kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(nbytes):
+    """A plain device copy of nbytes (calibration of the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = nbytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "launches": 5}), flush=True)
 
 
 def cpu_baseline(mol, target_s=12.0):
@@ -144,7 +193,12 @@ def main():
     ap.add_argument("--natom", type=int, default=None, help="smaller molecule of the same recipe (debug)")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and batched measurements")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); the J/K path "
               f"would shard by bra-pair tiles with one all-reduce of J and K, which is not built.", file=sys.stderr)
@@ -164,15 +218,18 @@ def main():
     K = torch.empty_like(D)
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         plan.execute(D, J, K)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log(f"warmup {w} done")
 
     per_class = {}
     prep_ms = fin_ms = 0.0
     t = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         plan.execute(D, J, K)
+        if args.steps <= 3:
+            log(f"step {k} enqueued")
         for e in plan.profile():          # HIP events recorded on this stream inside the step
             if e["kind"] == 1:
                 prep_ms += e["ms"]
@@ -215,13 +272,13 @@ def main():
         "metric": METRIC, "value": value, "unit": "screened quartets/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded)",
-        "config": {"workload": f"cfg{args.config}: {mol.natom}-atom clustered 3s2p1d (spherical d), "
+        "config": {"workload": f"cfg{args.config}: {mol.natom} atoms, {WORKLOAD_BASIS.get(args.config, '')}, "
                                f"{mol.nbf} AOs, Schwarz tau {mol.thresh:g}, FP64",
                    "natom": mol.natom, "nao": mol.nbf, "nshell": mol.nshell, "tau": mol.thresh,
                    "kept_quartets": kept, "prim_quartets": st["prim_quartets"], "plan_ms": round(plan_ms, 2)},
         "roofline": {"bound": "alu", "kernel": kname(dom_key, dom),
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kname(dom_key, dom)),
                      "kernel_ms": dom_ms},
         "breakdown": {"prep_ms": prep_ms / args.steps, "class_kernels_ms": class_ms,
                       "finalize_ms": fin_ms / args.steps, "all_classes_tflops": tot_flops / (class_ms * 1e-3) / 1e12,

@@ -124,14 +124,15 @@ int jk_stats(const jk_plan_t *plan, jk_stats_t *out);
 /* Per-launch profile of the last jk_plan_execute of a plan created with JK_FLAG_PROFILE.
  * One entry per integral launch (kind 0): either one quartet class (lc, ld >= 0) or one
  * register tier of a bra class fused over its ket classes (lc = -1, ld = tier, team = 2),
- * plus the preparation launches
- * (kind 1: density transform, block maxima, screening) and the final symmetrise and
- * transform (kind 2). ms is the HIP-event time of the launch on the caller's stream;
- * flops is the algorithmic count of the class, prim_quartets * 3 N nc(a)nc(b)nc(c)nc(d)
- * (the three-operand Rys product of section 2 per root) plus quartets * 12
- * nc(a)nc(b)nc(c)nc(d) (the six multiply-adds per integral of the digestion, Algorithm
- * 2). out is HOST memory of max_entries entries; *n_entries receives the count.
- * Synchronises the plan's last stream. */
+ * plus the preparation launches (kind 1: density transform, block maxima, screening) and
+ * the final symmetrise and transform (kind 2). ms is the HIP-event time of the launch on the
+ * caller's stream. flops is the algorithmic operation count of the launch's quartets (an FMA
+ * counts 2), from the steps of the method: per primitive quartet the pair-quartet scalars,
+ * and per Rys root (section 2) the root and weight, the recurrence coefficients, the 2D
+ * recurrences in x, y, z and the three-operand product per [e0|f0] element; per contracted
+ * quartet the two transfers and the six multiply-adds per integral of the digestion
+ * (Algorithm 2). out is HOST memory of max_entries entries; *n_entries receives the count.
+ * Synchronises the plan's last stream. Graph replays are not profiled. */
 typedef struct {
   int kind;                     /* 0 class kernel, 1 preparation, 2 finalisation */
   int la, lb, lc, ld;           /* class (kind 0); lc = -1, ld = tier for a fused launch */

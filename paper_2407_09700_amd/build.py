@@ -13,7 +13,8 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libjk.so")
+LIB = os.environ.get("JK_LIB_OUT", os.path.join(HERE, "libjk.so"))
+BUILD = os.environ.get("JK_BUILD_DIR", BUILD)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["jk_api.cpp", "jk_aux.hip"] + [f"classes_{c}.hip" for c in
@@ -35,7 +36,8 @@ def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     if not force and not _stale(src, obj):
         return obj
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *os.environ.get("JK_DEFINES", "").split(), "-x", "hip", "-c", os.path.join(CSRC, src),
+           "-o", obj]
     if os.environ.get("JK_RESOURCE_USAGE"):
         cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -111,6 +111,51 @@ void solid_harmonics(int l, double *T) {
   }
 }
 
+// ------------------------------------------------------------------ algorithmic operation counts
+// Floating-point operations of the method for one class (an FMA counts 2), counted from its
+// steps as the kernels run them (no divergence, masking or recomputation):
+//  per primitive quartet:  scalars p, q, P-Q, P-A, Q-C, rho, T, prefactor (24);
+//                          per root: interpolated u and w (2 x 11 FMAs = 44), the recurrence
+//                          coefficients and the three C00/C00' pairs (14), the 2D recurrence in
+//                          three directions, and the Rys product over the [e0|f0] elements
+//                          (one multiply and one FMA = 3 per element, the paper's count);
+//  per contracted quartet: the two binomial transfers and the digestion (six FMAs per
+//                          integral, Algorithm 2).
+double vrr_ops(int E, int F) {
+  double n = E > 0 ? 1 : 0;                                  // G[1][0]
+  for (int e = 1; e < E; ++e) n += (e > 1 ? 1 : 0) + 1 + 2;  // e*b10, *G, fma
+  for (int e = 2; e <= E; ++e) n += 1;                       // e*b00 (hoisted)
+  for (int f = 0; f < F; ++f) {
+    if (f > 1) n += 1;                                       // f*b01 (hoisted)
+    for (int e = 0; e <= E; ++e) n += 1 + (f > 0 ? 2 : 0) + (e > 0 ? 2 : 0);
+  }
+  return n;
+}
+
+int range_count_h(int l0, int l1) {
+  int n = 0;
+  for (int l = l0; l <= l1; ++l) n += ncart(l);
+  return n;
+}
+
+// transfer terms of one shell: sum over its Cartesian components of (x+1)(y+1)(z+1)
+int transfer_terms(int l) {
+  int n = 0;
+  for (int x = l; x >= 0; --x)
+    for (int y = l - x; y >= 0; --y) n += (x + 1) * (y + 1) * (l - x - y + 1);
+  return n;
+}
+
+void class_ops(int la, int lb, int lc, int ld, double *per_prim, double *per_quartet) {
+  const int E = la + lb, F = lc + ld, N = (E + F) / 2 + 1;
+  const int NE = range_count_h(la, E), NF = range_count_h(lc, F);
+  const int na = ncart(la), nb = ncart(lb), nc = ncart(lc), nd = ncart(ld);
+  *per_prim = 24.0 + N * (44.0 + 14.0 + 3.0 * vrr_ops(E, F) + 3.0 * NE * NF);
+  const double bra = (double)na * transfer_terms(lb) * (3.0 + 2.0 * NF);
+  const double ket = (double)nc * transfer_terms(ld) * (3.0 + 2.0 * na * nb);
+  *per_quartet = bra + ket + 12.0 * na * nb * nc * nd;
+}
+
 template <class T>
 int dalloc(T **p, size_t n) {
   *p = nullptr;
@@ -167,7 +212,7 @@ struct jk_plan {
   PrimPair *d_pp = nullptr;
   double *d_pairI = nullptr;
   int *d_pair_cls = nullptr, *d_pair_sa = nullptr, *d_pair_sb = nullptr, *d_cls_beg = nullptr;
-  int *d_pair_mol = nullptr, *d_cm_beg = nullptr;
+  int *d_pair_mol = nullptr, *d_bin_beg = nullptr, *d_cm_bin = nullptr;
   int *d_l = nullptr, *d_pure = nullptr, *d_cart_off = nullptr, *d_ao_off = nullptr;
   int *d_cart2shell = nullptr, *d_ao2shell = nullptr;
   int *d_sbase = nullptr, *d_cbase = nullptr, *d_abase = nullptr, *d_mnc = nullptr;
@@ -228,7 +273,7 @@ void plan_free(jk_plan *p) {
   if (p->h_overflow) (void)hipHostFree(p->h_overflow);
   p->h_overflow = nullptr;
   dfree(p->d_pairs); dfree(p->d_pp); dfree(p->d_pairI); dfree(p->d_pair_cls); dfree(p->d_pair_sa);
-  dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_pair_mol); dfree(p->d_cm_beg); dfree(p->d_l);
+  dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_pair_mol); dfree(p->d_bin_beg); dfree(p->d_cm_bin); dfree(p->d_l);
   dfree(p->d_pure); dfree(p->d_cart_off); dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell);
   dfree(p->d_sbase); dfree(p->d_cbase); dfree(p->d_abase); dfree(p->d_mnc); dfree(p->d_mc_off);
   dfree(p->d_mf_off); dfree(p->d_ps_off); dfree(p->d_mf_user); dfree(p->d_tsph); dfree(p->d_Dc);
@@ -550,9 +595,31 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   order.reserve(nall);
   for (int i = 0; i < nall; ++i)
     if (std::sqrt(smax[i]) > p->tau) order.push_back(i);
+  // bins: inside a (class, molecule), pairs of equal contraction length npp are kept
+  // together (sorted by I descending inside the bin), so that the kets the screen writes
+  // next to each other -- the quartets of neighbouring lanes -- run the same number of
+  // primitive quartets. More than MAX_BINS lengths in one (class, molecule): neighbouring
+  // lengths share a bin.
+  std::vector<int> bucket(nall, 0);
+  {
+    std::vector<std::vector<int>> lens((size_t)NPAIRCLASS * nmol);
+    for (int i : order) lens[(size_t)all[i].cls * nmol + all[i].mol].push_back(all[i].npp);
+    std::vector<std::vector<int>> uniq(lens.size());
+    for (size_t g = 0; g < lens.size(); ++g) {
+      auto &v = lens[g];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    for (int i : order) {
+      const auto &v = lens[(size_t)all[i].cls * nmol + all[i].mol];
+      const int r = (int)(std::lower_bound(v.begin(), v.end(), all[i].npp) - v.begin());
+      bucket[i] = (int)((long long)r * MAX_BINS / (long long)v.size());   // identity when <= MAX_BINS lengths
+    }
+  }
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     if (all[x].cls != all[y].cls) return all[x].cls < all[y].cls;
     if (all[x].mol != all[y].mol) return all[x].mol < all[y].mol;
+    if (bucket[x] != bucket[y]) return bucket[x] < bucket[y];
     return smax[x] > smax[y];
   });
   p->npairs = (int)order.size();
@@ -582,6 +649,21 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
     cm[0] = p->cls_beg[c];
     for (int m = 0; m < nmol; ++m) cm[m + 1] = cm[m] + (int)cmcnt[(size_t)c * nmol + m];
   }
+  // bins and the first bin of every (class, molecule)
+  std::vector<int> bin_beg, cm_bin((size_t)NPAIRCLASS * (nmol + 1), 0);
+  for (int k = 0; k < p->npairs; ++k)
+    if (k == 0 || kcls[k] != kcls[k - 1] || kmol[k] != kmol[k - 1] || bucket[order[k]] != bucket[order[k - 1]])
+      bin_beg.push_back(k);
+  bin_beg.push_back(p->npairs);
+  {
+    size_t b = 0;
+    for (int c = 0; c < NPAIRCLASS; ++c)
+      for (int m = 0; m <= nmol; ++m) {
+        const int first = p->cm_beg[(size_t)c * (nmol + 1) + m];   // first pair of (c, m)
+        while (b + 1 < bin_beg.size() && bin_beg[b] < first) ++b;
+        cm_bin[(size_t)c * (nmol + 1) + m] = (int)b;
+      }
+  }
   p->possible.assign(NQCLASS, 0);
   for (int cb = 0; cb < NPAIRCLASS; ++cb)
     for (int ck = 0; ck <= cb; ++ck)
@@ -598,7 +680,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
       (rc = dupload(&p->d_pair_npp, knpp)) || (rc = dupload(&p->d_pair_ca, kca)) ||
       (rc = dupload(&p->d_pair_cb, kcb)) || (rc = dupload(&p->d_pair_la, kla)) ||
       (rc = dupload(&p->d_pair_lb, klb)) || (rc = dupload(&p->d_pair_mol, kmol)) ||
-      (rc = dupload(&p->d_cm_beg, p->cm_beg)))
+      (rc = dupload(&p->d_bin_beg, bin_beg)) || (rc = dupload(&p->d_cm_bin, cm_bin)))
     return cleanup(rc);
   // Coulomb pair buffer: per pair class, element-major over the pairs of the class
   p->jp_off.assign(NPAIRCLASS, 0);
@@ -682,7 +764,7 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
       if (!any) continue;
       int split = beg;
       if (bi.fusable[tier]) {
-        const size_t fixed = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)bi.pool_bytes[tier];
+        const size_t fixed = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)bi.pool_bytes[tier];   // jab_s, pool
         const long long fit = fixed < FUSED_LDS_MAX ? (long long)((FUSED_LDS_MAX - fixed) / ((size_t)(na + nbb) * 8)) : 0;
         int m = 0;
         while (m < nmol && p->mnc[m] <= fit) ++m;      // molecules are in ascending size
@@ -698,7 +780,7 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         const int qc = qclass_index(cb, ck);
         if (!((bi.tier_mask[tier] >> ck) & 1) || !active[qc]) continue;
         const ClassInfo &ci = g_classes[qc];
-        const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;
+        const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;   // jab_s, pool
         out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 0, lds, ci.scratch_per_wg});
       }
     }
@@ -743,7 +825,8 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   A.pair_sb = p->d_pair_sb;
   A.pair_npp = p->d_pair_npp;
   A.pair_mol = p->d_pair_mol;
-  A.cm_beg = p->d_cm_beg;
+  A.bin_beg = p->d_bin_beg;
+  A.cm_bin = p->d_cm_bin;
   A.Pblk = p->d_Pblk;
   A.ps_off = p->d_ps_off;
   A.sbase = p->d_sbase;
@@ -1067,11 +1150,11 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
   };
   auto class_flops = [&](int qc, jk_profile_t &r) {
     const ClassInfo &ci = g_classes[qc];
-    const int nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
-    const double nel = (double)ncart(ci.la) * ncart(ci.lb) * ncart(ci.lc) * ncart(ci.ld);
+    double fp = 0.0, fq = 0.0;
+    class_ops(ci.la, ci.lb, ci.lc, ci.ld, &fp, &fq);
     r.quartets += cnt[qc];
     r.prim_quartets += (long long)np[qc];
-    r.flops += (double)np[qc] * 3.0 * nroots * nel + (double)cnt[qc] * 12.0 * nel;
+    r.flops += (double)np[qc] * fp + (double)cnt[qc] * fq;
   };
   float ms = 0.f;
   jk_profile_t e{};

@@ -6,6 +6,8 @@
 
 namespace jk {
 
+constexpr int MAX_BINS = 64;  // bins of one (pair class, molecule): distinct contraction lengths, merged above this
+
 struct ShellInfo {            // device pointers; molecules are stored one after another
   const int *l, *pure;        // per shell (global shell index)
   const int *cart_off, *ao_off;   // per shell, inside its molecule
@@ -25,7 +27,8 @@ struct ShellInfo {            // device pointers; molecules are stored one after
 struct ScreenArgs {           // device pointers
   const double *pairI;        // Schwarz factor per kept pair (sorted by class, molecule, then I descending)
   const int *pair_cls, *pair_sa, *pair_sb, *pair_npp, *pair_mol;
-  const int *cm_beg;          // [15 * (nmol+1)] first pair of each (class, molecule)
+  const int *bin_beg;         // [nbins+1] first pair of each bin (class, molecule, contraction length)
+  const int *cm_bin;          // [15 * (nmol+1)] first bin of each (class, molecule)
   const double *Pblk;         // per molecule: nshell_m x nshell_m block maxima of |D_cart|
   const long long *ps_off;    // [nmol+1] first element of each molecule's block in Pblk
   const int *sbase;           // [nmol+1] first shell of each molecule

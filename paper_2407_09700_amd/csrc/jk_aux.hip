@@ -88,9 +88,23 @@ __device__ __forceinline__ int ket_prefix(const double *__restrict__ Iket, int n
   return lo;
 }
 
-// Segments: for every bra pair and ket class, room for the ket prefix that can pass the
-// screen under the global density bound. Each workgroup adds its per-class totals with one
-// global atomic per class and hands out offsets inside its block from LDS.
+// Candidate kets of bra pair i in one bin (kets of one class, molecule and contraction
+// length, sorted by I descending): the prefix that can pass the screen under the global
+// density bound; in the bra's own class only kets with index <= i (unique quartets).
+__device__ __forceinline__ int bin_candidates(const ScreenArgs &A, int bin, int i, bool same_class, double Ib,
+                                              double pglob) {
+  const int kb = A.bin_beg[bin];
+  int nk = A.bin_beg[bin + 1] - kb;
+  if (same_class) {
+    if (kb > i) return 0;
+    nk = min(nk, i - kb + 1);
+  }
+  return ket_prefix(A.pairI + kb, nk, Ib, pglob, A.tau);
+}
+
+// Segments: for every bra pair and ket class, room for the ket prefixes (one per bin) that
+// can pass the screen under the global density bound. Each workgroup adds its per-class
+// totals with one global atomic per class and hands out offsets inside its block from LDS.
 __global__ __launch_bounds__(256) void k_capacity(ScreenArgs A) {
   __shared__ unsigned long long s_tot[NQCLASS], s_base[NQCLASS];
   for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) s_tot[t] = 0ull;
@@ -101,16 +115,14 @@ __global__ __launch_bounds__(256) void k_capacity(ScreenArgs A) {
   if (i < A.npairs) {
     cb = A.pair_cls[i];
     const int m = A.pair_mol[i];
-    const int li = i - A.cm_beg[cb * (A.nmol + 1) + m];
     const double Ib = A.pairI[i];
     const double pglob = *A.gmax;
     for (int ck = 0; ck < NPAIRCLASS; ++ck) {
       loc[ck] = 0;
       if (ck > cb) continue;
-      const int kb = A.cm_beg[ck * (A.nmol + 1) + m];
-      const int nk = A.cm_beg[ck * (A.nmol + 1) + m + 1] - kb;
-      int n = ket_prefix(A.pairI + kb, nk, Ib, pglob, A.tau);
-      if (ck == cb) n = min(n, li + 1);
+      int n = 0;
+      const int b1 = A.cm_bin[ck * (A.nmol + 1) + m + 1];
+      for (int bin = A.cm_bin[ck * (A.nmol + 1) + m]; bin < b1; ++bin) n += bin_candidates(A, bin, i, ck == cb, Ib, pglob);
       if (n > 0) loc[ck] = (int)atomicAdd(&s_tot[qclass_index(cb, ck)], (unsigned long long)n);
     }
   }
@@ -142,20 +154,22 @@ __global__ void k_class_off(const unsigned long long *cap, long long *class_off,
 
 // One wave per bra pair: tests the candidates of every ket class with the exact
 // predicate I_ab I_cd P >= tau (P = max |D_cart| over the six shell-pair blocks), writes the
-// kept kets to the front of the (bra, class) segment and its count.
+// kept kets to the (bra, class) segment -- bin after bin, so that kets of equal contraction
+// length sit next to each other -- and its count.
 __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
   __shared__ int s_cnt[NQCLASS], s_c32[NQCLASS];
   __shared__ unsigned long long s_np[NQCLASS];
+  __shared__ int s_pref[4][MAX_BINS + 1];          // per wave: candidate prefix over the bins
   for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) { s_cnt[t] = 0; s_c32[t] = 0; s_np[t] = 0ull; }
   __syncthreads();
   const int lane = threadIdx.x & 63;
+  int *pref = s_pref[threadIdx.x >> 6];
   const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (i < A.npairs) {
     const double tau = A.tau;
     const double pglob = *A.gmax;
     const int cb = A.pair_cls[i];
     const int m = A.pair_mol[i];
-    const int li = i - A.cm_beg[cb * (A.nmol + 1) + m];
     const double Ib = A.pairI[i];
     const int sb0 = A.sbase[m];
     const int ns = A.sbase[m + 1] - sb0;
@@ -166,10 +180,21 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
     const double pab = Pa[sb];
     const unsigned long long nppb = (unsigned long long)A.pair_npp[i];
     for (int ck = 0; ck <= cb; ++ck) {
-      const int kb = A.cm_beg[ck * (A.nmol + 1) + m];
-      const int nk = A.cm_beg[ck * (A.nmol + 1) + m + 1] - kb;
-      int n = ket_prefix(A.pairI + kb, nk, Ib, pglob, tau);
-      if (ck == cb) n = min(n, li + 1);
+      const int b0 = A.cm_bin[ck * (A.nmol + 1) + m];
+      const int nb = A.cm_bin[ck * (A.nmol + 1) + m + 1] - b0;   // <= MAX_BINS (plan creation)
+      // candidates per bin (one lane per bin), exclusive prefix through the wave
+      const int mine = lane < nb ? bin_candidates(A, b0 + lane, i, ck == cb, Ib, pglob) : 0;
+      int incl = mine;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+      }
+      if (lane < nb) pref[lane + 1] = incl;
+      if (lane == 0) pref[0] = 0;
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      int n = __shfl(incl, 63);
       const int qc = qclass_index(cb, ck);
       const long long so = A.segoff[(size_t)i * NPAIRCLASS + ck];
       {                                       // never write past the class region
@@ -183,8 +208,14 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
       for (int k0 = 0; k0 < n; k0 += 64) {
         const int k = k0 + lane;
         bool keep = false, lo = false;
+        int kg = 0;
         if (k < n) {
-          const int kg = kb + k;
+          int lo_b = 0, hi_b = nb - 1;        // last bin with pref[bin] <= k
+          while (lo_b < hi_b) {
+            const int mid = (lo_b + hi_b + 1) >> 1;
+            if (pref[mid] <= k) lo_b = mid; else hi_b = mid - 1;
+          }
+          kg = A.bin_beg[b0 + lo_b] + (k - pref[lo_b]);
           const int sc = A.pair_sa[kg] - sb0, sd = A.pair_sb[kg] - sb0;
           double p = pab;
           p = fmax(p, Pm[(size_t)sc * ns + sd]);
@@ -200,8 +231,8 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
         // FP64 kets fill the segment from the front, FP32 kets from the back
         const unsigned long long below = (1ull << lane) - 1ull;
         const unsigned long long m64 = __ballot(keep && !lo), m32 = __ballot(lo);
-        if (keep && !lo) out[kept + __popcll(m64 & below)] = kb + k;
-        if (lo) out[n - 1 - (kept32 + __popcll(m32 & below))] = kb + k;
+        if (keep && !lo) out[kept + __popcll(m64 & below)] = kg;
+        if (lo) out[n - 1 - (kept32 + __popcll(m32 & below))] = kg;
         kept += __popcll(m64);
         kept32 += __popcll(m32);
       }
@@ -220,6 +251,8 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
         }
         if (kept32) atomicAdd(&s_c32[qc], kept32);
       }
+      __threadfence_block();              // every lane has read pref before the next class rewrites it
+      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();

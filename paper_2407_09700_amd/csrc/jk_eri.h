@@ -15,6 +15,12 @@
 #pragma once
 #include "jk_device.h"
 
+// 1 and 2 roots from the closed-form rule (Boys moments) instead of the interpolation table
+// (off: the table measured faster for the light classes)
+#ifndef JK_CLOSED_LOW_ROOTS
+#define JK_CLOSED_LOW_ROOTS 0
+#endif
+
 namespace jk {
 
 // ================================================================== lane per quartet
@@ -67,7 +73,7 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
           }
         }
       };
-      if constexpr (N <= 2) {
+      if constexpr (N <= 2 && JK_CLOSED_LOW_ROOTS) {
         double u[N], w[N];
         rys_closed<N>(Q.T, u, w);
 #pragma unroll

@@ -22,6 +22,11 @@
 #pragma once
 #include "jk_eri.h"
 
+// FP32 lane bodies for the mixed-precision quartets (0: they run the FP64 bodies)
+#ifndef JK_FP32_BODIES
+#define JK_FP32_BODIES 1
+#endif
+
 namespace jk {
 
 constexpr int SMALL_REG_LIMIT = 320;   // lane per quartet when [e0|f0] accumulators + one root's 2D integrals fit
@@ -480,7 +485,7 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
       const int *cls_kets = A.kets + A.class_off[qclass_index(cb, ck)];
       const int cnt = A.segcnt[sg];
       const int cnt32 = A.segcnt32 ? A.segcnt32[sg] : 0;
-      if constexpr (TIER == 2) {
+      if constexpr (TIER == 2 || !JK_FP32_BODIES) {
         // team bodies: the FP32 part of the segment is evaluated in double as well
         for (int part = 0; part < 2; ++part) {
           const int n = part ? cnt32 : cnt;

@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libjk.so")
+LIB_PATH = os.environ.get("JK_LIB", os.path.join(_HERE, "libjk.so"))
 
 JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE, JK_ENODEV = 0, -1, -2, -3, -4, -5
 JK_FP64, JK_MIXED = 0, 1
