@@ -224,6 +224,10 @@ struct jk_plan {
   int *d_pair_ca = nullptr, *d_pair_cb = nullptr, *d_pair_la = nullptr, *d_pair_lb = nullptr;
   int *d_segoff = nullptr, *d_segcnt = nullptr, *d_next = nullptr;
   int *d_segoff32 = nullptr, *d_segcnt32 = nullptr, *d_count32 = nullptr;   // mixed precision
+  int2 *d_units = nullptr;             // work units of the current launch (bra pair, slice)
+  int units_cap = 0;
+  int *d_nunits = nullptr;             // [NSLOT] unit count per launch slot
+  std::vector<int> slice, units_est;   // per launch slot: kets per unit, expected units (last eager build)
   long long *d_class_off = nullptr, *d_jp_off = nullptr, *d_room = nullptr;
   int *d_overflow = nullptr;
   int *h_overflow = nullptr;                     // pinned host copy of the overflow flag
@@ -281,7 +285,7 @@ void plan_free(jk_plan *p) {
   dfree(p->d_kets); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
   dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
   dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair);
-  dfree(p->d_room); dfree(p->d_overflow); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
+  dfree(p->d_room); dfree(p->d_overflow); dfree(p->d_units); dfree(p->d_nunits); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
 }
@@ -705,7 +709,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
       (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
       (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
       (rc = dalloc(&p->d_room, NQCLASS)) || (rc = dalloc(&p->d_overflow, 1)) ||
-      (rc = dalloc(&p->d_next, NSLOT)))
+      (rc = dalloc(&p->d_next, NSLOT)) || (rc = dalloc(&p->d_nunits, NSLOT)))
     return cleanup(rc);
   if (hipHostMalloc((void **)&p->h_overflow, sizeof(int), hipHostMallocDefault) != hipSuccess) {
     p->h_overflow = nullptr;
@@ -713,6 +717,8 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   }
   *p->h_overflow = 0;
   p->grid.assign(NSLOT, 0);
+  p->slice.assign(NSLOT, 0);
+  p->units_est.assign(NSLOT, 0);
   if (p->flags & (JK_FLAG_PROFILE | JK_FLAG_TUNE)) {
     p->events.resize(2 * NSLOT + 4, nullptr);
     for (auto &e : p->events)
@@ -741,6 +747,7 @@ struct Launch {
   int tier;          // fused: register tier; per class: -1
   int qc;            // per class: quartet class; fused: -1
   int bra_beg, bra_end;   // bra pairs of the launch
+  int mask;          // ket classes of the launch (bit ck)
   int nc_max;        // fused: largest Cartesian size among the launch's molecules
   size_t lds;        // dynamic LDS bytes
   long long scratch_per_wg;
@@ -772,7 +779,8 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         if (split > beg) {
           const int ncm = p->mnc[m - 1];
           const size_t lds = (size_t)(na + nbb) * ncm * 8 + fixed;
-          out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, ncm, lds, bi.scratch_per_wg[tier]});
+          out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], ncm, lds,
+                               bi.scratch_per_wg[tier]});
         }
       }
       if (split == end) continue;
@@ -781,16 +789,32 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         if (!((bi.tier_mask[tier] >> ck) & 1) || !active[qc]) continue;
         const ClassInfo &ci = g_classes[qc];
         const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;   // jab_s, pool
-        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 0, lds, ci.scratch_per_wg});
+        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 0, lds, ci.scratch_per_wg});
       }
     }
   }
 }
 
 int launch_grid(const jk_plan *p, const Launch &L) {
-  const int nb = L.bra_end - L.bra_beg;
+  const int nu = p->units_est[L.slot] > 0 ? p->units_est[L.slot] : L.bra_end - L.bra_beg;
   const int g = p->grid[L.slot] > 0 ? p->grid[L.slot] : GRID_TEAM_MAX;
-  return std::max(1, std::min(nb, g));
+  return std::max(1, std::min(nu, g));
+}
+
+constexpr long long TARGET_UNITS = 4096;   // work units per launch the slicing aims for (16 per CU)
+constexpr int SLICE_MIN = 64;              // fewest kets per unit
+
+// Kets per work unit of a launch from its candidate count (an upper bound of its kets): the
+// whole bra when there are many bras, slices of the bra's kets when a few bras carry the work.
+void size_units(jk_plan *p, const Launch &L, long long cand, long long *units_need) {
+  const long long nbra = L.bra_end - L.bra_beg;
+  long long sl = (cand + TARGET_UNITS - 1) / TARGET_UNITS;
+  sl = std::max<long long>(SLICE_MIN, (sl + SLICE_MIN - 1) / SLICE_MIN * SLICE_MIN);
+  sl = std::min<long long>(sl, 1LL << 30);
+  p->slice[L.slot] = (int)sl;
+  const long long est = std::min<long long>(nbra + (cand + sl - 1) / sl, 1LL << 30);
+  p->units_est[L.slot] = (int)est;
+  *units_need = std::max(*units_need, est + 1);
 }
 
 // Enqueue one build on `st`. Eager (record = false): reads the class capacities back to size
@@ -814,6 +838,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
   HIPCHK(launch_fill_i32(p->d_count32, NQCLASS, 0, st));
   HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
+  HIPCHK(launch_fill_i32(p->d_nunits, NSLOT, 0, st));
   HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
   HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
   HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
@@ -850,9 +875,10 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   A.nmol = p->nmol;
   if (p->npairs > 0) HIPCHK(launch_capacity(A, st));
   bool active[NQCLASS];
+  unsigned long long cap_host[NQCLASS] = {};
   if (!record) {
-    unsigned long long cap[NQCLASS];
-    HIPCHK(hipMemcpyAsync(cap, p->d_cap, sizeof(cap), hipMemcpyDeviceToHost, st));
+    unsigned long long *cap = cap_host;
+    HIPCHK(hipMemcpyAsync(cap, p->d_cap, sizeof(cap_host), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     long long total = 0;
     for (int c = 0; c < NQCLASS; ++c) {
@@ -882,6 +908,25 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   std::vector<Launch> launches;
   plan_launches(p, active, launches);
   if (!record) {
+    long long units_need = 1;
+    for (const Launch &L : launches) {
+      long long cand = 0;
+      for (int ck = 0; ck <= L.cb; ++ck)
+        if ((L.mask >> ck) & 1) cand += (long long)cap_host[qclass_index(L.cb, ck)];
+      size_units(p, L, cand, &units_need);
+    }
+    if (units_need > 0x7fffffffLL) return fail(JK_EUNSUPPORTED, "%lld work units exceed 2^31", units_need);
+    if (units_need > p->units_cap) {
+      // graph replays reuse this buffer: leave room for densities that keep a few more quartets
+      const long long want = (p->flags & JK_FLAG_GRAPH) ? std::min(units_need + units_need / 4 + 1024, 0x7fffffffLL)
+                                                         : units_need;
+      dfree(p->d_units);
+      p->units_cap = 0;
+      p->graph_stale = true;
+      int rc = dalloc(&p->d_units, (size_t)want);
+      if (rc) return rc;
+      p->units_cap = (int)want;
+    }
     long long need = 0;
     for (const Launch &L : launches) need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
     if (need > 0) {
@@ -913,6 +958,12 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
     J_.bra_beg = L.bra_beg;
     J_.bra_end = L.bra_end;
     J_.nc_max = L.nc_max;
+    J_.slice = p->slice[L.slot] > 0 ? p->slice[L.slot] : (1 << 30);
+    J_.units = p->d_units;
+    J_.units_cap = p->units_cap;
+    J_.nunits = p->d_nunits + L.slot;
+    HIPCHK(launch_units(p->d_segcnt, p->d_segcnt32, L.bra_beg, L.bra_end, L.mask, J_.slice, p->d_units, p->units_cap,
+                        p->d_nunits + L.slot, p->d_overflow, st));
     J_.scratch_per_wg = L.scratch_per_wg;
     J_.next = p->d_next + L.slot;
     if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot], st));
@@ -953,10 +1004,20 @@ int record_graph(jk_plan *p, const double *D, double *J, double *K, hipStream_t 
   for (int c = 0; c < NQCLASS; ++c) active[c] = p->possible[c] != 0;
   std::vector<Launch> launches;
   plan_launches(p, active, launches);
-  long long need = 0;
-  for (const Launch &L : launches) need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
+  long long need = 0, units_need = 1;
+  for (const Launch &L : launches) {
+    need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
+    const long long u = p->slice[L.slot] > 0 ? p->units_est[L.slot] : L.bra_end - L.bra_beg;
+    units_need = std::max(units_need, u + 1);
+  }
   int rc = ensure_scratch(p, need);
   if (rc) return rc;
+  if (units_need > p->units_cap) {
+    dfree(p->d_units);
+    p->units_cap = 0;
+    if ((rc = dalloc(&p->d_units, (size_t)units_need))) return rc;
+    p->units_cap = (int)units_need;
+  }
   graph_free(p);
   HIPCHK(hipStreamBeginCapture(p->rec_stream, hipStreamCaptureModeThreadLocal));
   rc = enqueue_build(p, D, J, K, p->rec_stream, true);

@@ -71,5 +71,7 @@ hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *K
 hipError_t launch_fold(const FoldArgs &F, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int *p, long long n, int v, hipStream_t st);
+hipError_t launch_units(const int *segcnt, const int *segcnt32, int bra_beg, int bra_end, int mask, int slice,
+                        int2 *units, int units_cap, int *nunits, int *overflow, hipStream_t st);
 
 }  // namespace jk

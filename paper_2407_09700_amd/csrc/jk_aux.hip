@@ -323,6 +323,40 @@ __global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long lon
     p[t] = v;
 }
 
+// Work units of one integral launch: every bra pair of [bra_beg, bra_end) with kets in the
+// launch's ket classes (bit ck of mask) gives ceil(kets / slice) units (bra, slice index).
+// Units are handed out with one atomic per wave; their order does not matter.
+__global__ void k_units(const int *__restrict__ segcnt, const int *__restrict__ segcnt32, int bra_beg, int bra_end,
+                        int mask, int slice, int2 *__restrict__ units, int units_cap, int *nunits, int *overflow) {
+  const int lane = threadIdx.x & 63;
+  const int bi = bra_beg + blockIdx.x * blockDim.x + threadIdx.x;
+  int n = 0;
+  if (bi < bra_end) {
+    long long tot = 0;
+    for (int ck = 0; ck < NPAIRCLASS; ++ck)
+      if ((mask >> ck) & 1) {
+        tot += segcnt[(size_t)bi * NPAIRCLASS + ck];
+        if (segcnt32) tot += segcnt32[(size_t)bi * NPAIRCLASS + ck];
+      }
+    n = (int)((tot + slice - 1) / slice);
+  }
+  int incl = n;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
+  }
+  const int wave_tot = __shfl(incl, 63);
+  int base = 0;
+  if (lane == 63 && wave_tot) base = atomicAdd(nunits, wave_tot);
+  base = __shfl(base, 63);
+  for (int j = 0; j < n; ++j) {
+    const long long at = (long long)base + incl - n + j;
+    if (at < units_cap) units[at] = make_int2(bi, j);
+    else *overflow = 1;        // only a graph replay (list sized at recording) can get here
+  }
+}
+
 __global__ void k_fill_i32(int *p, long long n, int v) {
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
     p[t] = v;
@@ -368,6 +402,13 @@ hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *K
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_units(const int *segcnt, const int *segcnt32, int bra_beg, int bra_end, int mask, int slice,
+                        int2 *units, int units_cap, int *nunits, int *overflow, hipStream_t st) {
+  if (bra_end <= bra_beg) return hipSuccess;
+  hipLaunchKernelGGL(k_units, dim3((bra_end - bra_beg + 255) / 256), dim3(256), 0, st, segcnt, segcnt32, bra_beg,
+                     bra_end, mask, slice, units, units_cap, nunits, overflow);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(int *p, long long n, int v, hipStream_t st) {

@@ -70,6 +70,12 @@ struct JKArgs {
   int nc_max;                   // largest nc_m (row length of the LDS exchange rows)
   int bra_beg, bra_end;         // bra pairs of the launched bra class
   int *next;                    // work counter of the launch
+  const int2 *units;            // work units (bra pair, slice index) of the launch (k_units)
+  const int *nunits;            // their number (entries beyond units_cap were not written)
+  int units_cap;
+  int slice;                    // kets per unit: a unit runs kets [j slice, (j+1) slice) of the bra's
+                                // kets in the launch, counted over the ket classes in order, FP64
+                                // part of each segment before its FP32 part
   double *scratch;              // global buffers of the largest team classes
   long long scratch_per_wg;
 };
@@ -461,7 +467,7 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
   double *Krow = smem;
   double *jab_s = smem + (size_t)(NA + NB) * A.nc_max;
   double *pool = jab_s + ((NA * NB + 1) & ~1);
-  const int nunits = A.bra_end - A.bra_beg;
+  const int nunits = min(*A.nunits, A.units_cap);
   const int tid = threadIdx.x;
   // the rows start at zero; the flush of each unit puts back the zeros it reads
   for (int t = tid; t < (NA + NB) * A.nc_max; t += blockDim.x) Krow[t] = 0.0;
@@ -471,7 +477,10 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
     __syncthreads();
     const int u = s_unit;
     if (u >= nunits) break;
-    const int bi = A.bra_beg + u;
+    const int2 unit = A.units[u];
+    const int bi = unit.x;
+    const long long lo = (long long)unit.y * A.slice, hi = lo + A.slice;
+    long long pos = 0;          // position of the current part in the bra's kets of this launch
     const int mol = A.pairs[bi].mol;
     const int nc = A.mnc[mol];
     double *Km = A.Kc + A.mbase[mol];
@@ -479,23 +488,23 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
 #pragma unroll
     for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
     constexpr int mask = tier_mask<LA, LB, TIER>();
-    for (int ck = 0; ck <= cb; ++ck) {
+    for (int ck = 0; ck <= cb && pos < hi; ++ck) {
       if (!((mask >> ck) & 1)) continue;
       const size_t sg = (size_t)bi * NPAIRCLASS + ck;
       const int *cls_kets = A.kets + A.class_off[qclass_index(cb, ck)];
-      const int cnt = A.segcnt[sg];
-      const int cnt32 = A.segcnt32 ? A.segcnt32[sg] : 0;
-      if constexpr (TIER == 2 || !JK_FP32_BODIES) {
-        // team bodies: the FP32 part of the segment is evaluated in double as well
-        for (int part = 0; part < 2; ++part) {
-          const int n = part ? cnt32 : cnt;
-          if (n) ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]), n, Krow,
-                                               jab_s, pool, jab);
+      for (int part = 0; part < 2; ++part) {   // FP64 part, then FP32 part of the segment
+        const int n = part ? (A.segcnt32 ? A.segcnt32[sg] : 0) : A.segcnt[sg];
+        const long long b0 = lo > pos ? lo : pos, b1 = hi < pos + n ? hi : pos + n;
+        if (b1 > b0) {
+          const int *kl = cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]) + (b0 - pos);
+          if constexpr (TIER == 2 || !JK_FP32_BODIES)   // team bodies evaluate the FP32 part in double
+            ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
+          else if (part == 0)
+            ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
+          else
+            ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
         }
-      } else {
-        if (cnt) ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, cls_kets + A.segoff[sg], cnt, Krow, jab_s, pool, jab);
-        if (cnt32)
-          ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, cls_kets + A.segoff32[sg], cnt32, Krow, jab_s, pool, jab);
+        pos += n;
       }
     }
     jab_reduce<NA * NB>(jab, jab_s);
@@ -528,7 +537,7 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
   __shared__ int s_unit;
   double *jab_s = smem;
   double *pool = smem + ((NA * NB + 1) & ~1);
-  const int nunits = A.bra_end - A.bra_beg;
+  const int nunits = min(*A.nunits, A.units_cap);
   const int tid = threadIdx.x;
   for (;;) {
     if (tid == 0) s_unit = atomicAdd(A.next, 1);
@@ -536,16 +545,23 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
     __syncthreads();
     const int u = s_unit;
     if (u >= nunits) break;
-    const int bi = A.bra_beg + u;
+    const int2 unit = A.units[u];
+    const int bi = unit.x;
     const size_t sg = (size_t)bi * NPAIRCLASS + ck;
-    const int cnt = A.segcnt[sg];
-    const int cnt32 = A.segcnt32 ? A.segcnt32[sg] : 0;
+    // this unit's kets: positions [lo, hi) of the segment's FP64 part [0, n64) followed by
+    // its FP32 part [n64, n64 + n32)
+    const long long n64 = A.segcnt[sg], n32 = A.segcnt32 ? A.segcnt32[sg] : 0;
+    const long long lo = (long long)unit.y * A.slice, hi = lo + A.slice;
+    const long long s64 = min(lo, n64), e64 = min(hi, n64);
+    const long long s32 = max(lo, n64) - n64, e32 = max(min(hi, n64 + n32), n64) - n64;
+    const int cnt = (int)(e64 - s64), cnt32 = (int)max(e32 - s32, 0ll);
     if (cnt + cnt32 > 0) {
-      const int *cls_kets = A.kets + A.class_off[qclass_index(cb, ck)];
+      const int *cls_kets = A.kets + A.class_off[qclass_index(cb, ck)] + s64;   // + segoff: FP64 kets of the unit
+      const int *cls_kets32 = A.kets + A.class_off[qclass_index(cb, ck)] + s32; // + segoff32: FP32 kets
       if constexpr (use_team<LA, LB, LC, LD>() && !use_team2<LA, LB, LC, LD>()) {
         for (int part = 0; part < 2; ++part) {   // FP32 part in double as well
           const int n = part ? cnt32 : cnt;
-          if (n) jk_team_body<LA, LB, LC, LD, false>(A, bi, cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]), n,
+          if (n) jk_team_body<LA, LB, LC, LD, false>(A, bi, (part ? cls_kets32 + A.segoff32[sg] : cls_kets + A.segoff[sg]), n,
                                                      nullptr, jab_s, pool);
         }
       } else if constexpr (use_team2<LA, LB, LC, LD>()) {
@@ -554,7 +570,7 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
         for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
         for (int part = 0; part < 2; ++part) {
           const int n = part ? cnt32 : cnt;
-          if (n) jk_body<LA, LB, LC, LD, false>(A, bi, cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]), n, nullptr,
+          if (n) jk_body<LA, LB, LC, LD, false>(A, bi, (part ? cls_kets32 + A.segoff32[sg] : cls_kets + A.segoff[sg]), n, nullptr,
                                                 jab_s, pool, jab);
         }
         jab_reduce<NA * NB>(jab, jab_s);
@@ -564,7 +580,7 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
         for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
         if (cnt) jk_body<LA, LB, LC, LD, false>(A, bi, cls_kets + A.segoff[sg], cnt, nullptr, jab_s, pool, jab);
         if (cnt32)
-          jk_body<LA, LB, LC, LD, false, float>(A, bi, cls_kets + A.segoff32[sg], cnt32, nullptr, jab_s, pool, jab);
+          jk_body<LA, LB, LC, LD, false, float>(A, bi, cls_kets32 + A.segoff32[sg], cnt32, nullptr, jab_s, pool, jab);
         jab_reduce<NA * NB>(jab, jab_s);
       }
       __syncthreads();
