@@ -50,6 +50,12 @@ constexpr CartTable make_cart_table() {
 static constexpr CartTable CT = make_cart_table();
 static __constant__ CartTable CTD = make_cart_table();   // for run-time indexing
 
+// flat index of the component (x, y, z) in the table above, by arithmetic (no table load)
+__host__ __device__ __forceinline__ constexpr int cart_flat(int x, int y, int z) {
+  const int L = x + y + z;
+  return L * (L + 1) * (L + 2) / 6 + (L - x) * (L - x + 1) / 2 + (L - x - y);
+}
+
 constexpr __host__ __device__ int range_count(int lo, int hi) {  // components of degrees lo..hi
   int n = 0;
   for (int L = lo; L <= hi; ++L) n += ncart(L);

@@ -336,59 +336,79 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
     }
   }
   __syncthreads();
-  for (int t = tid; t < QB * NA * NB * NF; t += BLOCK) {
-    const int q = t / (NA * NB * NF);
-    const int rem = t % (NA * NB * NF);
-    const int ab = rem / NF, f = rem % NF;
-    const int a = ab / NB, b = ab % NB;
+  // Bra transfer, one task per (quartet, a, f): the X[e][f] this a can reach (e = a + k,
+  // |k| <= lb) are loaded together, then the NB outputs (a, b) are formed from registers.
+  constexpr int NKB = range_count(0, LB);       // components k with |k| <= lb
+  for (int t = tid; t < QB * NA * NF; t += BLOCK) {
+    const int q = t / (NA * NF);
+    const int rem = t % (NA * NF);
+    const int a = rem / NF, f = rem % NF;
     const int ax = CTD.x[E0 + a], ay = CTD.y[E0 + a], az = CTD.z[E0 + a];
-    const int bx = CTD.x[CT.start[LB] + b], by = CTD.y[CT.start[LB] + b], bz = CTD.z[CT.start[LB] + b];
-    const double ABx = geo[q * 12 + 0] - geo[q * 12 + 3], ABy = geo[q * 12 + 1] - geo[q * 12 + 4],
-                 ABz = geo[q * 12 + 2] - geo[q * 12 + 5];
-    double v = 0.0, px = 1.0;
-    for (int kx = bx; kx >= 0; --kx) {
-      double py = 1.0;
-      for (int ky = by; ky >= 0; --ky) {
-        double pz = 1.0;
-        for (int kz = bz; kz >= 0; --kz) {
-          const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * px * py * pz;
-          const int ie = CTD.idx[ax + kx][ay + ky][az + kz] - E0;
-          v = fma(cf, X[(q * NE + ie) * NF + f], v);
-          pz *= ABz;
-        }
-        py *= ABy;
-      }
-      px *= ABx;
+    const double AB[3] = {geo[q * 12 + 0] - geo[q * 12 + 3], geo[q * 12 + 1] - geo[q * 12 + 4],
+                          geo[q * 12 + 2] - geo[q * 12 + 5]};
+    double xv[NKB];
+#pragma unroll
+    for (int k = 0; k < NKB; ++k) xv[k] = X[(q * NE + cart_flat(ax + CT.x[k], ay + CT.y[k], az + CT.z[k]) - E0) * NF + f];
+    double pw[3][LB + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      pw[d][0] = 1.0;
+#pragma unroll
+      for (int i = 1; i <= LB; ++i) pw[d][i] = pw[d][i - 1] * AB[d];
     }
-    Y[(q * NA * NB + ab) * NF + f] = v;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      constexpr int B0 = CT.start[LB];
+      const int bx = CT.x[B0 + b], by = CT.y[B0 + b], bz = CT.z[B0 + b];
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NKB; ++k) {
+        const int kx = CT.x[k], ky = CT.y[k], kz = CT.z[k];
+        if (kx > bx || ky > by || kz > bz) continue;
+        const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * pw[0][bx - kx] * pw[1][by - ky] *
+                          pw[2][bz - kz];
+        v = fma(cf, xv[k], v);
+      }
+      Y[(q * NA * NB + a * NB + b) * NF + f] = v;
+    }
   }
   __syncthreads();
+  // Ket transfer, one task per (quartet, ab, c): Y[ab][c + k] for |k| <= ld loaded together,
+  // then the ND outputs (c, d).
+  constexpr int NKD = range_count(0, LD);
   double *Z = X;
-  for (int t = tid; t < QB * NA * NB * NC * ND; t += BLOCK) {
-    const int q = t / (NA * NB * NC * ND);
-    const int rem = t % (NA * NB * NC * ND);
-    const int ab = rem / (NC * ND), cd = rem % (NC * ND);
-    const int c = cd / ND, d = cd % ND;
+  for (int t = tid; t < QB * NA * NB * NC; t += BLOCK) {
+    const int q = t / (NA * NB * NC);
+    const int rem = t % (NA * NB * NC);
+    const int ab = rem / NC, c = rem % NC;
     const int cx = CTD.x[F0 + c], cy = CTD.y[F0 + c], cz = CTD.z[F0 + c];
-    const int dx = CTD.x[CT.start[LD] + d], dy = CTD.y[CT.start[LD] + d], dz = CTD.z[CT.start[LD] + d];
-    const double CDx = geo[q * 12 + 6] - geo[q * 12 + 9], CDy = geo[q * 12 + 7] - geo[q * 12 + 10],
-                 CDz = geo[q * 12 + 8] - geo[q * 12 + 11];
-    double v = 0.0, px = 1.0;
-    for (int kx = dx; kx >= 0; --kx) {
-      double py = 1.0;
-      for (int ky = dy; ky >= 0; --ky) {
-        double pz = 1.0;
-        for (int kz = dz; kz >= 0; --kz) {
-          const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * px * py * pz;
-          const int jf = CTD.idx[cx + kx][cy + ky][cz + kz] - F0;
-          v = fma(cf, Y[(q * NA * NB + ab) * NF + jf], v);
-          pz *= CDz;
-        }
-        py *= CDy;
-      }
-      px *= CDx;
+    const double CD[3] = {geo[q * 12 + 6] - geo[q * 12 + 9], geo[q * 12 + 7] - geo[q * 12 + 10],
+                          geo[q * 12 + 8] - geo[q * 12 + 11]};
+    double yv[NKD];
+#pragma unroll
+    for (int k = 0; k < NKD; ++k) yv[k] = Y[(q * NA * NB + ab) * NF + cart_flat(cx + CT.x[k], cy + CT.y[k], cz + CT.z[k]) - F0];
+    double pw[3][LD + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      pw[d][0] = 1.0;
+#pragma unroll
+      for (int i = 1; i <= LD; ++i) pw[d][i] = pw[d][i - 1] * CD[d];
     }
-    Z[(q * NA * NB + ab) * NC * ND + cd] = v;   // region 1 is free: X was consumed by the pass above
+#pragma unroll
+    for (int dd = 0; dd < ND; ++dd) {
+      constexpr int D0 = CT.start[LD];
+      const int dx = CT.x[D0 + dd], dy = CT.y[D0 + dd], dz = CT.z[D0 + dd];
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NKD; ++k) {
+        const int kx = CT.x[k], ky = CT.y[k], kz = CT.z[k];
+        if (kx > dx || ky > dy || kz > dz) continue;
+        const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * pw[0][dx - kx] * pw[1][dy - ky] *
+                          pw[2][dz - kz];
+        v = fma(cf, yv[k], v);
+      }
+      Z[(q * NA * NB + ab) * NC * ND + c * ND + dd] = v;   // region 1 is free: X was consumed by the pass above
+    }
   }
   __syncthreads();
   return Z;

@@ -232,50 +232,65 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       const int oa = bra.ca, ob = bra.cb, oc = ket.ca, od = ket.cb;
       const double *g = Z + (size_t)q * NA * NB * NC * ND;
       double v = 0.0;
+      // the sums below are unrolled so that their loads (g and D) are in flight together
       if (r < T1) {                       // J[a,b] += 2s sum_cd g D[c,d]
         const int a = r / NB, b = r % NB;
-        for (int c = 0; c < NC; ++c)
-          for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oc + c) * nc + od + d], v);
+        const double *gr = g + (a * NB + b) * NC * ND;
+#pragma unroll 16
+        for (int i = 0; i < NC * ND; ++i) v = fma(gr[i], Dm[(size_t)(oc + i / ND) * nc + od + i % ND], v);
         atomicAdd(&jab_s[r], 2.0 * s * v);
         continue;
       }
       r -= T1;
       if (r < T2) {                       // J[c,d] += 2s sum_ab g D[a,b]
         const int c = r / ND, d = r % ND;
-        for (int a = 0; a < NA; ++a)
-          for (int b = 0; b < NB; ++b) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + ob + b], v);
+#pragma unroll 16
+        for (int i = 0; i < NA * NB; ++i)
+          v = fma(g[i * NC * ND + c * ND + d], Dm[(size_t)(oa + i / NB) * nc + ob + i % NB], v);
         atomic_add(jp_elem(A, ck, ki, r), 2.0 * s * v);
         continue;
       }
       r -= T2;
       if (r < T3) {                       // K[a,c] += s sum_bd g D[b,d]
         const int a = r / NC, c = r % NC;
-        for (int b = 0; b < NB; ++b)
-          for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + od + d], v);
+#pragma unroll 16
+        for (int i = 0; i < NB * ND; ++i) {
+          const int b = i / ND, d = i % ND;
+          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + od + d], v);
+        }
         k_update<KLDS>(Krow, Km, nc, a, oa + a, oc + c, s * v);
         continue;
       }
       r -= T3;
       if (r < T4) {                       // K[a,d] += s sum_bc g D[b,c]
         const int a = r / ND, d = r % ND;
-        for (int b = 0; b < NB; ++b)
-          for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + oc + c], v);
+#pragma unroll 16
+        for (int i = 0; i < NB * NC; ++i) {
+          const int b = i / NC, c = i % NC;
+          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + oc + c], v);
+        }
         k_update<KLDS>(Krow, Km, nc, a, oa + a, od + d, s * v);
         continue;
       }
       r -= T4;
       if (r < T5) {                       // K[b,c] += s sum_ad g D[a,d]
         const int b = r / NC, c = r % NC;
-        for (int a = 0; a < NA; ++a)
-          for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + od + d], v);
+#pragma unroll 16
+        for (int i = 0; i < NA * ND; ++i) {
+          const int a = i / ND, d = i % ND;
+          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + od + d], v);
+        }
         k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, oc + c, s * v);
         continue;
       }
       r -= T5;
       {                                   // K[b,d] += s sum_ac g D[a,c]
         const int b = r / ND, d = r % ND;
-        for (int a = 0; a < NA; ++a)
-          for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + oc + c], v);
+#pragma unroll 16
+        for (int i = 0; i < NA * NC; ++i) {
+          const int a = i / NC, c = i % NC;
+          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + oc + c], v);
+        }
         k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, od + d, s * v);
       }
     }
