@@ -171,10 +171,14 @@ struct TeamCfg {
   static constexpr int GS1 = (E + 1) * (F + 1);          // one direction of one root
   static constexpr int GS = 3 * GS1;
   static constexpr int EMAXACC = 56;                     // accumulators per lane
-  static constexpr int NEP = (NE + EMAXACC - 1) / EMAXACC;
-  static constexpr int EPS = (NE + NEP - 1) / NEP;
-  static constexpr int FW = NEP > 1 ? ((NF + 63) / 64) * 64 : NF;
-  static constexpr int TPQ = NEP * FW;
+  // Product roles. f-major: a lane owns one f component and a slice of EPS e components
+  // (NEP slices per f, each slice wave-uniform). e-major (few f, many e): a lane owns one e
+  // component and all NF f components, so that small ket classes keep the lanes busy.
+  static constexpr bool EMAJOR = NF <= EMAXACC && NE > NF && NE <= 256;
+  static constexpr int NEP = EMAJOR ? 1 : (NE + EMAXACC - 1) / EMAXACC;
+  static constexpr int EPS = EMAJOR ? NF : (NE + NEP - 1) / NEP;   // accumulators per lane
+  static constexpr int FW = EMAJOR ? 0 : (NEP > 1 ? ((NF + 63) / 64) * 64 : NF);
+  static constexpr int TPQ = EMAJOR ? NE : NEP * FW;
   static constexpr int BLOCK = TPQ > 256 ? ((TPQ + 63) / 64) * 64 : 256;
   static constexpr int QB0 = BLOCK / TPQ;
   static constexpr int QBL = (40 * 1024) / (N * GS * 8);       // one primitive chunk of 2D integrals in 40 KB
@@ -261,14 +265,20 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
 
   const int pq_ = tid / C::TPQ;
   const int pr = tid % C::TPQ;
-  const int part = pr / C::FW;
-  const int pf = pr % C::FW;
-  const bool prole = pq_ < QB && pf < NF;
+  const int part = C::EMAJOR ? 0 : pr / (C::EMAJOR ? 1 : C::FW);
+  const int pf = C::EMAJOR ? pr : pr % (C::EMAJOR ? 1 : C::FW);   // e-major: the lane's e component
+  const bool prole = pq_ < QB && (C::EMAJOR || pf < NF);
   int xo = 0, yo = 0, zo = 0;
   if (prole) {
-    xo = CTD.x[F0 + pf];
-    yo = GS1 + CTD.y[F0 + pf];
-    zo = 2 * GS1 + CTD.z[F0 + pf];
+    if constexpr (C::EMAJOR) {                 // row e of each direction's table
+      xo = CTD.x[E0 + pf] * (F + 1);
+      yo = GS1 + CTD.y[E0 + pf] * (F + 1);
+      zo = 2 * GS1 + CTD.z[E0 + pf] * (F + 1);
+    } else {                                   // column f
+      xo = CTD.x[F0 + pf];
+      yo = GS1 + CTD.y[F0 + pf];
+      zo = 2 * GS1 + CTD.z[F0 + pf];
+    }
   }
   if (tid == 0) {
     int m = 0;
@@ -321,7 +331,20 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
 #pragma unroll
         for (int n = 0; n < N; ++n) {
           const double *base = sG + ((pq_ * PC + pl) * N + n) * GS;
-          team_product_dispatch<LA, LB, LC, LD, 0>(part, base, xo, yo, zo, acc);
+          if constexpr (C::EMAJOR) {
+            double gx[F + 1], gy[F + 1], gz[F + 1];
+#pragma unroll
+            for (int f = 0; f <= F; ++f) {
+              gx[f] = base[xo + f];
+              gy[f] = base[yo + f];
+              gz[f] = base[zo + f];
+            }
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+              acc[j] = fma(gx[CT.x[F0 + j]] * gy[CT.y[F0 + j]], gz[CT.z[F0 + j]], acc[j]);
+          } else {
+            team_product_dispatch<LA, LB, LC, LD, 0>(part, base, xo, yo, zo, acc);
+          }
         }
       }
     }
@@ -329,10 +352,15 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   }
 
   if (prole) {
+    if constexpr (C::EMAJOR) {
 #pragma unroll
-    for (int i = 0; i < C::EPS; ++i) {
-      const int e = part * C::EPS + i;
-      if (e < NE) X[(pq_ * NE + e) * NF + pf] = acc[i];
+      for (int j = 0; j < NF; ++j) X[(pq_ * NE + pf) * NF + j] = acc[j];
+    } else {
+#pragma unroll
+      for (int i = 0; i < C::EPS; ++i) {
+        const int e = part * C::EPS + i;
+        if (e < NE) X[(pq_ * NE + e) * NF + pf] = acc[i];
+      }
     }
   }
   __syncthreads();
