@@ -138,7 +138,7 @@ def mixed_extra(steps=2, warmup=1):
     return out
 
 
-def batched_extra(steps=2, warmup=1):
+def batched_extra(steps=1, warmup=1):
     """64 molecules of 10-120 atoms (3s2p1d1f): one batched graph-replayed build (FP64 and
     mixed) vs 64 sequential single-molecule FP64 builds."""
     import torch
@@ -164,9 +164,11 @@ def batched_extra(steps=2, warmup=1):
     out["sequential_fp64_ms"] = seq_ms
     out["kept_quartets"] = kept
     log(f"cfg5 sequential: {seq_ms:.1f} ms, {kept} quartets")
+    import tempfile
+    cache = os.path.join(tempfile.gettempdir(), f"jk_tune_cfg5_{os.getpid()}.txt")   # FP64 tunes, mixed reuses
     for name, prec in (("fp64", jk.JK_FP64), ("mixed", jk.JK_MIXED)):
         t = time.perf_counter()
-        b = jk.Batch(mols, precision=prec, graph=True, tune=True)
+        b = jk.Batch(mols, precision=prec, graph=True, tune=True, tune_cache=cache)
         D = b.pack([m.D for m in mols])
         J = torch.empty_like(D)
         K = torch.empty_like(D)
@@ -181,6 +183,11 @@ def batched_extra(steps=2, warmup=1):
         out[f"batched_{name}_speedup_vs_sequential"] = seq_ms / ms
         out[f"dE_batched_{name}_vs_sequential"] = abs(E - E_seq)
         out[f"graph_replays_{name}"] = info["replays"]
+    if os.path.exists(cache):
+        w = open(cache).read().split()
+        out["tuned_grids"] = {w[i]: int(w[i + 1]) for i in range(0, len(w) - 1, 2)}
+    if os.path.exists(cache):
+        os.remove(cache)
     return out
 
 
