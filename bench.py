@@ -243,7 +243,7 @@ def main():
             elif e["kind"] == 2:
                 fin_ms += e["ms"]
             else:
-                key = (e["la"], e["lb"], e["lc"], e["ld"])
+                key = (e["la"], e["lb"], e["lc"], e["ld"], e["team"])
                 acc = per_class.setdefault(key, dict(ms=0.0, flops=0.0, quartets=0, prim=0, team=e["team"]))
                 acc["ms"] += e["ms"]
                 acc["flops"] += e["flops"]
@@ -264,12 +264,16 @@ def main():
     class_ms = sum(v["ms"] for v in per_class.values()) / args.steps
     top = sorted(per_class.items(), key=lambda kv: -kv[1]["ms"])[:8]
     def cname(k):
-        return "(%d%d|**) tier %d" % (k[0], k[1], k[3]) if k[2] < 0 else "(%d%d|%d%d)" % k
+        if k[2] < 0:
+            return "(%d%d|**) tier %d%s" % (k[0], k[1], k[3], " FP32" if k[4] == 3 else "")
+        return "(%d%d|%d%d)" % k[:4]
 
     def kname(k, v):
         if v["team"] == 2:
             return "k_bra<%d,%d,%d>" % (k[0], k[1], k[3])
-        return "k_cls<%d,%d,%d,%d>" % k + (" team" if v["team"] else " lane")
+        if v["team"] == 3:
+            return "k_bra32<%d,%d,%d>" % (k[0], k[1], k[3])
+        return "k_cls<%d,%d,%d,%d>" % k[:4] + (" team" if v["team"] else " lane")
 
     classes = [{"class": cname(k), "kernel": kname(k, v),
                 "ms": round(v["ms"] / args.steps, 4), "quartets": v["quartets"] // args.steps,

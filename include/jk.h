@@ -136,7 +136,8 @@ int jk_stats(const jk_plan_t *plan, jk_stats_t *out);
 typedef struct {
   int kind;                     /* 0 class kernel, 1 preparation, 2 finalisation */
   int la, lb, lc, ld;           /* class (kind 0); lc = -1, ld = tier for a fused launch */
-  int team;                     /* 0 lane-per-quartet, 1 workgroup body, 2 fused bra-class launch */
+  int team;                     /* 0 lane-per-quartet, 1 workgroup body, 2 fused bra-class launch,
+                                   3 fused launch of the FP32 quartets (mixed precision) */
   int nroots;                   /* Rys roots N of the class */
   long long quartets;           /* kept unique shell quartets */
   long long prim_quartets;      /* their primitive quartets */

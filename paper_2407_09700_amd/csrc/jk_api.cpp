@@ -294,7 +294,8 @@ constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quar
 constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels (default)
 constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
 constexpr int NFUSED = NPAIRCLASS * NTIERS;     // launch slots of the fused kernels
-constexpr int NSLOT = NFUSED + NQCLASS;
+constexpr int NF32_BASE = NFUSED + NQCLASS;    // slots of the FP32-only fused launches (mixed precision)
+constexpr int NSLOT = NF32_BASE + NFUSED;
 const int TUNE_GRIDS[] = {256, 512, 1024, 2048};   // candidates of the grid tuner
 
 int ensure_scratch(jk_plan *p, long long doubles) {
@@ -707,7 +708,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
       (rc = dalloc(&p->d_Pblk, (size_t)p->ps_off[nmol])) || (rc = dalloc(&p->d_gmax, 1)) ||
       (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
-      (rc = dalloc(&p->d_nprim, NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
+      (rc = dalloc(&p->d_nprim, 2 * NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
       (rc = dalloc(&p->d_room, NQCLASS)) || (rc = dalloc(&p->d_overflow, 1)) ||
       (rc = dalloc(&p->d_next, NSLOT)) || (rc = dalloc(&p->d_nunits, NSLOT)))
     return cleanup(rc);
@@ -748,6 +749,8 @@ struct Launch {
   int qc;            // per class: quartet class; fused: -1
   int bra_beg, bra_end;   // bra pairs of the launch
   int mask;          // ket classes of the launch (bit ck)
+  int parts;         // segment parts: 1 FP64, 2 FP32, 3 both
+  bool f32;          // the FP32-only fused kernel
   int nc_max;        // fused: largest Cartesian size among the launch's molecules
   size_t lds;        // dynamic LDS bytes
   long long scratch_per_wg;
@@ -779,8 +782,13 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         if (split > beg) {
           const int ncm = p->mnc[m - 1];
           const size_t lds = (size_t)(na + nbb) * ncm * 8 + fixed;
-          out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], ncm, lds,
-                               bi.scratch_per_wg[tier]});
+          // mixed precision: the FP32 parts of the lane tiers run in their own FP32-only kernel
+          const bool sep = p->precision == JK_MIXED && bi.launch_bra32[tier] != nullptr;
+          out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], sep ? 1 : 3, false,
+                               ncm, lds, bi.scratch_per_wg[tier]});
+          if (sep)
+            out.push_back(Launch{NF32_BASE + cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], 2, true,
+                                 ncm, lds, bi.scratch_per_wg[tier]});
         }
       }
       if (split == end) continue;
@@ -789,7 +797,7 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         if (!((bi.tier_mask[tier] >> ck) & 1) || !active[qc]) continue;
         const ClassInfo &ci = g_classes[qc];
         const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;   // jab_s, pool
-        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 0, lds, ci.scratch_per_wg});
+        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 3, false, 0, lds, ci.scratch_per_wg});
       }
     }
   }
@@ -834,7 +842,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jpair, p->jp_total, 0ull, st));
   HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
   HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
-  HIPCHK(launch_fill_u64(p->d_nprim, NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_nprim, 2 * NQCLASS, 0ull, st));
   HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
   HIPCHK(launch_fill_i32(p->d_count32, NQCLASS, 0, st));
   HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
@@ -962,13 +970,14 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
     J_.units = p->d_units;
     J_.units_cap = p->units_cap;
     J_.nunits = p->d_nunits + L.slot;
-    HIPCHK(launch_units(p->d_segcnt, p->d_segcnt32, L.bra_beg, L.bra_end, L.mask, J_.slice, p->d_units, p->units_cap,
-                        p->d_nunits + L.slot, p->d_overflow, st));
+    J_.parts = L.parts;
+    HIPCHK(launch_units(p->d_segcnt, p->d_segcnt32, L.bra_beg, L.bra_end, L.mask, L.parts, J_.slice, p->d_units,
+                        p->units_cap, p->d_nunits + L.slot, p->d_overflow, st));
     J_.scratch_per_wg = L.scratch_per_wg;
     J_.next = p->d_next + L.slot;
     if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot], st));
     if (L.qc < 0)
-      HIPCHK(g_bras[L.cb].launch_bra[L.tier](J_, grid, L.lds, st));
+      HIPCHK((L.f32 ? g_bras[L.cb].launch_bra32[L.tier] : g_bras[L.cb].launch_bra[L.tier])(J_, grid, L.lds, st));
     else
       HIPCHK(g_classes[L.qc].launch_cls(J_, grid, L.lds, st));
     if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot + 1], st));
@@ -1048,6 +1057,9 @@ std::string slot_name(int slot) {
   if (slot < NFUSED) {
     const BraInfo &bi = g_bras[slot / NTIERS];
     snprintf(buf, sizeof(buf), "k_bra<%d,%d,%d>", bi.la, bi.lb, slot % NTIERS);
+  } else if (slot >= NF32_BASE) {
+    const BraInfo &bi = g_bras[(slot - NF32_BASE) / NTIERS];
+    snprintf(buf, sizeof(buf), "k_bra32<%d,%d,%d>", bi.la, bi.lb, (slot - NF32_BASE) % NTIERS);
   } else {
     const ClassInfo &ci = g_classes[slot - NFUSED];
     snprintf(buf, sizeof(buf), "k_cls<%d,%d,%d,%d>", ci.la, ci.lb, ci.lc, ci.ld);
@@ -1200,22 +1212,27 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
   if (!(p->flags & JK_FLAG_PROFILE)) return fail(JK_EINVAL, "plan was not created with JK_FLAG_PROFILE");
   if (p->launched.empty() && p->replays > 0) return fail(JK_EINVAL, "graph replays are not profiled");
   HIPCHK(hipStreamSynchronize(p->last_stream));
-  int cnt[NQCLASS];
-  unsigned long long np[NQCLASS];
+  int cnt[NQCLASS], c32[NQCLASS];
+  unsigned long long np[2 * NQCLASS];
   HIPCHK(hipMemcpy(cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(c32, p->d_count32, sizeof(c32), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(np, p->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
   int n = 0;
   auto push = [&](const jk_profile_t &e) {
     if (n < max_entries) out[n] = e;
     ++n;
   };
-  auto class_flops = [&](int qc, jk_profile_t &r) {
+  // parts: 3 every kept quartet of the class, 1 its FP64 ones, 2 its FP32 ones
+  auto class_flops = [&](int qc, jk_profile_t &r, int parts) {
     const ClassInfo &ci = g_classes[qc];
     double fp = 0.0, fq = 0.0;
     class_ops(ci.la, ci.lb, ci.lc, ci.ld, &fp, &fq);
-    r.quartets += cnt[qc];
-    r.prim_quartets += (long long)np[qc];
-    r.flops += (double)np[qc] * fp + (double)cnt[qc] * fq;
+    const double q = parts == 3 ? cnt[qc] : parts == 2 ? c32[qc] : cnt[qc] - c32[qc];
+    const double pq = parts == 3 ? (double)np[qc] : parts == 2 ? (double)np[NQCLASS + qc]
+                                                               : (double)(np[qc] - np[NQCLASS + qc]);
+    r.quartets += (long long)q;
+    r.prim_quartets += (long long)pq;
+    r.flops += pq * fp + q * fq;
   };
   float ms = 0.f;
   jk_profile_t e{};
@@ -1226,19 +1243,22 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
   for (int slot : p->launched) {
     jk_profile_t r{};
     r.kind = 0;
-    if (slot < NFUSED) {                          // fused launch of one tier of a bra class
-      const int cb = slot / NTIERS, tier = slot % NTIERS;
+    if (slot < NFUSED || slot >= NF32_BASE) {     // fused launch of one tier of a bra class
+      const bool f32 = slot >= NF32_BASE;
+      const int fs = f32 ? slot - NF32_BASE : slot;
+      const int cb = fs / NTIERS, tier = fs % NTIERS;
       const BraInfo &bi = g_bras[cb];
       r.la = bi.la; r.lb = bi.lb; r.lc = -1; r.ld = tier;
-      r.team = 2;
+      r.team = f32 ? 3 : 2;
+      const int parts = f32 ? 2 : (p->precision == JK_MIXED && bi.launch_bra32[tier]) ? 1 : 3;
       for (int ck = 0; ck <= cb; ++ck)
-        if ((bi.tier_mask[tier] >> ck) & 1) class_flops(qclass_index(cb, ck), r);
+        if ((bi.tier_mask[tier] >> ck) & 1) class_flops(qclass_index(cb, ck), r, parts);
     } else {
       const ClassInfo &ci = g_classes[slot - NFUSED];
       r.la = ci.la; r.lb = ci.lb; r.lc = ci.lc; r.ld = ci.ld;
       r.team = ci.team;
       r.nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
-      class_flops(slot - NFUSED, r);
+      class_flops(slot - NFUSED, r, 3);
     }
     HIPCHK(hipEventElapsedTime(&ms, p->events[2 * slot], p->events[2 * slot + 1]));
     r.ms = ms;

@@ -39,7 +39,7 @@ struct ScreenArgs {           // device pointers
   int *segoff32, *segcnt32;   // [npairs * 15] FP32 part of the segment (mixed precision) or null
   int *count;                 // [120] kept quartets per class (k_screen)
   int *count32;               // [120] of those, evaluated in FP32
-  unsigned long long *nprim;  // [120] primitive quartets of the kept quartets (k_screen)
+  unsigned long long *nprim;  // [240] primitive quartets of the kept quartets, then of the FP32 ones (k_screen)
   const long long *class_off; // [120] first entry of each class region in kets
   const long long *room;      // [120] entries available to each class region (k_class_off)
   int *kets;
@@ -71,7 +71,7 @@ hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *K
 hipError_t launch_fold(const FoldArgs &F, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int *p, long long n, int v, hipStream_t st);
-hipError_t launch_units(const int *segcnt, const int *segcnt32, int bra_beg, int bra_end, int mask, int slice,
-                        int2 *units, int units_cap, int *nunits, int *overflow, hipStream_t st);
+hipError_t launch_units(const int *segcnt, const int *segcnt32, int bra_beg, int bra_end, int mask, int parts,
+                        int slice, int2 *units, int units_cap, int *nunits, int *overflow, hipStream_t st);
 
 }  // namespace jk

@@ -158,9 +158,9 @@ __global__ void k_class_off(const unsigned long long *cap, long long *class_off,
 // length sit next to each other -- and its count.
 __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
   __shared__ int s_cnt[NQCLASS], s_c32[NQCLASS];
-  __shared__ unsigned long long s_np[NQCLASS];
+  __shared__ unsigned long long s_np[NQCLASS], s_np32[NQCLASS];
   __shared__ int s_pref[4][MAX_BINS + 1];          // per wave: candidate prefix over the bins
-  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) { s_cnt[t] = 0; s_c32[t] = 0; s_np[t] = 0ull; }
+  for (int t = threadIdx.x; t < NQCLASS; t += blockDim.x) { s_cnt[t] = 0; s_c32[t] = 0; s_np[t] = 0ull; s_np32[t] = 0ull; }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   int *pref = s_pref[threadIdx.x >> 6];
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
       int *out = A.kets + A.class_off[qc] + so;
       const double cut = ((A.f32_classes[qc >> 6] >> (qc & 63)) & 1ull) ? A.fp32_cut : 0.0;
       int kept = 0, kept32 = 0;
-      unsigned long long np = 0ull;
+      unsigned long long np = 0ull, np32 = 0ull;
       for (int k0 = 0; k0 < n; k0 += 64) {
         const int k = k0 + lane;
         bool keep = false, lo = false;
@@ -227,6 +227,7 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
           keep = bound >= tau;
           lo = keep && bound < cut;            // mixed precision: evaluated in FP32
           if (keep) np += nppb * (unsigned long long)A.pair_npp[kg];
+          if (lo) np32 += nppb * (unsigned long long)A.pair_npp[kg];
         }
         // FP64 kets fill the segment from the front, FP32 kets from the back
         const unsigned long long below = (1ull << lane) - 1ull;
@@ -237,7 +238,10 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
         kept32 += __popcll(m32);
       }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+      for (int o = 32; o > 0; o >>= 1) {
+        np += __shfl_xor(np, o);
+        np32 += __shfl_xor(np32, o);
+      }
       if (lane == 0) {
         const size_t sg = (size_t)i * NPAIRCLASS + ck;
         A.segcnt[sg] = kept;
@@ -249,7 +253,10 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
           atomicAdd(&s_cnt[qc], kept + kept32);
           atomicAdd(&s_np[qc], np);
         }
-        if (kept32) atomicAdd(&s_c32[qc], kept32);
+        if (kept32) {
+          atomicAdd(&s_c32[qc], kept32);
+          atomicAdd(&s_np32[qc], np32);
+        }
       }
       __threadfence_block();              // every lane has read pref before the next class rewrites it
       __builtin_amdgcn_wave_barrier();
@@ -260,7 +267,10 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
     if (s_cnt[t]) {
       atomicAdd(&A.count[t], s_cnt[t]);
       atomicAdd(&A.nprim[t], s_np[t]);
-      if (s_c32[t]) atomicAdd(&A.count32[t], s_c32[t]);
+      if (s_c32[t]) {
+        atomicAdd(&A.count32[t], s_c32[t]);
+        atomicAdd(&A.nprim[NQCLASS + t], s_np32[t]);
+      }
     }
 }
 
@@ -324,10 +334,12 @@ __global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long lon
 }
 
 // Work units of one integral launch: every bra pair of [bra_beg, bra_end) with kets in the
-// launch's ket classes (bit ck of mask) gives ceil(kets / slice) units (bra, slice index).
+// launch's ket classes (bit ck of mask) and segment parts (parts: 1 FP64, 2 FP32) gives
+// ceil(kets / slice) units (bra, slice index).
 // Units are handed out with one atomic per wave; their order does not matter.
 __global__ void k_units(const int *__restrict__ segcnt, const int *__restrict__ segcnt32, int bra_beg, int bra_end,
-                        int mask, int slice, int2 *__restrict__ units, int units_cap, int *nunits, int *overflow) {
+                        int mask, int parts, int slice, int2 *__restrict__ units, int units_cap, int *nunits,
+                        int *overflow) {
   const int lane = threadIdx.x & 63;
   const int bi = bra_beg + blockIdx.x * blockDim.x + threadIdx.x;
   int n = 0;
@@ -335,8 +347,8 @@ __global__ void k_units(const int *__restrict__ segcnt, const int *__restrict__ 
     long long tot = 0;
     for (int ck = 0; ck < NPAIRCLASS; ++ck)
       if ((mask >> ck) & 1) {
-        tot += segcnt[(size_t)bi * NPAIRCLASS + ck];
-        if (segcnt32) tot += segcnt32[(size_t)bi * NPAIRCLASS + ck];
+        if (parts & 1) tot += segcnt[(size_t)bi * NPAIRCLASS + ck];
+        if ((parts & 2) && segcnt32) tot += segcnt32[(size_t)bi * NPAIRCLASS + ck];
       }
     n = (int)((tot + slice - 1) / slice);
   }
@@ -404,11 +416,11 @@ hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long lon
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
-hipError_t launch_units(const int *segcnt, const int *segcnt32, int bra_beg, int bra_end, int mask, int slice,
-                        int2 *units, int units_cap, int *nunits, int *overflow, hipStream_t st) {
+hipError_t launch_units(const int *segcnt, const int *segcnt32, int bra_beg, int bra_end, int mask, int parts,
+                        int slice, int2 *units, int units_cap, int *nunits, int *overflow, hipStream_t st) {
   if (bra_end <= bra_beg) return hipSuccess;
   hipLaunchKernelGGL(k_units, dim3((bra_end - bra_beg + 255) / 256), dim3(256), 0, st, segcnt, segcnt32, bra_beg,
-                     bra_end, mask, slice, units, units_cap, nunits, overflow);
+                     bra_end, mask, parts, slice, units, units_cap, nunits, overflow);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(int *p, long long n, int v, hipStream_t st) {

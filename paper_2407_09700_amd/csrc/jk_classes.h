@@ -30,6 +30,7 @@ struct BraInfo {             // one bra class (la lb), per register tier
   int pool_bytes[NTIERS];    // team LDS of k_bra
   long long scratch_per_wg[NTIERS];  // doubles of global team buffer per workgroup
   jk_launch_fn launch_bra[NTIERS];   // k_bra (null if not fusable)
+  jk_launch_fn launch_bra32[NTIERS]; // FP32-only k_bra of the lane tiers (null for the team tier)
 };
 
 #define JK_DECL_BRA(LA, LB) void register_bra_##LA##LB(ClassInfo *classes, BraInfo *bras);

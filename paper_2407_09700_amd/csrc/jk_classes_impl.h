@@ -28,9 +28,9 @@ hipError_t launch_mode(const ModeArgs &args, int grid, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int LA, int LB, int TIER>
+template <int LA, int LB, int TIER, bool F32 = false>
 hipError_t launch_bra(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((k_bra<LA, LB, TIER>), dim3(grid), dim3(256), lds, stream, args);
+  hipLaunchKernelGGL((k_bra<LA, LB, TIER, F32>), dim3(grid), dim3(256), lds, stream, args);
   return hipGetLastError();
 }
 
@@ -73,9 +73,14 @@ void register_tier(BraInfo &b) {
   b.fusable[TIER] = bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0;
   b.pool_bytes[TIER] = bra_pool_bytes<LA, LB, TIER>();
   b.scratch_per_wg[TIER] = bra_scratch_doubles<LA, LB, TIER>();
+  b.launch_bra32[TIER] = nullptr;
   if constexpr (bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0) {
     b.launch_bra[TIER] = launch_bra<LA, LB, TIER>;
     allow_dyn_lds(k_bra<LA, LB, TIER>);
+    if constexpr (TIER < 2 && JK_FP32_BODIES) {
+      b.launch_bra32[TIER] = launch_bra<LA, LB, TIER, true>;
+      allow_dyn_lds(k_bra<LA, LB, TIER, true>);
+    }
   } else
     b.launch_bra[TIER] = nullptr;
 }

@@ -29,7 +29,10 @@
 
 namespace jk {
 
-constexpr int SMALL_REG_LIMIT = 320;   // lane per quartet when [e0|f0] accumulators + one root's 2D integrals fit
+#ifndef JK_SMALL_REG_LIMIT
+#define JK_SMALL_REG_LIMIT 200
+#endif
+constexpr int SMALL_REG_LIMIT = JK_SMALL_REG_LIMIT;   // lane per quartet when [e0|f0] accumulators + one root's 2D integrals fit
 constexpr int SMALL_OUT_LIMIT = 400;   // ... and the contracted block + the bra Coulomb partials fit
 
 template <int LA, int LB, int LC, int LD>
@@ -76,6 +79,7 @@ struct JKArgs {
   int slice;                    // kets per unit: a unit runs kets [j slice, (j+1) slice) of the bra's
                                 // kets in the launch, counted over the ket classes in order, FP64
                                 // part of each segment before its FP32 part
+  int parts;                    // segment parts of the launch: 1 FP64, 2 FP32, 3 both (k_bra)
   double *scratch;              // global buffers of the largest team classes
   long long scratch_per_wg;
 };
@@ -116,15 +120,8 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
   for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
     const int ki = kl[k];
     const Pair ket = A.pairs[ki];
-    double g[C::NG];
-    if constexpr (sizeof(R) == sizeof(double)) {
-      small_eri<LA, LB, LC, LD>(bra, ket, A.pp, g);
-    } else {
-      R gr[C::NG];
-      small_eri<LA, LB, LC, LD, R>(bra, ket, A.pp, gr);
-#pragma unroll
-      for (int e = 0; e < C::NG; ++e) g[e] = (double)gr[e];
-    }
+    R g[C::NG];                 // FP32 integrals stay FP32 in registers; each use widens to double
+    small_eri<LA, LB, LC, LD, R>(bra, ket, A.pp, g);
     const double s = sym_factor(bra, ket, bi, ki);
     const int oc = ket.ca, od = ket.cb;
     double Dcd[NC * ND];
@@ -136,14 +133,14 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
     for (int ab = 0; ab < NA * NB; ++ab) {
       double v = 0.0;
 #pragma unroll
-      for (int cd = 0; cd < NC * ND; ++cd) v = fma(g[ab * NC * ND + cd], Dcd[cd], v);
+      for (int cd = 0; cd < NC * ND; ++cd) v = fma((double)g[ab * NC * ND + cd], Dcd[cd], v);
       jab[ab] = fma(2.0 * s, v, jab[ab]);
     }
 #pragma unroll
     for (int cd = 0; cd < NC * ND; ++cd) {
       double v = 0.0;
 #pragma unroll
-      for (int ab = 0; ab < NA * NB; ++ab) v = fma(g[ab * NC * ND + cd], Dab[ab], v);
+      for (int ab = 0; ab < NA * NB; ++ab) v = fma((double)g[ab * NC * ND + cd], Dab[ab], v);
       atomic_add(jp_elem(A, ck, ki, cd), 2.0 * s * v);
     }
     // exchange: rows a (K[a,c] with D[b,d], K[a,d] with D[b,c]), rows b (K[b,c] with D[a,d], K[b,d] with D[a,c])
@@ -155,7 +152,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + od + d], v);
+          for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + od + d], v);
         k_update<KLDS>(Krow, Km, nc, a, bra.ca + a, oc + c, s * v);
       }
 #pragma unroll
@@ -164,7 +161,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + oc + c], v);
+          for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + oc + c], v);
         k_update<KLDS>(Krow, Km, nc, a, bra.ca + a, od + d, s * v);
       }
     }
@@ -176,7 +173,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int a = 0; a < NA; ++a)
 #pragma unroll
-          for (int d = 0; d < ND; ++d) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + od + d], v);
+          for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + od + d], v);
         k_update<KLDS>(Krow, Km, nc, NA + b, bra.cb + b, oc + c, s * v);
       }
 #pragma unroll
@@ -185,7 +182,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int a = 0; a < NA; ++a)
 #pragma unroll
-          for (int c = 0; c < NC; ++c) v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + oc + c], v);
+          for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + oc + c], v);
         k_update<KLDS>(Krow, Km, nc, NA + b, bra.cb + b, od + d, s * v);
       }
     }
@@ -474,7 +471,9 @@ constexpr long long bra_scratch_doubles() {
 
 // ------------------------------------------------------------------ fused kernel: one bra pair, every ket class
 // Dynamic LDS: Krow (NA+NB) x nc | jab_s NA*NB (padded to even) | team pool.
-template <int LA, int LB, int TIER>
+// F32: the FP32-only variant (lane tiers of mixed precision): it holds only the FP32 bodies,
+// so its register budget, and hence its occupancy, is set by them alone.
+template <int LA, int LB, int TIER, bool F32 = false>
 __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB);
   extern __shared__ double smem[];
@@ -508,11 +507,14 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
       const size_t sg = (size_t)bi * NPAIRCLASS + ck;
       const int *cls_kets = A.kets + A.class_off[qclass_index(cb, ck)];
       for (int part = 0; part < 2; ++part) {   // FP64 part, then FP32 part of the segment
+        if (!((A.parts >> part) & 1)) continue; // parts this launch runs
         const int n = part ? (A.segcnt32 ? A.segcnt32[sg] : 0) : A.segcnt[sg];
         const long long b0 = lo > pos ? lo : pos, b1 = hi < pos + n ? hi : pos + n;
         if (b1 > b0) {
           const int *kl = cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]) + (b0 - pos);
-          if constexpr (TIER == 2 || !JK_FP32_BODIES)   // team bodies evaluate the FP32 part in double
+          if constexpr (F32)
+            ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
+          else if constexpr (TIER == 2 || !JK_FP32_BODIES)   // team bodies evaluate the FP32 part in double
             ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
           else if (part == 0)
             ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
