@@ -202,6 +202,40 @@ __device__ __forceinline__ void vrr2d(R (&G)[E + 1][F + 1], R g00, R c00, R c00p
   }
 }
 
+// The same table written to dst[e * (F + 1) + f] (LDS) column by column, so that only three
+// columns are live in registers (the workgroup bodies hold their accumulators meanwhile).
+template <int E, int F>
+__device__ __forceinline__ void vrr2d_store(double *dst, double g00, double c00, double c00p, double b10, double b01,
+                                            double b00) {
+  double prev[E + 1], cur[E + 1];
+  cur[0] = g00;
+  if constexpr (E > 0) cur[1] = c00 * g00;
+#pragma unroll
+  for (int e = 1; e < E; ++e) cur[e + 1] = fma(c00, cur[e], (double)e * b10 * cur[e - 1]);
+#pragma unroll
+  for (int e = 0; e <= E; ++e) {
+    dst[e * (F + 1)] = cur[e];
+    prev[e] = 0.0;
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    double nxt[E + 1];
+#pragma unroll
+    for (int e = 0; e <= E; ++e) {
+      double v = c00p * cur[e];
+      if (f > 0) v = fma((double)f * b01, prev[e], v);
+      if (e > 0) v = fma((double)e * b00, cur[e - 1], v);
+      nxt[e] = v;
+      dst[e * (F + 1) + f + 1] = v;
+    }
+#pragma unroll
+    for (int e = 0; e <= E; ++e) {
+      prev[e] = cur[e];
+      cur[e] = nxt[e];
+    }
+  }
+}
+
 // Per-primitive-quartet scalars shared by the roots.
 struct PrimQuartet {
   double p, q, pq_inv, PQ[3], PA[3], QC[3], pref, T;

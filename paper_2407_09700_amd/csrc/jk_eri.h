@@ -15,6 +15,20 @@
 #pragma once
 #include "jk_device.h"
 
+// Accumulators per lane in the workgroup body (more: fewer lanes per quartet, smaller blocks,
+// more registers per lane)
+#ifndef JK_TEAM_EMAX
+#define JK_TEAM_EMAX 48
+#endif
+
+// LDS budget (KB) and largest primitive chunk of the one-stage workgroup body
+#ifndef JK_TEAM2_KB
+#define JK_TEAM2_KB 48
+#endif
+#ifndef JK_TEAM2_PCMAX
+#define JK_TEAM2_PCMAX 4
+#endif
+
 // 1 and 2 roots from the closed-form rule (Boys moments) instead of the interpolation table
 // (off: the table measured faster for the light classes)
 #ifndef JK_CLOSED_LOW_ROOTS
@@ -170,7 +184,7 @@ struct TeamCfg {
   static constexpr int NE = range_count(LA, E), NF = range_count(LC, F);
   static constexpr int GS1 = (E + 1) * (F + 1);          // one direction of one root
   static constexpr int GS = 3 * GS1;
-  static constexpr int EMAXACC = 56;                     // accumulators per lane
+  static constexpr int EMAXACC = JK_TEAM_EMAX;           // accumulators per lane
   // Product roles. f-major: a lane owns one f component and a slice of EPS e components
   // (NEP slices per f, each slice wave-uniform). e-major (few f, many e): a lane owns one e
   // component and all NF f components, so that small ket classes keep the lanes busy.
@@ -315,13 +329,8 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
         const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
         const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
         const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
-        double G[E + 1][F + 1];
-        vrr2d<E, F>(G, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
         double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
-#pragma unroll
-        for (int e = 0; e <= E; ++e)
-#pragma unroll
-          for (int f = 0; f <= F; ++f) dst[e * (F + 1) + f] = G[e][f];
+        vrr2d_store<E, F>(dst, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
       }
     }
     __syncthreads();
@@ -461,15 +470,18 @@ struct Team2Cfg {
   static constexpr bool OK = NE <= 56 && NF <= 256;
   static constexpr int YS = NA * NB * NF;
   static constexpr int QB0 = 256 / NF;
-  static constexpr int BUDGET = 48 * 1024 / 8;                   // doubles of LDS for G + Y
-  static constexpr int QB1 = BUDGET / (YS + N * GS);             // at least one primitive chunk
+  // The 2D integrals of a primitive chunk and, once the primitive loop is done, the
+  // bra-transferred Y share one LDS region of BUDGET doubles.
+  static constexpr int BUDGET = JK_TEAM2_KB * 1024 / 8;
+  static constexpr int QB1 = BUDGET / (YS > N * GS ? YS : N * GS);   // Y fits, and one primitive chunk
   static constexpr int QB = (QB0 < QB1 ? QB0 : QB1) < 1 ? 1 : (QB0 < QB1 ? QB0 : QB1);
-  static constexpr int PCB = (BUDGET - QB * YS) / (QB * N * GS);
+  static constexpr int PCB = BUDGET / (QB * N * GS);
   static constexpr int PCT = 256 / (QB * N * 3);                 // VRR items in one pass of the block
   static constexpr int PC0 = PCB < PCT ? PCB : PCT;
-  static constexpr int PC = PC0 < 1 ? 1 : (PC0 > 4 ? 4 : PC0);
+  static constexpr int PC = PC0 < 1 ? 1 : (PC0 > JK_TEAM2_PCMAX ? JK_TEAM2_PCMAX : PC0);
   static constexpr int SG = QB * PC * N * GS;
-  static constexpr int LDS_DOUBLES = SG + QB * YS + QB * 12;
+  static constexpr int SGY = SG > QB * YS ? SG : QB * YS;       // the shared region
+  static constexpr int LDS_DOUBLES = SGY + QB * 12;
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
@@ -527,13 +539,8 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
         const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
         const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
         const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
-        double G[E + 1][F + 1];
-        vrr2d<E, F>(G, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
         double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
-#pragma unroll
-        for (int e = 0; e <= E; ++e)
-#pragma unroll
-          for (int f = 0; f <= F; ++f) dst[e * (F + 1) + f] = G[e][f];
+        vrr2d_store<E, F>(dst, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
       }
     }
     __syncthreads();

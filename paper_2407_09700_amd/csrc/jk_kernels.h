@@ -33,7 +33,10 @@ namespace jk {
 #define JK_SMALL_REG_LIMIT 200
 #endif
 constexpr int SMALL_REG_LIMIT = JK_SMALL_REG_LIMIT;   // lane per quartet when [e0|f0] accumulators + one root's 2D integrals fit
-constexpr int SMALL_OUT_LIMIT = 400;   // ... and the contracted block + the bra Coulomb partials fit
+#ifndef JK_SMALL_OUT_LIMIT
+#define JK_SMALL_OUT_LIMIT 200
+#endif
+constexpr int SMALL_OUT_LIMIT = JK_SMALL_OUT_LIMIT;   // ... and the contracted block + the bra Coulomb partials fit
 
 template <int LA, int LB, int LC, int LD>
 constexpr bool use_team() {
@@ -304,8 +307,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, QB = C::QB;
   constexpr int ck = pair_class(LC, LD);
   double *sG = pool;
-  double *Y = pool + C::SG;
-  double *geo = Y + QB * C::YS;
+  double *Y = pool;                      // written after the primitive loop, over the 2D integrals
+  double *geo = pool + C::SGY;
   int *qi = reinterpret_cast<int *>(geo + QB * 12);
   int *smax = qi + QB * 8;
   const Pair bra = A.pairs[bi];
