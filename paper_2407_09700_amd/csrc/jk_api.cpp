@@ -343,6 +343,7 @@ void build_pairs(const jk_basis_t *B, const double *coords, const int *cart_off,
           q.Py = (ea * A[1] + eb * Bc[1]) / q.p;
           q.Pz = (ea * A[2] + eb * Bc[2]) / q.p;
           q.K = ca * cb * std::exp(-ea * eb / q.p * ab2);
+          q.ip = 1.0 / q.p;
           pps.push_back(q);
         }
       pairs.push_back(P);

@@ -26,7 +26,8 @@ struct alignas(16) Pair {
 // One primitive pair: exponent sum p = a + b, product centre P = (aA + bB)/p and
 // K = c_a c_b exp(-a b |A-B|^2 / p) (the contraction coefficients are folded in).
 struct alignas(16) PrimPair {
-  double p, Px, Py, Pz, K, rsv;
+  double p, Px, Py, Pz, K;
+  double ip;             // 1 / p
 };
 
 // Parameters of one class launch.

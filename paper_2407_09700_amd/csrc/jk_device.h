@@ -238,21 +238,24 @@ __device__ __forceinline__ void vrr2d_store(double *dst, double g00, double c00,
 
 // Per-primitive-quartet scalars shared by the roots.
 struct PrimQuartet {
-  double p, q, pq_inv, PQ[3], PA[3], QC[3], pref, T;
+  double p, q, ip, iq, pq_inv, PQ[3], PA[3], QC[3], pref, T;
 };
 
 __device__ __forceinline__ void prim_quartet(const PrimPair &b, const PrimPair &k, const double *A, const double *C,
                                              PrimQuartet &o) {
   o.p = b.p;
   o.q = k.p;
-  const double pq = b.p + k.p;
-  o.pq_inv = 1.0 / pq;
+  o.ip = b.ip;
+  o.iq = k.ip;
+  // one reciprocal square root gives both 1/(p+q) and the 1/sqrt(p+q) of the prefactor
+  const double r = rsqrt(b.p + k.p);
+  o.pq_inv = r * r;
   o.PQ[0] = b.Px - k.Px; o.PQ[1] = b.Py - k.Py; o.PQ[2] = b.Pz - k.Pz;
   o.PA[0] = b.Px - A[0]; o.PA[1] = b.Py - A[1]; o.PA[2] = b.Pz - A[2];
   o.QC[0] = k.Px - C[0]; o.QC[1] = k.Py - C[1]; o.QC[2] = k.Pz - C[2];
   const double rho = b.p * k.p * o.pq_inv;
   o.T = rho * (o.PQ[0] * o.PQ[0] + o.PQ[1] * o.PQ[1] + o.PQ[2] * o.PQ[2]);
-  o.pref = PI_2P5_X2 / (b.p * k.p * sqrt(pq)) * b.K * k.K;
+  o.pref = PI_2P5_X2 * (b.ip * k.ip) * r * (b.K * k.K);
 }
 
 // Symmetry factor of a unique shell quartet: 1 / |stabiliser| in the eight-fold group.

@@ -60,14 +60,24 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 #pragma unroll
   for (int i = 0; i < NE * NF; ++i) acc[i] = (R)0;
 
-  for (int ib = 0; ib < bra.npp; ++ib) {
-    const PrimPair pb = pp[bra.pp_off + ib];
-    const double hp = 0.5 / pb.p;
-    for (int ik = 0; ik < ket.npp; ++ik) {
-      const PrimPair pk = pp[ket.pp_off + ik];
+  // primitive quartets (ib, ik) in one flat loop; the pairs of the next quartet are loaded
+  // one iteration ahead so that their latency overlaps the current quartet's arithmetic
+  const int npk = ket.npp, ntot = bra.npp * ket.npp;
+  int ik = 0;
+  PrimPair pb = pp[bra.pp_off], pk = pp[ket.pp_off];
+  int nb_next = 1;                      // bra primitive the next bra load fetches
+  for (int it = 0; it < ntot; ++it) {
+    const bool new_bra = ik + 1 == npk;
+    PrimPair pkn = pk, pbn = pb;
+    if (it + 1 < ntot) {
+      pkn = pp[ket.pp_off + (new_bra ? 0 : ik + 1)];
+      if (new_bra) pbn = pp[bra.pp_off + nb_next];
+    }
+    {
+      const double hp = 0.5 * pb.ip;
       PrimQuartet Q;
       prim_quartet(pb, pk, bra.A, ket.A, Q);
-      const double hq = 0.5 / pk.p;
+      const double hq = 0.5 * pk.ip;
       auto root = [&](double un, double wn) {
         const double uq = un * Q.pq_inv;
         const R b00 = (R)(0.5 * uq);
@@ -100,6 +110,14 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
           root(un, wn);
         }
       }
+    }
+    pk = pkn;
+    pb = pbn;
+    if (new_bra) {
+      ik = 0;
+      ++nb_next;
+    } else {
+      ++ik;
     }
   }
 
@@ -177,6 +195,32 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 }
 
 // ================================================================== workgroup per batch
+// Number of e slices per f component in the f-major product: the count (each slice at most
+// emax accumulators) that keeps the largest share of a 256-lane block busy.
+// Candidates whose accumulators and per-root 2D values (2 registers per double, plus ~48
+// registers of other state) would not fit the register share of their block are skipped.
+constexpr int team_slices(int ne, int nf, int emax, int e) {
+  int best = (ne + emax - 1) / emax;
+  double best_util = -1.0;
+  for (int nep = 1; nep <= 8; ++nep) {
+    const int eps = (ne + nep - 1) / nep;
+    if (eps > emax) continue;
+    const int fw = nep > 1 ? ((nf + 63) / 64) * 64 : nf;
+    const int tpq = nep * fw;
+    const int block = tpq > 256 ? ((tpq + 63) / 64) * 64 : 256;
+    const int waves_per_simd = (block + 255) / 256;
+    const int reg_cap = 512 / waves_per_simd > 256 && waves_per_simd > 1 ? 256 : 512 / waves_per_simd;
+    if (2 * (eps + 3 * (e + 1)) + 48 > reg_cap) continue;
+    const int qb = block / tpq;
+    const double util = (double)(qb * nep * nf) / block;
+    if (util > best_util + 1e-9) {
+      best_util = util;
+      best = nep;
+    }
+  }
+  return best;
+}
+
 template <int LA, int LB, int LC, int LD>
 struct TeamCfg {
   static constexpr int E = LA + LB, F = LC + LD, N = (E + F) / 2 + 1;
@@ -189,7 +233,7 @@ struct TeamCfg {
   // (NEP slices per f, each slice wave-uniform). e-major (few f, many e): a lane owns one e
   // component and all NF f components, so that small ket classes keep the lanes busy.
   static constexpr bool EMAJOR = NF <= EMAXACC && NE > NF && NE <= 256;
-  static constexpr int NEP = EMAJOR ? 1 : (NE + EMAXACC - 1) / EMAXACC;
+  static constexpr int NEP = EMAJOR ? 1 : team_slices(NE, NF, EMAXACC, E);
   static constexpr int EPS = EMAJOR ? NF : (NE + NEP - 1) / NEP;   // accumulators per lane
   static constexpr int FW = EMAJOR ? 0 : (NEP > 1 ? ((NF + 63) / 64) * 64 : NF);
   static constexpr int TPQ = EMAJOR ? NE : NEP * FW;
@@ -199,7 +243,9 @@ struct TeamCfg {
   static constexpr int R1_ = (NE * NF > NA * NB * NC * ND) ? NE * NF : NA * NB * NC * ND;
   static constexpr int QBB = (48 * 1024) / ((R1_ + NA * NB * NF) * 8);   // transfer buffers in 48 KB of LDS
   static constexpr int QB1 = QB0 < QBL ? QB0 : QBL;
-  static constexpr int QB2 = QB1 < QBB ? QB1 : QBB;
+  // the transfer buffers limit QB only while they are meant to stay in LDS
+  static constexpr bool BUF_LDS = QB1 * (R1_ + NA * NB * NF) * 8 <= 48 * 1024;
+  static constexpr int QB2 = BUF_LDS ? QB1 : (QB1 < 4 ? QB1 : 4);
   static constexpr int QB = QB2 < 1 ? 1 : QB2;
   static constexpr int PC0 = (40 * 1024) / (QB * N * GS * 8);
   static constexpr int PC1 = BLOCK / (QB * N * 3);
@@ -324,8 +370,8 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
         rys_root1<N>(Q.T, n, u, w);
         const double uq = u * Q.pq_inv;
         const double b00 = 0.5 * uq;
-        const double b10 = 0.5 / Q.p * (1.0 - uq * Q.q);
-        const double b01 = 0.5 / Q.q * (1.0 - uq * Q.p);
+        const double b10 = 0.5 * Q.ip * (1.0 - uq * Q.q);
+        const double b01 = 0.5 * Q.iq * (1.0 - uq * Q.p);
         const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
         const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
         const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
@@ -534,8 +580,8 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
         rys_root1<N>(Q.T, n, u, w);
         const double uq = u * Q.pq_inv;
         const double b00 = 0.5 * uq;
-        const double b10 = 0.5 / Q.p * (1.0 - uq * Q.q);
-        const double b01 = 0.5 / Q.q * (1.0 - uq * Q.p);
+        const double b10 = 0.5 * Q.ip * (1.0 - uq * Q.q);
+        const double b01 = 0.5 * Q.iq * (1.0 - uq * Q.p);
         const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
         const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
         const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
