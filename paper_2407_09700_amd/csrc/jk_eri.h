@@ -256,7 +256,9 @@ struct TeamCfg {
   static constexpr bool GLOBAL_BUF = BUF * 8 > 48 * 1024;
   static constexpr int SG = QB * PC * N * GS;
   // LDS carved by team_eri: 2D integrals, (buffer), geometry; descriptors are ints
-  static constexpr int LDS_DOUBLES = SG + (GLOBAL_BUF ? 0 : BUF) + QB * 12;
+  // per-quartet digestion accumulators: K[a,c], K[a,d], K[b,c], K[b,d] and J[c,d]
+  static constexpr int DG = NA * NC + NA * ND + NB * NC + NB * ND + NC * ND;
+  static constexpr int LDS_DOUBLES = SG + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };

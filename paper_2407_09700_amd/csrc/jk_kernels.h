@@ -194,6 +194,8 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 
 // ------------------------------------------------------------------ workgroup body
 // pool: TeamCfg::LDS_BYTES of LDS; jab_s: NA*NB doubles of LDS (bra Coulomb block).
+// Ket blocks of at least this many components use the streaming digestion.
+constexpr int TEAM_STREAM_MIN = 24;
 template <int LA, int LB, int LC, int LD, bool KLDS>
 __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                              double *jab_s, double *pool) {
@@ -202,7 +204,8 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   constexpr int ck = pair_class(LC, LD);
   double *sG = pool;
   double *lbuf = pool + C::SG;
-  double *geo = lbuf + (C::GLOBAL_BUF ? 0 : C::BUF);
+  double *dg = lbuf + (C::GLOBAL_BUF ? 0 : C::BUF);   // QB x DG digestion accumulators
+  double *geo = dg + QB * C::DG;
   int *qi = reinterpret_cast<int *>(geo + QB * 12);
   int *smax = qi + QB * 8;
   double *buf = C::GLOBAL_BUF ? A.scratch + (size_t)blockIdx.x * A.scratch_per_wg : lbuf;
@@ -211,8 +214,6 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   const int nc = A.mnc[bra.mol];
   const double *Dm = A.Dc + A.mbase[bra.mol];
   double *Km = A.Kc + A.mbase[bra.mol];
-  constexpr int T1 = NA * NB, T2 = NC * ND, T3 = NA * NC, T4 = NA * ND, T5 = NB * NC, T6 = NB * ND;
-  constexpr int TOT = T1 + T2 + T3 + T4 + T5 + T6;
   for (int k0 = 0; k0 < cnt; k0 += QB) {
     if (tid < QB) {
       const int k = k0 + tid;
@@ -222,77 +223,183 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     }
     __syncthreads();
     const double *Z = team_eri<LA, LB, LC, LD>(A.pp, sG, buf, qi, geo, smax);
-    for (int t = tid; t < QB * TOT; t += blockDim.x) {
-      const int q = t / TOT;
-      int r = t % TOT;
+    constexpr int NCD = NC * ND, CH = (NCD + 63) / 64;
+    if constexpr (NCD < TEAM_STREAM_MIN) {
+      // Small ket blocks: one task per output element, its sum loaded in unrolled batches.
+      constexpr int T1 = NA * NB, T2 = NC * ND, T3 = NA * NC, T4 = NA * ND, T5 = NB * NC;
+      constexpr int TOT = T1 + T2 + T3 + T4 + T5 + NB * ND;
+      for (int t = tid; t < QB * TOT; t += blockDim.x) {
+        const int q = t / TOT;
+        int r = t % TOT;
+        if (!qi[q * 8 + 6]) continue;
+        const int ki = qi[q * 8 + 1];
+        const Pair &ket = A.pairs[ki];
+        const double s = sym_factor(bra, ket, bi, ki);
+        const int oa = bra.ca, ob = bra.cb, oc = ket.ca, od = ket.cb;
+        const double *g = Z + (size_t)q * NA * NB * NC * ND;
+        double v = 0.0;
+        // the sums below are unrolled so that their loads (g and D) are in flight together
+        if (r < T1) {                       // J[a,b] += 2s sum_cd g D[c,d]
+          const int a = r / NB, b = r % NB;
+          const double *gr = g + (a * NB + b) * NC * ND;
+#pragma unroll 16
+          for (int i = 0; i < NC * ND; ++i) v = fma(gr[i], Dm[(size_t)(oc + i / ND) * nc + od + i % ND], v);
+          atomicAdd(&jab_s[r], 2.0 * s * v);
+          continue;
+        }
+        r -= T1;
+        if (r < T2) {                       // J[c,d] += 2s sum_ab g D[a,b]
+          const int c = r / ND, d = r % ND;
+#pragma unroll 16
+          for (int i = 0; i < NA * NB; ++i)
+            v = fma(g[i * NC * ND + c * ND + d], Dm[(size_t)(oa + i / NB) * nc + ob + i % NB], v);
+          atomic_add(jp_elem(A, ck, ki, r), 2.0 * s * v);
+          continue;
+        }
+        r -= T2;
+        if (r < T3) {                       // K[a,c] += s sum_bd g D[b,d]
+          const int a = r / NC, c = r % NC;
+#pragma unroll 16
+          for (int i = 0; i < NB * ND; ++i) {
+            const int b = i / ND, d = i % ND;
+            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + od + d], v);
+          }
+          k_update<KLDS>(Krow, Km, nc, a, oa + a, oc + c, s * v);
+          continue;
+        }
+        r -= T3;
+        if (r < T4) {                       // K[a,d] += s sum_bc g D[b,c]
+          const int a = r / ND, d = r % ND;
+#pragma unroll 16
+          for (int i = 0; i < NB * NC; ++i) {
+            const int b = i / NC, c = i % NC;
+            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + oc + c], v);
+          }
+          k_update<KLDS>(Krow, Km, nc, a, oa + a, od + d, s * v);
+          continue;
+        }
+        r -= T4;
+        if (r < T5) {                       // K[b,c] += s sum_ad g D[a,d]
+          const int b = r / NC, c = r % NC;
+#pragma unroll 16
+          for (int i = 0; i < NA * ND; ++i) {
+            const int a = i / ND, d = i % ND;
+            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + od + d], v);
+          }
+          k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, oc + c, s * v);
+          continue;
+        }
+        r -= T5;
+        {                                   // K[b,d] += s sum_ac g D[a,c]
+          const int b = r / ND, d = r % ND;
+#pragma unroll 16
+          for (int i = 0; i < NA * NC; ++i) {
+            const int a = i / NC, c = i % NC;
+            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + oc + c], v);
+          }
+          k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, od + d, s * v);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    // Digestion, every integral read once: each wave streams rows (a, b) of the block, its
+    // lanes run over (c, d). J[a,b] is wave-reduced per row; J[c,d], K[a,c] and K[a,d] collect
+    // in registers; K[b,c] and K[b,d] in LDS. The per-quartet sums are flushed below.
+    for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    for (int q = 0; q < QB; ++q) {
       if (!qi[q * 8 + 6]) continue;
+      const int ki = qi[q * 8 + 1];
+      const Pair &ket = A.pairs[ki];
+      const double s2 = 2.0 * sym_factor(bra, ket, bi, ki);
+      const int oa = bra.ca, ob = bra.cb, oc = ket.ca, od = ket.cb;
+      const double *g = Z + (size_t)q * NA * NB * NCD;
+      double *kac = dg + q * C::DG, *kad = kac + NA * NC, *kbc = kad + NA * ND, *kbd = kbc + NB * NC;
+      double *jcd = kbd + NB * ND;
+      int cc[CH], dd[CH];
+      bool on[CH];
+      double dcd[CH], jcda[CH];
+#pragma unroll
+      for (int h = 0; h < CH; ++h) {
+        const int cd = h * 64 + lane;
+        on[h] = cd < NCD;
+        cc[h] = on[h] ? cd / ND : 0;
+        dd[h] = on[h] ? cd % ND : 0;
+        dcd[h] = on[h] ? Dm[(size_t)(oc + cc[h]) * nc + od + dd[h]] : 0.0;
+        jcda[h] = 0.0;
+      }
+      for (int a = wave; a < NA; a += nwave) {
+        double dad[CH], dac[CH], kacs[CH], kads[CH];
+#pragma unroll
+        for (int h = 0; h < CH; ++h) {
+          dad[h] = on[h] ? Dm[(size_t)(oa + a) * nc + od + dd[h]] : 0.0;
+          dac[h] = on[h] ? Dm[(size_t)(oa + a) * nc + oc + cc[h]] : 0.0;
+          kacs[h] = 0.0;
+          kads[h] = 0.0;
+        }
+        for (int b = 0; b < NB; ++b) {
+          const int row = a * NB + b;
+          const double dab = Dm[(size_t)(oa + a) * nc + ob + b];
+          double vab = 0.0;
+#pragma unroll
+          for (int h = 0; h < CH; ++h) {
+            if (!on[h]) continue;
+            const double x = g[(size_t)row * NCD + h * 64 + lane];
+            vab = fma(x, dcd[h], vab);
+            jcda[h] = fma(x, dab, jcda[h]);
+            kacs[h] = fma(x, Dm[(size_t)(ob + b) * nc + od + dd[h]], kacs[h]);
+            kads[h] = fma(x, Dm[(size_t)(ob + b) * nc + oc + cc[h]], kads[h]);
+            atomicAdd(&kbc[b * NC + cc[h]], x * dad[h]);
+            atomicAdd(&kbd[b * ND + dd[h]], x * dac[h]);
+          }
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) vab += __shfl_xor(vab, o);
+          if (lane == 0 && vab != 0.0) atomicAdd(&jab_s[row], s2 * vab);
+        }
+#pragma unroll
+        for (int h = 0; h < CH; ++h)
+          if (on[h]) {
+            atomicAdd(&kac[a * NC + cc[h]], kacs[h]);
+            atomicAdd(&kad[a * ND + dd[h]], kads[h]);
+          }
+      }
+#pragma unroll
+      for (int h = 0; h < CH; ++h)
+        if (on[h]) atomicAdd(&jcd[h * 64 + lane], jcda[h]);
+    }
+    __syncthreads();
+    for (int t = tid; t < QB * C::DG; t += blockDim.x) {
+      const int q = t / C::DG;
+      int r = t % C::DG;
+      const double v = dg[t];
+      if (!qi[q * 8 + 6] || v == 0.0) continue;
       const int ki = qi[q * 8 + 1];
       const Pair &ket = A.pairs[ki];
       const double s = sym_factor(bra, ket, bi, ki);
       const int oa = bra.ca, ob = bra.cb, oc = ket.ca, od = ket.cb;
-      const double *g = Z + (size_t)q * NA * NB * NC * ND;
-      double v = 0.0;
-      // the sums below are unrolled so that their loads (g and D) are in flight together
-      if (r < T1) {                       // J[a,b] += 2s sum_cd g D[c,d]
-        const int a = r / NB, b = r % NB;
-        const double *gr = g + (a * NB + b) * NC * ND;
-#pragma unroll 16
-        for (int i = 0; i < NC * ND; ++i) v = fma(gr[i], Dm[(size_t)(oc + i / ND) * nc + od + i % ND], v);
-        atomicAdd(&jab_s[r], 2.0 * s * v);
+      if (r < NA * NC) {                                // K[a,c] += s sum_bd g D[b,d]
+        k_update<KLDS>(Krow, Km, nc, r / NC, oa + r / NC, oc + r % NC, s * v);
         continue;
       }
-      r -= T1;
-      if (r < T2) {                       // J[c,d] += 2s sum_ab g D[a,b]
-        const int c = r / ND, d = r % ND;
-#pragma unroll 16
-        for (int i = 0; i < NA * NB; ++i)
-          v = fma(g[i * NC * ND + c * ND + d], Dm[(size_t)(oa + i / NB) * nc + ob + i % NB], v);
-        atomic_add(jp_elem(A, ck, ki, r), 2.0 * s * v);
+      r -= NA * NC;
+      if (r < NA * ND) {                                // K[a,d] += s sum_bc g D[b,c]
+        k_update<KLDS>(Krow, Km, nc, r / ND, oa + r / ND, od + r % ND, s * v);
         continue;
       }
-      r -= T2;
-      if (r < T3) {                       // K[a,c] += s sum_bd g D[b,d]
-        const int a = r / NC, c = r % NC;
-#pragma unroll 16
-        for (int i = 0; i < NB * ND; ++i) {
-          const int b = i / ND, d = i % ND;
-          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + od + d], v);
-        }
-        k_update<KLDS>(Krow, Km, nc, a, oa + a, oc + c, s * v);
+      r -= NA * ND;
+      if (r < NB * NC) {                                // K[b,c] += s sum_ad g D[a,d]
+        k_update<KLDS>(Krow, Km, nc, NA + r / NC, ob + r / NC, oc + r % NC, s * v);
         continue;
       }
-      r -= T3;
-      if (r < T4) {                       // K[a,d] += s sum_bc g D[b,c]
-        const int a = r / ND, d = r % ND;
-#pragma unroll 16
-        for (int i = 0; i < NB * NC; ++i) {
-          const int b = i / NC, c = i % NC;
-          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + oc + c], v);
-        }
-        k_update<KLDS>(Krow, Km, nc, a, oa + a, od + d, s * v);
+      r -= NB * NC;
+      if (r < NB * ND) {                                // K[b,d] += s sum_ac g D[a,c]
+        k_update<KLDS>(Krow, Km, nc, NA + r / ND, ob + r / ND, od + r % ND, s * v);
         continue;
       }
-      r -= T4;
-      if (r < T5) {                       // K[b,c] += s sum_ad g D[a,d]
-        const int b = r / NC, c = r % NC;
-#pragma unroll 16
-        for (int i = 0; i < NA * ND; ++i) {
-          const int a = i / ND, d = i % ND;
-          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + od + d], v);
-        }
-        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, oc + c, s * v);
-        continue;
-      }
-      r -= T5;
-      {                                   // K[b,d] += s sum_ac g D[a,c]
-        const int b = r / ND, d = r % ND;
-#pragma unroll 16
-        for (int i = 0; i < NA * NC; ++i) {
-          const int a = i / NC, c = i % NC;
-          v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + oc + c], v);
-        }
-        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, od + d, s * v);
-      }
+      r -= NB * ND;                                     // J[c,d] += 2s sum_ab g D[a,b]
+      atomic_add(jp_elem(A, ck, ki, r), 2.0 * s * v);
     }
     __syncthreads();
   }
