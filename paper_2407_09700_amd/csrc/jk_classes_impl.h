@@ -43,7 +43,10 @@ void register_one(ClassInfo *table) {
     ci.team = 1;
     ci.block = C::BLOCK;
     ci.per_block = C::QB;
-    ci.team_lds = team_lds_bytes<LA, LB, LC, LD>();
+    // k_cls sends exchange to global memory: the one-stage body then also needs its
+    // per-quartet exchange blocks in LDS
+    ci.team_lds = team_lds_bytes<LA, LB, LC, LD>() +
+                  (use_team2<LA, LB, LC, LD>() ? Team2Cfg<LA, LB, LC, LD>::QB * Team2Cfg<LA, LB, LC, LD>::KQ * 8 : 0);
     ci.scratch_per_wg = C::GLOBAL_BUF ? (long long)C::BUF : 0;
   } else {
     ci.team = 0;

@@ -529,7 +529,8 @@ struct Team2Cfg {
   static constexpr int PC = PC0 < 1 ? 1 : (PC0 > JK_TEAM2_PCMAX ? JK_TEAM2_PCMAX : PC0);
   static constexpr int SG = QB * PC * N * GS;
   static constexpr int SGY = SG > QB * YS ? SG : QB * YS;       // the shared region
-  static constexpr int LDS_DOUBLES = SGY + QB * 12;
+  static constexpr int KQ = (NA + NB) * (NC + ND);               // exchange block of one quartet
+  static constexpr int LDS_DOUBLES = SGY + QB * 12;              // + QB * KQ when K goes to global memory
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };

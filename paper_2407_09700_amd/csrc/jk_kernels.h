@@ -415,7 +415,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
   constexpr int ck = pair_class(LC, LD);
   double *sG = pool;
   double *Y = pool;                      // written after the primitive loop, over the 2D integrals
-  double *geo = pool + C::SGY;
+  double *kq = pool + C::SGY;            // per-quartet exchange blocks (rows a|b, columns c|d), !KLDS only
+  double *geo = kq + (KLDS ? 0 : QB * C::KQ);
   int *qi = reinterpret_cast<int *>(geo + QB * 12);
   int *smax = qi + QB * 8;
   const Pair bra = A.pairs[bi];
@@ -431,8 +432,19 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
       const int ki = kl[valid ? k : k0];
       team_fill<LA, LB, LC, LD>(tid, bra, A.pairs[ki], bi, ki, valid, qi, geo);
     }
+    if constexpr (!KLDS)
+      for (int t = tid; t < QB * C::KQ; t += blockDim.x) kq[t] = 0.0;
     __syncthreads();
     team2_eri<LA, LB, LC, LD>(A.pp, sG, Y, qi, geo, smax);
+    // exchange: into the LDS rows of the bra (KLDS), else into the quartet's LDS block, which
+    // is flushed once per quartet below (one global atomic per element instead of one per
+    // contributing lane)
+    auto kadd = [&](int q, int r, int grow, int lc, int gcol, double v) {
+      if constexpr (KLDS)
+        k_update<true>(Krow, Km, nc, r, grow, gcol, v);
+      else
+        atomicAdd(&kq[q * C::KQ + r * (NC + ND) + lc], v);
+    };
     for (int t = tid; t < QB * NC * ND; t += blockDim.x) {
       const int q = t / (NC * ND), cd = t % (NC * ND);
       if (!qi[q * 8 + 6]) continue;
@@ -459,8 +471,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
           kc = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + dd], kc);
           kd = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + cc], kd);
         }
-        k_update<KLDS>(Krow, Km, nc, a, oa + a, cc, s * kc);
-        k_update<KLDS>(Krow, Km, nc, a, oa + a, dd, s * kd);
+        kadd(q, a, oa + a, c, cc, s * kc);
+        kadd(q, a, oa + a, NC + d, dd, s * kd);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
@@ -470,11 +482,23 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
           kc = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + dd], kc);
           kd = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + cc], kd);
         }
-        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, cc, s * kc);
-        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, dd, s * kd);
+        kadd(q, NA + b, ob + b, c, cc, s * kc);
+        kadd(q, NA + b, ob + b, NC + d, dd, s * kd);
       }
     }
     __syncthreads();
+    if constexpr (!KLDS) {
+      for (int t = tid; t < QB * C::KQ; t += blockDim.x) {
+        const int q = t / C::KQ, r = (t % C::KQ) / (NC + ND), lc = t % (NC + ND);
+        const double v = kq[t];
+        if (!qi[q * 8 + 6] || v == 0.0) continue;
+        const Pair &ket = A.pairs[qi[q * 8 + 1]];
+        const int row = r < NA ? oa + r : ob + (r - NA);
+        const int col = lc < NC ? ket.ca + lc : ket.cb + (lc - NC);
+        atomic_add(&Km[(size_t)row * nc + col], v);
+      }
+      __syncthreads();
+    }
   }
 }
 
