@@ -145,3 +145,20 @@ def test_cfg5_full_batch_sampled():
         dj, dk = maxabs(Js[big][sl_i, sl_j], Jb), maxabs(Ks[big][sl_i, sl_j], Kb)
         say(f"[cfg5] largest block ({si},{sj}) |dJ|={dj:.2e} |dK|={dk:.2e}")
         assert dj <= TOL and dk <= TOL
+
+
+def test_batch_of_degenerate_molecules():
+    # one-atom molecules (a single s function; an f and a p shell) next to a normal molecule:
+    # molecules are independent, so each must match its own oracle build
+    mols = [synth.custom([[0.0, 0.0, 0.0]], [(0, 1)], 1.0, 1.0, nocc=1, seed=31),
+            synth.make_config(2, natom=4),
+            synth.custom([[0.5, 0.5, 0.5]], [(3, 1), (1, 2)], 0.3, 2.0, pure_from_l=2, nocc=2, seed=32)]
+    for m in mols:
+        m.thresh = 1e-12
+    b, Js, Ks = _run_batch(mols)
+    b.close()
+    for i, m in enumerate(mols):
+        Jo, Ko = oracle.Oracle(m).jk(tau=m.thresh)
+        dj, dk = maxabs(Js[i], Jo), maxabs(Ks[i], Ko)
+        say(f"[batch degenerate] mol {i} nbf {m.nbf}: |dJ|={dj:.2e} |dK|={dk:.2e}")
+        assert dj <= TOL and dk <= TOL

@@ -119,3 +119,25 @@ def test_cfg3_full_size_sampled():
     # shells per atom: s s s s p p p d d f g -> 11 per atom
     _sampled(mol, [(0, 0), (11 * 7 + 4, 11 * 3 + 1), (11 * 20 + 7, 11 * 20 + 0), (11 * 31 + 9, 11 * 2 + 3)],
              "cfg3 full")
+
+
+def test_edge_all_pairs_screened_out():
+    # a threshold above every Schwarz factor: no pair survives, J = K = 0
+    mol = synth.make_config(2, natom=3)
+    (J, K), st = gpu_jk(mol, thresh=1e6)
+    say(f"[edge screened] stats {st}")
+    assert st["npairs_kept"] == 0 and st["kept_quartets"] == 0
+    assert not J.any() and not K.any()
+
+
+def test_edge_single_shell_molecule():
+    for l in (0, 2, 4):
+        mol = synth.custom([[0.3, -0.2, 0.1]], [(l, 2)], 0.4, 3.0, pure_from_l=2, nocc=1, seed=10 + l)
+        _check(mol, thresh=0.0, tag=f"one shell l={l}")
+
+
+def test_edge_long_contraction():
+    # K = 20 primitives on s and p shells (many primitive quartets per lane and per bin)
+    coords = [[0.0, 0.0, 0.0], [0.0, 1.4, 0.9]]
+    mol = synth.custom(coords, [(0, 20), (1, 20), (2, 1)], 0.05, 5000.0, pure_from_l=2, nocc=3, seed=21)
+    _check(mol, thresh=1e-12, tag="K=20")
