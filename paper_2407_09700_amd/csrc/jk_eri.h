@@ -60,20 +60,10 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 #pragma unroll
   for (int i = 0; i < NE * NF; ++i) acc[i] = (R)0;
 
-  // primitive quartets (ib, ik) in one flat loop; the pairs of the next quartet are loaded
-  // one iteration ahead so that their latency overlaps the current quartet's arithmetic
-  const int npk = ket.npp, ntot = bra.npp * ket.npp;
-  int ik = 0;
-  PrimPair pb = pp[bra.pp_off], pk = pp[ket.pp_off];
-  int nb_next = 1;                      // bra primitive the next bra load fetches
-  for (int it = 0; it < ntot; ++it) {
-    const bool new_bra = ik + 1 == npk;
-    PrimPair pkn = pk, pbn = pb;
-    if (it + 1 < ntot) {
-      pkn = pp[ket.pp_off + (new_bra ? 0 : ik + 1)];
-      if (new_bra) pbn = pp[bra.pp_off + nb_next];
-    }
-    {
+  for (int ib = 0; ib < bra.npp; ++ib) {
+    const PrimPair pb = pp[bra.pp_off + ib];
+    for (int ik = 0; ik < ket.npp; ++ik) {
+      const PrimPair pk = pp[ket.pp_off + ik];
       const double hp = 0.5 * pb.ip;
       PrimQuartet Q;
       prim_quartet(pb, pk, bra.A, ket.A, Q);
@@ -110,14 +100,6 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
           root(un, wn);
         }
       }
-    }
-    pk = pkn;
-    pb = pbn;
-    if (new_bra) {
-      ik = 0;
-      ++nb_next;
-    } else {
-      ++ik;
     }
   }
 
