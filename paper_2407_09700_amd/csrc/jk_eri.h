@@ -177,6 +177,44 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 }
 
 // ================================================================== workgroup per batch
+// Recurrence coefficients of the primitive quartets [w0, w0 + PW) of every quartet of a batch
+// and every root, computed once per window (primitive pairs, Rys root and weight):
+//   co[((q * PW + p) * N + n) * 10 + k], k = b00, b10, b01, z weight x prefactor,
+//   C00 (x, y, z), C00' (x, y, z).
+template <int N, int QB, int PW>
+__device__ __forceinline__ void prim_coefs(const PrimPair *__restrict__ pp, const int *qi, const double *geo, int w0,
+                                           double *co) {
+  for (int t = threadIdx.x; t < QB * PW * N; t += blockDim.x) {
+    const int q = t / (PW * N), p = (t / N) % PW, n = t % N;
+    const int pidx = w0 + p;
+    const int nk = qi[q * 8 + 5];
+    if (pidx >= qi[q * 8 + 3] * nk) continue;
+    const PrimPair pb = pp[qi[q * 8 + 2] + pidx / nk];
+    const PrimPair pk = pp[qi[q * 8 + 4] + pidx % nk];
+    PrimQuartet Q;
+    prim_quartet(pb, pk, &geo[q * 12], &geo[q * 12 + 6], Q);
+    double u, w;
+    rys_root1<N>(Q.T, n, u, w);
+    const double uq = u * Q.pq_inv;
+    double *c = co + (size_t)t * 10;
+    c[0] = 0.5 * uq;
+    c[1] = 0.5 * Q.ip * (1.0 - uq * Q.q);
+    c[2] = 0.5 * Q.iq * (1.0 - uq * Q.p);
+    c[3] = w * Q.pref;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      c[4 + d] = Q.PA[d] - uq * Q.q * Q.PQ[d];
+      c[7 + d] = Q.QC[d] + uq * Q.p * Q.PQ[d];
+    }
+  }
+}
+
+// primitive quartets per coefficient window: a multiple of the chunk pc within `bytes` of LDS
+constexpr int coef_window(int qb, int pc, int n, int bytes) {
+  const int m = bytes / (qb * pc * n * 80);
+  return pc * (m < 1 ? 1 : m);
+}
+
 // Number of e slices per f component in the f-major product: the count (each slice at most
 // emax accumulators) that keeps the largest share of a 256-lane block busy.
 // Candidates whose accumulators and per-root 2D values (2 registers per double, plus ~48
@@ -240,7 +278,9 @@ struct TeamCfg {
   // LDS carved by team_eri: 2D integrals, (buffer), geometry; descriptors are ints
   // per-quartet digestion accumulators: K[a,c], K[a,d], K[b,c], K[b,d] and J[c,d]
   static constexpr int DG = NA * NC + NA * ND + NB * NC + NB * ND + NC * ND;
-  static constexpr int LDS_DOUBLES = SG + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
+  static constexpr int PW = coef_window(QB, PC, N, 16 * 1024);     // coefficient window (primitive quartets)
+  static constexpr int CO = QB * PW * N * 10;
+  static constexpr int LDS_DOUBLES = SG + CO + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
@@ -296,8 +336,8 @@ __device__ __forceinline__ void team_product_dispatch(int part, const double *ba
 // (Z = buf) holds the contracted Cartesian blocks. Every thread of the block must call it;
 // it synchronises the block. sG: SG doubles of LDS; buf: BUF doubles (LDS or global).
 template <int LA, int LB, int LC, int LD>
-__device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ pp, double *sG, double *buf,
-                                                  const int *qi, const double *geo, int *smax) {
+__device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ pp, double *sG, double *co,
+                                                  double *buf, const int *qi, const double *geo, int *smax) {
   using C = TeamCfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
@@ -336,7 +376,12 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
 #pragma unroll
   for (int i = 0; i < C::EPS; ++i) acc[i] = 0.0;
 
-  for (int c0 = 0; c0 < kmax; c0 += PC) {
+  constexpr int PW = C::PW;
+  for (int w0 = 0; w0 < kmax; w0 += PW) {
+  prim_coefs<N, QB, PW>(pp, qi, geo, w0, co);
+  __syncthreads();
+  const int wend = min(w0 + PW, kmax);
+  for (int c0 = w0; c0 < wend; c0 += PC) {
     for (int t = tid; t < QB * PC * N * 3; t += BLOCK) {
       const int q = t / (PC * N * 3);
       const int rem = t % (PC * N * 3);
@@ -344,23 +389,10 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
       const int n = (rem % (N * 3)) / 3;
       const int dir = rem % 3;
       const int pidx = c0 + pl;
-      const int nk = qi[q * 8 + 5];
-      if (pidx < qi[q * 8 + 3] * nk) {
-        const PrimPair pb = pp[qi[q * 8 + 2] + pidx / nk];
-        const PrimPair pk = pp[qi[q * 8 + 4] + pidx % nk];
-        PrimQuartet Q;
-        prim_quartet(pb, pk, &geo[q * 12], &geo[q * 12 + 6], Q);
-        double u, w;
-        rys_root1<N>(Q.T, n, u, w);
-        const double uq = u * Q.pq_inv;
-        const double b00 = 0.5 * uq;
-        const double b10 = 0.5 * Q.ip * (1.0 - uq * Q.q);
-        const double b01 = 0.5 * Q.iq * (1.0 - uq * Q.p);
-        const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
-        const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
-        const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
+      if (pidx < qi[q * 8 + 3] * qi[q * 8 + 5]) {
+        const double *c = co + ((q * PW + (pidx - w0)) * N + n) * 10;
         double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
-        vrr2d_store<E, F>(dst, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
+        vrr2d_store<E, F>(dst, dir == 2 ? c[3] : 1.0, c[4 + dir], c[7 + dir], c[1], c[2], c[0]);
       }
     }
     __syncthreads();
@@ -388,6 +420,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
       }
     }
     __syncthreads();
+  }
   }
 
   if (prole) {
@@ -512,7 +545,9 @@ struct Team2Cfg {
   static constexpr int SG = QB * PC * N * GS;
   static constexpr int SGY = SG > QB * YS ? SG : QB * YS;       // the shared region
   static constexpr int KQ = (NA + NB) * (NC + ND);               // exchange block of one quartet
-  static constexpr int LDS_DOUBLES = SGY + QB * 12;              // + QB * KQ when K goes to global memory
+  static constexpr int PW = coef_window(QB, PC, N, 24 * 1024);   // coefficient window (primitive quartets)
+  static constexpr int CO = QB * PW * N * 10;
+  static constexpr int LDS_DOUBLES = SGY + CO + QB * 12;         // + QB * KQ when K goes to global memory
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
@@ -520,7 +555,7 @@ struct Team2Cfg {
 // Fills Y[q][ab][f] = (ab|f0) of the QB quartets described in qi/geo (same layout as team_eri).
 // Every thread of the block calls it; it synchronises the block. Returns Y.
 template <int LA, int LB, int LC, int LD>
-__device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ pp, double *sG, double *Y,
+__device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ pp, double *sG, double *co, double *Y,
                                                    const int *qi, const double *geo, int *smax) {
   using C = Team2Cfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
@@ -547,7 +582,12 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
   double acc[NE];
 #pragma unroll
   for (int i = 0; i < NE; ++i) acc[i] = 0.0;
-  for (int c0 = 0; c0 < kmax; c0 += PC) {
+  constexpr int PW = C::PW;
+  for (int w0 = 0; w0 < kmax; w0 += PW) {
+  prim_coefs<N, QB, PW>(pp, qi, geo, w0, co);
+  __syncthreads();
+  const int wend = min(w0 + PW, kmax);
+  for (int c0 = w0; c0 < wend; c0 += PC) {
     for (int t = tid; t < QB * PC * N * 3; t += blockDim.x) {
       const int q = t / (PC * N * 3);
       const int rem = t % (PC * N * 3);
@@ -555,23 +595,10 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
       const int n = (rem % (N * 3)) / 3;
       const int dir = rem % 3;
       const int pidx = c0 + pl;
-      const int nk = qi[q * 8 + 5];
-      if (pidx < qi[q * 8 + 3] * nk) {
-        const PrimPair pb = pp[qi[q * 8 + 2] + pidx / nk];
-        const PrimPair pk = pp[qi[q * 8 + 4] + pidx % nk];
-        PrimQuartet Q;
-        prim_quartet(pb, pk, &geo[q * 12], &geo[q * 12 + 6], Q);
-        double u, w;
-        rys_root1<N>(Q.T, n, u, w);
-        const double uq = u * Q.pq_inv;
-        const double b00 = 0.5 * uq;
-        const double b10 = 0.5 * Q.ip * (1.0 - uq * Q.q);
-        const double b01 = 0.5 * Q.iq * (1.0 - uq * Q.p);
-        const double pa = dir == 0 ? Q.PA[0] : (dir == 1 ? Q.PA[1] : Q.PA[2]);
-        const double qc = dir == 0 ? Q.QC[0] : (dir == 1 ? Q.QC[1] : Q.QC[2]);
-        const double pqd = dir == 0 ? Q.PQ[0] : (dir == 1 ? Q.PQ[1] : Q.PQ[2]);
+      if (pidx < qi[q * 8 + 3] * qi[q * 8 + 5]) {
+        const double *c = co + ((q * PW + (pidx - w0)) * N + n) * 10;
         double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
-        vrr2d_store<E, F>(dst, dir == 2 ? w * Q.pref : 1.0, pa - uq * Q.q * pqd, qc + uq * Q.p * pqd, b10, b01, b00);
+        vrr2d_store<E, F>(dst, dir == 2 ? c[3] : 1.0, c[4 + dir], c[7 + dir], c[1], c[2], c[0]);
       }
     }
     __syncthreads();
@@ -595,6 +622,7 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
       }
     }
     __syncthreads();
+  }
   }
   if (prole) {
     const double AB[3] = {geo[pq_ * 12 + 0] - geo[pq_ * 12 + 3], geo[pq_ * 12 + 1] - geo[pq_ * 12 + 4],

@@ -203,7 +203,8 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, QB = C::QB;
   constexpr int ck = pair_class(LC, LD);
   double *sG = pool;
-  double *lbuf = pool + C::SG;
+  double *co = pool + C::SG;                          // recurrence coefficients of a primitive window
+  double *lbuf = co + C::CO;
   double *dg = lbuf + (C::GLOBAL_BUF ? 0 : C::BUF);   // QB x DG digestion accumulators
   double *geo = dg + QB * C::DG;
   int *qi = reinterpret_cast<int *>(geo + QB * 12);
@@ -222,7 +223,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       team_fill<LA, LB, LC, LD>(tid, bra, A.pairs[ki], bi, ki, valid, qi, geo);
     }
     __syncthreads();
-    const double *Z = team_eri<LA, LB, LC, LD>(A.pp, sG, buf, qi, geo, smax);
+    const double *Z = team_eri<LA, LB, LC, LD>(A.pp, sG, co, buf, qi, geo, smax);
     constexpr int NCD = NC * ND, CH = (NCD + 63) / 64;
     if constexpr (NCD < TEAM_STREAM_MIN) {
       // Small ket blocks: one task per output element, its sum loaded in unrolled batches.
@@ -415,7 +416,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
   constexpr int ck = pair_class(LC, LD);
   double *sG = pool;
   double *Y = pool;                      // written after the primitive loop, over the 2D integrals
-  double *kq = pool + C::SGY;            // per-quartet exchange blocks (rows a|b, columns c|d), !KLDS only
+  double *co = pool + C::SGY;            // recurrence coefficients of a primitive window
+  double *kq = co + C::CO;               // per-quartet exchange blocks (rows a|b, columns c|d), !KLDS only
   double *geo = kq + (KLDS ? 0 : QB * C::KQ);
   int *qi = reinterpret_cast<int *>(geo + QB * 12);
   int *smax = qi + QB * 8;
@@ -435,7 +437,7 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
     if constexpr (!KLDS)
       for (int t = tid; t < QB * C::KQ; t += blockDim.x) kq[t] = 0.0;
     __syncthreads();
-    team2_eri<LA, LB, LC, LD>(A.pp, sG, Y, qi, geo, smax);
+    team2_eri<LA, LB, LC, LD>(A.pp, sG, co, Y, qi, geo, smax);
     // exchange: into the LDS rows of the bra (KLDS), else into the quartet's LDS block, which
     // is flushed once per quartet below (one global atomic per element instead of one per
     // contributing lane)
@@ -774,6 +776,7 @@ __global__ __launch_bounds__((mode_block<LA, LB, LC, LD>())) void k_mode(ModeArg
   if constexpr (use_team<LA, LB, LC, LD>()) {
     using C = TeamCfg<LA, LB, LC, LD>;
     __shared__ double sG[C::SG];
+    __shared__ double sCo[C::CO];
     __shared__ double sBuf[C::GLOBAL_BUF ? 1 : C::BUF];
     __shared__ double geo[C::QB * 12];
     __shared__ int qi[C::QB * 8];
@@ -788,7 +791,7 @@ __global__ __launch_bounds__((mode_block<LA, LB, LC, LD>())) void k_mode(ModeArg
         team_fill<LA, LB, LC, LD>(threadIdx.x, M.pairs[qd.x], M.pairs[qd.y], qd.x, qd.y, valid, qi, geo);
       }
       __syncthreads();
-      const double *Z = team_eri<LA, LB, LC, LD>(M.pp, sG, buf, qi, geo, &smax);
+      const double *Z = team_eri<LA, LB, LC, LD>(M.pp, sG, sCo, buf, qi, geo, &smax);
       if constexpr (MODE == MODE_SCHWARZ && LA == LC && LB == LD) {
         for (int t = threadIdx.x; t < C::QB * NA * NB; t += blockDim.x) {
           const int q = t / (NA * NB), ab = t % (NA * NB);
