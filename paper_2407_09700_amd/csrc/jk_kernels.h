@@ -107,7 +107,7 @@ __device__ __forceinline__ void k_update(double *Krow, double *Km, int nc, int r
 // mixed precision); the digestion always runs in double.
 template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double>
 __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
-                                              double (&jab)[ncart(LA) * ncart(LB)]) {
+                                              double (&jab)[ncart(LA) * ncart(LB)], int rot) {
   using C = SmallCfg<LA, LB, LC, LD>;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int ck = pair_class(LC, LD);
@@ -120,7 +120,9 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) Dab[a * NB + b] = Dm[(size_t)(bra.ca + a) * nc + bra.cb + b];
-  for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+  // ket k runs on lane (k + rot) mod blockDim: successive segments of a unit continue where the
+  // previous one ended, so the waves of the workgroup share the unit's kets evenly
+  for (int k = (int)((threadIdx.x + blockDim.x - rot) % blockDim.x); k < cnt; k += blockDim.x) {
     const int ki = kl[k];
     const Pair ket = A.pairs[ki];
     R g[C::NG];                 // FP32 integrals stay FP32 in registers; each use widens to double
@@ -523,13 +525,13 @@ constexpr int team_block() {
 // R = float selects the FP32 lane body; the team bodies always evaluate in double.
 template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double>
 __device__ __forceinline__ void jk_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow, double *jab_s,
-                                        double *pool, double (&jab)[ncart(LA) * ncart(LB)]) {
+                                        double *pool, double (&jab)[ncart(LA) * ncart(LB)], int rot = 0) {
   if constexpr (use_team2<LA, LB, LC, LD>())
     jk_team2_body<LA, LB, LC, LD, KLDS>(A, bi, kl, cnt, Krow, pool, jab);
   else if constexpr (use_team<LA, LB, LC, LD>())
     jk_team_body<LA, LB, LC, LD, KLDS>(A, bi, kl, cnt, Krow, jab_s, pool);
   else
-    jk_small_body<LA, LB, LC, LD, KLDS, R>(A, bi, kl, cnt, Krow, jab);
+    jk_small_body<LA, LB, LC, LD, KLDS, R>(A, bi, kl, cnt, Krow, jab, rot);
 }
 
 // adds the per-lane bra Coulomb partials into jab_s (LDS), one wave-reduced value per wave
@@ -546,15 +548,15 @@ __device__ __forceinline__ void jab_reduce(double (&jab)[NAB], double *jab_s) {
 
 template <int LA, int LB, int TIER, int P, typename R = double>
 __device__ __forceinline__ void ket_dispatch(int ck, const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
-                                             double *jab_s, double *pool, double (&jab)[ncart(LA) * ncart(LB)]) {
+                                             double *jab_s, double *pool, double (&jab)[ncart(LA) * ncart(LB)], int rot) {
   if constexpr (P <= pair_class(LA, LB)) {
     if constexpr (tier_of<LA, LB, pc_la(P), pc_lb(P)>() == TIER) {
       if (ck == P) {
-        jk_body<LA, LB, pc_la(P), pc_lb(P), true, R>(A, bi, kl, cnt, Krow, jab_s, pool, jab);
+        jk_body<LA, LB, pc_la(P), pc_lb(P), true, R>(A, bi, kl, cnt, Krow, jab_s, pool, jab, rot);
         return;
       }
     }
-    ket_dispatch<LA, LB, TIER, P + 1, R>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab);
+    ket_dispatch<LA, LB, TIER, P + 1, R>(ck, A, bi, kl, cnt, Krow, jab_s, pool, jab, rot);
   }
 }
 
@@ -648,14 +650,15 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
         const long long b0 = lo > pos ? lo : pos, b1 = hi < pos + n ? hi : pos + n;
         if (b1 > b0) {
           const int *kl = cls_kets + (part ? A.segoff32[sg] : A.segoff[sg]) + (b0 - pos);
+          const int rot = (int)((b0 - lo) % blockDim.x);
           if constexpr (F32)
-            ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
+            ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab, rot);
           else if constexpr (TIER == 2 || !JK_FP32_BODIES)   // team bodies evaluate the FP32 part in double
-            ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
+            ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab, rot);
           else if (part == 0)
-            ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
+            ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab, rot);
           else
-            ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab);
+            ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab, rot);
         }
         pos += n;
       }
