@@ -60,10 +60,12 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 #pragma unroll
   for (int i = 0; i < NE * NF; ++i) acc[i] = (R)0;
 
-  for (int ib = 0; ib < bra.npp; ++ib) {
-    const PrimPair pb = pp[bra.pp_off + ib];
-    for (int ik = 0; ik < ket.npp; ++ik) {
-      const PrimPair pk = pp[ket.pp_off + ik];
+  // ket primitives outside: their loads differ from lane to lane, the bra's are the same for
+  // every lane of the workgroup (one cache line per wave)
+  for (int ik = 0; ik < ket.npp; ++ik) {
+    const PrimPair pk = pp[ket.pp_off + ik];
+    for (int ib = 0; ib < bra.npp; ++ib) {
+      const PrimPair pb = pp[bra.pp_off + ib];
       const double hp = 0.5 * pb.ip;
       PrimQuartet Q;
       prim_quartet(pb, pk, bra.A, ket.A, Q);
