@@ -309,6 +309,11 @@ int ensure_scratch(jk_plan *p, long long doubles) {
   return JK_OK;
 }
 
+// A primitive pair whose Gaussian product factor exp(-ab/(a+b) |AB|^2) is below exp(-60)
+// (8.8e-27) is left out of its shell pair: its share of any integral lies some ten orders of
+// magnitude below the rounding of the FP64 result.
+constexpr double PRIM_EXP_CUT = 60.0;
+
 // Primitive pairs and pair records of every shell pair i >= j of one molecule (canonical
 // order l_a >= l_b inside the pair). s0: first shell of the molecule in the batch; shell
 // indices of the records are batch-wide, Cartesian offsets are inside the molecule.
@@ -330,13 +335,13 @@ void build_pairs(const jk_basis_t *B, const double *coords, const int *cart_off,
       P.sa = s0 + a; P.sb = s0 + b;
       P.ca = cart_off[a]; P.cb = cart_off[b];
       P.pp_off = (int)pps.size();
-      P.npp = B->nprim[a] * B->nprim[b];
       P.cls = pair_class(B->l[a], B->l[b]);
       P.mol = mol;
       for (int ka = 0; ka < B->nprim[a]; ++ka)
         for (int kb = 0; kb < B->nprim[b]; ++kb) {
           const double ea = B->exps[B->prim_off[a] + ka], eb = B->exps[B->prim_off[b] + kb];
           const double ca = B->coefs[B->prim_off[a] + ka], cb = B->coefs[B->prim_off[b] + kb];
+          if (ea * eb / (ea + eb) * ab2 > PRIM_EXP_CUT) continue;
           PrimPair q{};
           q.p = ea + eb;
           q.Px = (ea * A[0] + eb * Bc[0]) / q.p;
@@ -346,6 +351,7 @@ void build_pairs(const jk_basis_t *B, const double *coords, const int *cart_off,
           q.ip = 1.0 / q.p;
           pps.push_back(q);
         }
+      P.npp = (int)pps.size() - P.pp_off;
       pairs.push_back(P);
     }
 }
