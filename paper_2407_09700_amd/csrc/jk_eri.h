@@ -282,7 +282,12 @@ struct TeamCfg {
   static constexpr int DG = NA * NC + NA * ND + NB * NC + NB * ND + NC * ND;
   static constexpr int PW = coef_window(QB, PC, N, 16 * 1024);     // coefficient window (primitive quartets)
   static constexpr int CO = QB * PW * N * 10;
-  static constexpr int LDS_DOUBLES = SG + CO + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
+  // density blocks of the digestion: D[a,b], then per quartet D[c,d], D[a,c], D[a,d], D[b,c],
+  // D[b,d] and the symmetry factor; they reuse the region of the 2D integrals and coefficients
+  static constexpr int DQ = NC * ND + (NA + NB) * (NC + ND);
+  static constexpr int DSTG = NA * NB + QB * (DQ + 1);
+  static constexpr int SGC = SG + CO > DSTG ? SG + CO : DSTG;
+  static constexpr int LDS_DOUBLES = SGC + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };

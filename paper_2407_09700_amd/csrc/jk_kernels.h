@@ -206,7 +206,8 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   constexpr int ck = pair_class(LC, LD);
   double *sG = pool;
   double *co = pool + C::SG;                          // recurrence coefficients of a primitive window
-  double *lbuf = co + C::CO;
+  double *ds = pool;                                  // D blocks of the batch (after team_eri, same region)
+  double *lbuf = pool + C::SGC;
   double *dg = lbuf + (C::GLOBAL_BUF ? 0 : C::BUF);   // QB x DG digestion accumulators
   double *geo = dg + QB * C::DG;
   int *qi = reinterpret_cast<int *>(geo + QB * 12);
@@ -217,6 +218,9 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   const int nc = A.mnc[bra.mol];
   const double *Dm = A.Dc + A.mbase[bra.mol];
   double *Km = A.Kc + A.mbase[bra.mol];
+  const int oa = bra.ca, ob = bra.cb;
+  constexpr int NCD = NC * ND, CH = (NCD + 63) / 64, DQ = C::DQ;
+  constexpr int NAB = NA * NB, NG = NAB * NCD;
   for (int k0 = 0; k0 < cnt; k0 += QB) {
     if (tid < QB) {
       const int k = k0 + tid;
@@ -226,99 +230,123 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     }
     __syncthreads();
     const double *Z = team_eri<LA, LB, LC, LD>(A.pp, sG, co, buf, qi, geo, smax);
-    constexpr int NCD = NC * ND, CH = (NCD + 63) / 64;
+    // The density blocks the digestion reads, staged in LDS (independent loads, all in flight):
+    //   ds[0, NAB) = D[a,b]; per quartet q from ds + NAB + q DQ: D[c,d] | D[a,c] | D[a,d] |
+    //   D[b,c] | D[b,d]; then the symmetry factors s of the QB quartets.
+    for (int t = tid; t < NAB + QB * (DQ + 1); t += blockDim.x) {
+      if (t < NAB) {
+        ds[t] = Dm[(size_t)(oa + t / NB) * nc + ob + t % NB];
+        continue;
+      }
+      int u = t - NAB;
+      if (u >= QB * DQ) {                      // symmetry factor of quartet u - QB DQ
+        const int q = u - QB * DQ;
+        if (qi[q * 8 + 6]) ds[t] = sym_factor(bra, A.pairs[qi[q * 8 + 1]], bi, qi[q * 8 + 1]);
+        continue;
+      }
+      const int q = u / DQ;
+      u %= DQ;
+      if (!qi[q * 8 + 6]) continue;
+      const Pair &ket = A.pairs[qi[q * 8 + 1]];
+      const int oc = ket.ca, od = ket.cb;
+      int r, c;
+      if (u < NCD) {
+        r = oc + u / ND; c = od + u % ND;
+      } else if ((u -= NCD) < NA * NC) {
+        r = oa + u / NC; c = oc + u % NC;
+      } else if ((u -= NA * NC) < NA * ND) {
+        r = oa + u / ND; c = od + u % ND;
+      } else if ((u -= NA * ND) < NB * NC) {
+        r = ob + u / NC; c = oc + u % NC;
+      } else {
+        u -= NB * NC;
+        r = ob + u / ND; c = od + u % ND;
+      }
+      ds[t] = Dm[(size_t)r * nc + c];
+    }
+    for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
+    __syncthreads();
+    const double *dab_s = ds, *sq = ds + NAB + QB * DQ;
     if constexpr (NCD < TEAM_STREAM_MIN) {
-      // Small ket blocks: one task per output element, its sum loaded in unrolled batches.
-      constexpr int T1 = NA * NB, T2 = NC * ND, T3 = NA * NC, T4 = NA * ND, T5 = NB * NC;
-      constexpr int TOT = T1 + T2 + T3 + T4 + T5 + NB * ND;
-      for (int t = tid; t < QB * TOT; t += blockDim.x) {
-        const int q = t / TOT;
-        int r = t % TOT;
+      // Small ket blocks: one task per output element, one loop per kind of output (no
+      // divergence between kinds), integrals and densities read from LDS (or the buffer).
+      for (int t = tid; t < QB * NAB; t += blockDim.x) {          // J[a,b] += 2s sum_cd g D[c,d]
+        const int q = t / NAB, r = t % NAB;
         if (!qi[q * 8 + 6]) continue;
-        const int ki = qi[q * 8 + 1];
-        const Pair &ket = A.pairs[ki];
-        const double s = sym_factor(bra, ket, bi, ki);
-        const int oa = bra.ca, ob = bra.cb, oc = ket.ca, od = ket.cb;
-        const double *g = Z + (size_t)q * NA * NB * NC * ND;
+        const double *gr = Z + (size_t)q * NG + r * NCD, *dcd = ds + NAB + q * DQ;
         double v = 0.0;
-        // the sums below are unrolled so that their loads (g and D) are in flight together
-        if (r < T1) {                       // J[a,b] += 2s sum_cd g D[c,d]
-          const int a = r / NB, b = r % NB;
-          const double *gr = g + (a * NB + b) * NC * ND;
+#pragma unroll
+        for (int i = 0; i < NCD; ++i) v = fma(gr[i], dcd[i], v);
+        atomicAdd(&jab_s[r], 2.0 * sq[q] * v);
+      }
+      for (int t = tid; t < QB * NCD; t += blockDim.x) {          // J[c,d] += 2s sum_ab g D[a,b]
+        const int q = t / NCD, r = t % NCD;
+        if (!qi[q * 8 + 6]) continue;
+        const double *g = Z + (size_t)q * NG + r;
+        double v = 0.0;
 #pragma unroll 16
-          for (int i = 0; i < NC * ND; ++i) v = fma(gr[i], Dm[(size_t)(oc + i / ND) * nc + od + i % ND], v);
-          atomicAdd(&jab_s[r], 2.0 * s * v);
-          continue;
-        }
-        r -= T1;
-        if (r < T2) {                       // J[c,d] += 2s sum_ab g D[a,b]
-          const int c = r / ND, d = r % ND;
+        for (int i = 0; i < NAB; ++i) v = fma(g[i * NCD], dab_s[i], v);
+        atomic_add(jp_elem(A, ck, qi[q * 8 + 1], r), 2.0 * sq[q] * v);
+      }
+      for (int t = tid; t < QB * NA * NC; t += blockDim.x) {      // K[a,c] += s sum_bd g D[b,d]
+        const int q = t / (NA * NC), a = (t / NC) % NA, c = t % NC;
+        if (!qi[q * 8 + 6]) continue;
+        const double *g = Z + (size_t)q * NG + a * NB * NCD + c * ND;
+        const double *dbd = ds + NAB + q * DQ + NCD + NA * NC + NA * ND + NB * NC;
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < NB * ND; ++i) v = fma(g[(i / ND) * NCD + i % ND], dbd[i], v);
+        const int oc = A.pairs[qi[q * 8 + 1]].ca;
+        k_update<KLDS>(Krow, Km, nc, a, oa + a, oc + c, sq[q] * v);
+      }
+      for (int t = tid; t < QB * NA * ND; t += blockDim.x) {      // K[a,d] += s sum_bc g D[b,c]
+        const int q = t / (NA * ND), a = (t / ND) % NA, d = t % ND;
+        if (!qi[q * 8 + 6]) continue;
+        const double *g = Z + (size_t)q * NG + a * NB * NCD + d;
+        const double *dbc = ds + NAB + q * DQ + NCD + NA * NC + NA * ND;
+        double v = 0.0;
 #pragma unroll 16
-          for (int i = 0; i < NA * NB; ++i)
-            v = fma(g[i * NC * ND + c * ND + d], Dm[(size_t)(oa + i / NB) * nc + ob + i % NB], v);
-          atomic_add(jp_elem(A, ck, ki, r), 2.0 * s * v);
-          continue;
-        }
-        r -= T2;
-        if (r < T3) {                       // K[a,c] += s sum_bd g D[b,d]
-          const int a = r / NC, c = r % NC;
+        for (int i = 0; i < NB * NC; ++i) v = fma(g[(i / NC) * NCD + (i % NC) * ND], dbc[i], v);
+        const int od = A.pairs[qi[q * 8 + 1]].cb;
+        k_update<KLDS>(Krow, Km, nc, a, oa + a, od + d, sq[q] * v);
+      }
+      for (int t = tid; t < QB * NB * NC; t += blockDim.x) {      // K[b,c] += s sum_ad g D[a,d]
+        const int q = t / (NB * NC), b = (t / NC) % NB, c = t % NC;
+        if (!qi[q * 8 + 6]) continue;
+        const double *g = Z + (size_t)q * NG + b * NCD + c * ND;
+        const double *dad = ds + NAB + q * DQ + NCD + NA * NC;
+        double v = 0.0;
 #pragma unroll 16
-          for (int i = 0; i < NB * ND; ++i) {
-            const int b = i / ND, d = i % ND;
-            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + od + d], v);
-          }
-          k_update<KLDS>(Krow, Km, nc, a, oa + a, oc + c, s * v);
-          continue;
-        }
-        r -= T3;
-        if (r < T4) {                       // K[a,d] += s sum_bc g D[b,c]
-          const int a = r / ND, d = r % ND;
+        for (int i = 0; i < NA * ND; ++i) v = fma(g[(i / ND) * NB * NCD + i % ND], dad[i], v);
+        const int oc = A.pairs[qi[q * 8 + 1]].ca;
+        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, oc + c, sq[q] * v);
+      }
+      for (int t = tid; t < QB * NB * ND; t += blockDim.x) {      // K[b,d] += s sum_ac g D[a,c]
+        const int q = t / (NB * ND), b = (t / ND) % NB, d = t % ND;
+        if (!qi[q * 8 + 6]) continue;
+        const double *g = Z + (size_t)q * NG + b * NCD + d;
+        const double *dac = ds + NAB + q * DQ + NCD;
+        double v = 0.0;
 #pragma unroll 16
-          for (int i = 0; i < NB * NC; ++i) {
-            const int b = i / NC, c = i % NC;
-            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(ob + b) * nc + oc + c], v);
-          }
-          k_update<KLDS>(Krow, Km, nc, a, oa + a, od + d, s * v);
-          continue;
-        }
-        r -= T4;
-        if (r < T5) {                       // K[b,c] += s sum_ad g D[a,d]
-          const int b = r / NC, c = r % NC;
-#pragma unroll 16
-          for (int i = 0; i < NA * ND; ++i) {
-            const int a = i / ND, d = i % ND;
-            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + od + d], v);
-          }
-          k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, oc + c, s * v);
-          continue;
-        }
-        r -= T5;
-        {                                   // K[b,d] += s sum_ac g D[a,c]
-          const int b = r / ND, d = r % ND;
-#pragma unroll 16
-          for (int i = 0; i < NA * NC; ++i) {
-            const int a = i / NC, c = i % NC;
-            v = fma(g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(oa + a) * nc + oc + c], v);
-          }
-          k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, od + d, s * v);
-        }
+        for (int i = 0; i < NA * NC; ++i) v = fma(g[(i / NC) * NB * NCD + (i % NC) * ND], dac[i], v);
+        const int od = A.pairs[qi[q * 8 + 1]].cb;
+        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, od + d, sq[q] * v);
       }
       __syncthreads();
       continue;
     }
-    // Digestion, every integral read once: each wave streams rows (a, b) of the block, its
-    // lanes run over (c, d). J[a,b] is wave-reduced per row; J[c,d], K[a,c] and K[a,d] collect
-    // in registers; K[b,c] and K[b,d] in LDS. The per-quartet sums are flushed below.
-    for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
-    __syncthreads();
+    // Digestion, every integral read once: each wave streams rows (a, b) of the block (RB rows
+    // loaded together), its lanes run over (c, d). J[a,b] is wave-reduced per row; J[c,d],
+    // K[a,c] and K[a,d] collect in registers; K[b,c] and K[b,d] in LDS. The per-quartet sums
+    // are flushed below.
     const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    constexpr int RB = 4;
     for (int q = 0; q < QB; ++q) {
       if (!qi[q * 8 + 6]) continue;
-      const int ki = qi[q * 8 + 1];
-      const Pair &ket = A.pairs[ki];
-      const double s2 = 2.0 * sym_factor(bra, ket, bi, ki);
-      const int oa = bra.ca, ob = bra.cb, oc = ket.ca, od = ket.cb;
-      const double *g = Z + (size_t)q * NA * NB * NCD;
+      const double s2 = 2.0 * sq[q];
+      const double *g = Z + (size_t)q * NG;
+      const double *Dcd = ds + NAB + q * DQ, *Dac = Dcd + NCD, *Dad = Dac + NA * NC, *Dbc = Dad + NA * ND,
+                   *Dbd = Dbc + NB * NC;
       double *kac = dg + q * C::DG, *kad = kac + NA * NC, *kbc = kad + NA * ND, *kbd = kbc + NB * NC;
       double *jcd = kbd + NB * ND;
       int cc[CH], dd[CH];
@@ -330,36 +358,47 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         on[h] = cd < NCD;
         cc[h] = on[h] ? cd / ND : 0;
         dd[h] = on[h] ? cd % ND : 0;
-        dcd[h] = on[h] ? Dm[(size_t)(oc + cc[h]) * nc + od + dd[h]] : 0.0;
+        dcd[h] = on[h] ? Dcd[cd] : 0.0;
         jcda[h] = 0.0;
       }
       for (int a = wave; a < NA; a += nwave) {
         double dad[CH], dac[CH], kacs[CH], kads[CH];
 #pragma unroll
         for (int h = 0; h < CH; ++h) {
-          dad[h] = on[h] ? Dm[(size_t)(oa + a) * nc + od + dd[h]] : 0.0;
-          dac[h] = on[h] ? Dm[(size_t)(oa + a) * nc + oc + cc[h]] : 0.0;
+          dad[h] = Dad[a * ND + dd[h]];
+          dac[h] = Dac[a * NC + cc[h]];
           kacs[h] = 0.0;
           kads[h] = 0.0;
         }
-        for (int b = 0; b < NB; ++b) {
-          const int row = a * NB + b;
-          const double dab = Dm[(size_t)(oa + a) * nc + ob + b];
-          double vab = 0.0;
 #pragma unroll
-          for (int h = 0; h < CH; ++h) {
-            if (!on[h]) continue;
-            const double x = g[(size_t)row * NCD + h * 64 + lane];
-            vab = fma(x, dcd[h], vab);
-            jcda[h] = fma(x, dab, jcda[h]);
-            kacs[h] = fma(x, Dm[(size_t)(ob + b) * nc + od + dd[h]], kacs[h]);
-            kads[h] = fma(x, Dm[(size_t)(ob + b) * nc + oc + cc[h]], kads[h]);
-            atomicAdd(&kbc[b * NC + cc[h]], x * dad[h]);
-            atomicAdd(&kbd[b * ND + dd[h]], x * dac[h]);
+        for (int b0 = 0; b0 < NB; b0 += RB) {
+          double xs[RB][CH];
+#pragma unroll
+          for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int h = 0; h < CH; ++h)
+              xs[i][h] = (b0 + i < NB && on[h]) ? g[(size_t)(a * NB + b0 + i) * NCD + h * 64 + lane] : 0.0;
+#pragma unroll
+          for (int i = 0; i < RB; ++i) {
+            const int b = b0 + i;
+            if (b >= NB) break;
+            const double dab = dab_s[a * NB + b];
+            double vab = 0.0;
+#pragma unroll
+            for (int h = 0; h < CH; ++h) {
+              if (!on[h]) continue;
+              const double x = xs[i][h];
+              vab = fma(x, dcd[h], vab);
+              jcda[h] = fma(x, dab, jcda[h]);
+              kacs[h] = fma(x, Dbd[b * ND + dd[h]], kacs[h]);
+              kads[h] = fma(x, Dbc[b * NC + cc[h]], kads[h]);
+              atomicAdd(&kbc[b * NC + cc[h]], x * dad[h]);
+              atomicAdd(&kbd[b * ND + dd[h]], x * dac[h]);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) vab += __shfl_xor(vab, o);
+            if (lane == 0 && vab != 0.0) atomicAdd(&jab_s[a * NB + b], s2 * vab);
           }
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) vab += __shfl_xor(vab, o);
-          if (lane == 0 && vab != 0.0) atomicAdd(&jab_s[row], s2 * vab);
         }
 #pragma unroll
         for (int h = 0; h < CH; ++h)
@@ -380,8 +419,8 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       if (!qi[q * 8 + 6] || v == 0.0) continue;
       const int ki = qi[q * 8 + 1];
       const Pair &ket = A.pairs[ki];
-      const double s = sym_factor(bra, ket, bi, ki);
-      const int oa = bra.ca, ob = bra.cb, oc = ket.ca, od = ket.cb;
+      const double s = sq[q];
+      const int oc = ket.ca, od = ket.cb;
       if (r < NA * NC) {                                // K[a,c] += s sum_bd g D[b,d]
         k_update<KLDS>(Krow, Km, nc, r / NC, oa + r / NC, oc + r % NC, s * v);
         continue;
