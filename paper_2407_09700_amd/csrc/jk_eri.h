@@ -445,76 +445,108 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   __syncthreads();
   // Bra transfer, one task per (quartet, a, f): the X[e][f] this a can reach (e = a + k,
   // |k| <= lb) are loaded together, then the NB outputs (a, b) are formed from registers.
+  // Each lane runs TU tasks at once, their loads issued before any of them is used (the
+  // buffer may be in global memory).
   constexpr int NKB = range_count(0, LB);       // components k with |k| <= lb
-  for (int t = tid; t < QB * NA * NF; t += BLOCK) {
-    const int q = t / (NA * NF);
-    const int rem = t % (NA * NF);
-    const int a = rem / NF, f = rem % NF;
-    const int ax = CTD.x[E0 + a], ay = CTD.y[E0 + a], az = CTD.z[E0 + a];
-    const double AB[3] = {geo[q * 12 + 0] - geo[q * 12 + 3], geo[q * 12 + 1] - geo[q * 12 + 4],
-                          geo[q * 12 + 2] - geo[q * 12 + 5]};
-    double xv[NKB];
+  constexpr int TUB = 3 * NKB <= 24 ? 3 : (2 * NKB <= 24 ? 2 : 1);
+  for (int t0 = tid; t0 < QB * NA * NF; t0 += TUB * BLOCK) {
+    double xv[TUB][NKB];
 #pragma unroll
-    for (int k = 0; k < NKB; ++k) xv[k] = X[(q * NE + cart_flat(ax + CT.x[k], ay + CT.y[k], az + CT.z[k]) - E0) * NF + f];
-    double pw[3][LB + 1];
+    for (int u = 0; u < TUB; ++u) {
+      const int t = t0 + u * BLOCK;
+      if (t >= QB * NA * NF) break;
+      const int q = t / (NA * NF);
+      const int rem = t % (NA * NF);
+      const int a = rem / NF, f = rem % NF;
+      const int ax = CTD.x[E0 + a], ay = CTD.y[E0 + a], az = CTD.z[E0 + a];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      pw[d][0] = 1.0;
-#pragma unroll
-      for (int i = 1; i <= LB; ++i) pw[d][i] = pw[d][i - 1] * AB[d];
+      for (int k = 0; k < NKB; ++k)
+        xv[u][k] = X[(q * NE + cart_flat(ax + CT.x[k], ay + CT.y[k], az + CT.z[k]) - E0) * NF + f];
     }
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      constexpr int B0 = CT.start[LB];
-      const int bx = CT.x[B0 + b], by = CT.y[B0 + b], bz = CT.z[B0 + b];
-      double v = 0.0;
+    for (int u = 0; u < TUB; ++u) {
+      const int t = t0 + u * BLOCK;
+      if (t >= QB * NA * NF) break;
+      const int q = t / (NA * NF);
+      const int rem = t % (NA * NF);
+      const int a = rem / NF, f = rem % NF;
+      const double AB[3] = {geo[q * 12 + 0] - geo[q * 12 + 3], geo[q * 12 + 1] - geo[q * 12 + 4],
+                            geo[q * 12 + 2] - geo[q * 12 + 5]};
+      double pw[3][LB + 1];
 #pragma unroll
-      for (int k = 0; k < NKB; ++k) {
-        const int kx = CT.x[k], ky = CT.y[k], kz = CT.z[k];
-        if (kx > bx || ky > by || kz > bz) continue;
-        const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * pw[0][bx - kx] * pw[1][by - ky] *
-                          pw[2][bz - kz];
-        v = fma(cf, xv[k], v);
+      for (int d = 0; d < 3; ++d) {
+        pw[d][0] = 1.0;
+#pragma unroll
+        for (int i = 1; i <= LB; ++i) pw[d][i] = pw[d][i - 1] * AB[d];
       }
-      Y[(q * NA * NB + a * NB + b) * NF + f] = v;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        constexpr int B0 = CT.start[LB];
+        const int bx = CT.x[B0 + b], by = CT.y[B0 + b], bz = CT.z[B0 + b];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NKB; ++k) {
+          const int kx = CT.x[k], ky = CT.y[k], kz = CT.z[k];
+          if (kx > bx || ky > by || kz > bz) continue;
+          const double cf = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * pw[0][bx - kx] *
+                            pw[1][by - ky] * pw[2][bz - kz];
+          v = fma(cf, xv[u][k], v);
+        }
+        Y[(q * NA * NB + a * NB + b) * NF + f] = v;
+      }
     }
   }
   __syncthreads();
   // Ket transfer, one task per (quartet, ab, c): Y[ab][c + k] for |k| <= ld loaded together,
-  // then the ND outputs (c, d).
+  // then the ND outputs (c, d); TU tasks per lane at once as above.
   constexpr int NKD = range_count(0, LD);
+  constexpr int TUK = 3 * NKD <= 24 ? 3 : (2 * NKD <= 24 ? 2 : 1);
   double *Z = X;
-  for (int t = tid; t < QB * NA * NB * NC; t += BLOCK) {
-    const int q = t / (NA * NB * NC);
-    const int rem = t % (NA * NB * NC);
-    const int ab = rem / NC, c = rem % NC;
-    const int cx = CTD.x[F0 + c], cy = CTD.y[F0 + c], cz = CTD.z[F0 + c];
-    const double CD[3] = {geo[q * 12 + 6] - geo[q * 12 + 9], geo[q * 12 + 7] - geo[q * 12 + 10],
-                          geo[q * 12 + 8] - geo[q * 12 + 11]};
-    double yv[NKD];
+  for (int t0 = tid; t0 < QB * NA * NB * NC; t0 += TUK * BLOCK) {
+    double yv[TUK][NKD];
 #pragma unroll
-    for (int k = 0; k < NKD; ++k) yv[k] = Y[(q * NA * NB + ab) * NF + cart_flat(cx + CT.x[k], cy + CT.y[k], cz + CT.z[k]) - F0];
-    double pw[3][LD + 1];
+    for (int u = 0; u < TUK; ++u) {
+      const int t = t0 + u * BLOCK;
+      if (t >= QB * NA * NB * NC) break;
+      const int q = t / (NA * NB * NC);
+      const int rem = t % (NA * NB * NC);
+      const int ab = rem / NC, c = rem % NC;
+      const int cx = CTD.x[F0 + c], cy = CTD.y[F0 + c], cz = CTD.z[F0 + c];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      pw[d][0] = 1.0;
-#pragma unroll
-      for (int i = 1; i <= LD; ++i) pw[d][i] = pw[d][i - 1] * CD[d];
+      for (int k = 0; k < NKD; ++k)
+        yv[u][k] = Y[(q * NA * NB + ab) * NF + cart_flat(cx + CT.x[k], cy + CT.y[k], cz + CT.z[k]) - F0];
     }
 #pragma unroll
-    for (int dd = 0; dd < ND; ++dd) {
-      constexpr int D0 = CT.start[LD];
-      const int dx = CT.x[D0 + dd], dy = CT.y[D0 + dd], dz = CT.z[D0 + dd];
-      double v = 0.0;
+    for (int u = 0; u < TUK; ++u) {
+      const int t = t0 + u * BLOCK;
+      if (t >= QB * NA * NB * NC) break;
+      const int q = t / (NA * NB * NC);
+      const int rem = t % (NA * NB * NC);
+      const int ab = rem / NC, c = rem % NC;
+      const double CD[3] = {geo[q * 12 + 6] - geo[q * 12 + 9], geo[q * 12 + 7] - geo[q * 12 + 10],
+                            geo[q * 12 + 8] - geo[q * 12 + 11]};
+      double pw[3][LD + 1];
 #pragma unroll
-      for (int k = 0; k < NKD; ++k) {
-        const int kx = CT.x[k], ky = CT.y[k], kz = CT.z[k];
-        if (kx > dx || ky > dy || kz > dz) continue;
-        const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * pw[0][dx - kx] * pw[1][dy - ky] *
-                          pw[2][dz - kz];
-        v = fma(cf, yv[k], v);
+      for (int d = 0; d < 3; ++d) {
+        pw[d][0] = 1.0;
+#pragma unroll
+        for (int i = 1; i <= LD; ++i) pw[d][i] = pw[d][i - 1] * CD[d];
       }
-      Z[(q * NA * NB + ab) * NC * ND + c * ND + dd] = v;   // region 1 is free: X was consumed by the pass above
+#pragma unroll
+      for (int dd = 0; dd < ND; ++dd) {
+        constexpr int D0 = CT.start[LD];
+        const int dx = CT.x[D0 + dd], dy = CT.y[D0 + dd], dz = CT.z[D0 + dd];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NKD; ++k) {
+          const int kx = CT.x[k], ky = CT.y[k], kz = CT.z[k];
+          if (kx > dx || ky > dy || kz > dz) continue;
+          const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * pw[0][dx - kx] *
+                            pw[1][dy - ky] * pw[2][dz - kz];
+          v = fma(cf, yv[u][k], v);
+        }
+        Z[(q * NA * NB + ab) * NC * ND + c * ND + dd] = v;   // region 1 is free: X was consumed by the pass above
+      }
     }
   }
   __syncthreads();

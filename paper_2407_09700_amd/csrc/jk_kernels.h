@@ -194,6 +194,53 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
   }
 }
 
+// ------------------------------------------------------------------ density blocks of a batch
+// The density blocks a batch's digestion reads, staged in LDS (independent loads, all in flight):
+//   ds[0, NA NB) = D[a,b]; per quartet q from ds + NA NB + q DQ: D[c,d] | D[a,c] | D[a,d] |
+//   D[b,c] | D[b,d]; then the symmetry factors s of the QB quartets.
+template <int NA, int NB, int NC, int ND>
+constexpr int stage_dq() { return NC * ND + (NA + NB) * (NC + ND); }
+template <int NA, int NB, int NC, int ND>
+constexpr int stage_doubles(int qb) { return NA * NB + qb * (stage_dq<NA, NB, NC, ND>() + 1); }
+
+template <int NA, int NB, int NC, int ND, int QB>
+__device__ __forceinline__ void stage_density(const JKArgs &A, const Pair &bra, int bi, const double *Dm, int nc,
+                                              const int *qi, double *ds) {
+  constexpr int NAB = NA * NB, NCD = NC * ND, DQ = stage_dq<NA, NB, NC, ND>();
+  const int oa = bra.ca, ob = bra.cb;
+  for (int t = threadIdx.x; t < NAB + QB * (DQ + 1); t += blockDim.x) {
+    if (t < NAB) {
+      ds[t] = Dm[(size_t)(oa + t / NB) * nc + ob + t % NB];
+      continue;
+    }
+    int u = t - NAB;
+    if (u >= QB * DQ) {                      // symmetry factor of quartet u - QB DQ
+      const int q = u - QB * DQ;
+      if (qi[q * 8 + 6]) ds[t] = sym_factor(bra, A.pairs[qi[q * 8 + 1]], bi, qi[q * 8 + 1]);
+      continue;
+    }
+    const int q = u / DQ;
+    u %= DQ;
+    if (!qi[q * 8 + 6]) continue;
+    const Pair &ket = A.pairs[qi[q * 8 + 1]];
+    const int oc = ket.ca, od = ket.cb;
+    int r, c;
+    if (u < NCD) {
+      r = oc + u / ND; c = od + u % ND;
+    } else if ((u -= NCD) < NA * NC) {
+      r = oa + u / NC; c = oc + u % NC;
+    } else if ((u -= NA * NC) < NA * ND) {
+      r = oa + u / ND; c = od + u % ND;
+    } else if ((u -= NA * ND) < NB * NC) {
+      r = ob + u / NC; c = oc + u % NC;
+    } else {
+      u -= NB * NC;
+      r = ob + u / ND; c = od + u % ND;
+    }
+    ds[t] = Dm[(size_t)r * nc + c];
+  }
+}
+
 // ------------------------------------------------------------------ workgroup body
 // pool: TeamCfg::LDS_BYTES of LDS; jab_s: NA*NB doubles of LDS (bra Coulomb block).
 // Ket blocks of at least this many components use the streaming digestion.
@@ -230,40 +277,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     }
     __syncthreads();
     const double *Z = team_eri<LA, LB, LC, LD>(A.pp, sG, co, buf, qi, geo, smax);
-    // The density blocks the digestion reads, staged in LDS (independent loads, all in flight):
-    //   ds[0, NAB) = D[a,b]; per quartet q from ds + NAB + q DQ: D[c,d] | D[a,c] | D[a,d] |
-    //   D[b,c] | D[b,d]; then the symmetry factors s of the QB quartets.
-    for (int t = tid; t < NAB + QB * (DQ + 1); t += blockDim.x) {
-      if (t < NAB) {
-        ds[t] = Dm[(size_t)(oa + t / NB) * nc + ob + t % NB];
-        continue;
-      }
-      int u = t - NAB;
-      if (u >= QB * DQ) {                      // symmetry factor of quartet u - QB DQ
-        const int q = u - QB * DQ;
-        if (qi[q * 8 + 6]) ds[t] = sym_factor(bra, A.pairs[qi[q * 8 + 1]], bi, qi[q * 8 + 1]);
-        continue;
-      }
-      const int q = u / DQ;
-      u %= DQ;
-      if (!qi[q * 8 + 6]) continue;
-      const Pair &ket = A.pairs[qi[q * 8 + 1]];
-      const int oc = ket.ca, od = ket.cb;
-      int r, c;
-      if (u < NCD) {
-        r = oc + u / ND; c = od + u % ND;
-      } else if ((u -= NCD) < NA * NC) {
-        r = oa + u / NC; c = oc + u % NC;
-      } else if ((u -= NA * NC) < NA * ND) {
-        r = oa + u / ND; c = od + u % ND;
-      } else if ((u -= NA * ND) < NB * NC) {
-        r = ob + u / NC; c = oc + u % NC;
-      } else {
-        u -= NB * NC;
-        r = ob + u / ND; c = od + u % ND;
-      }
-      ds[t] = Dm[(size_t)r * nc + c];
-    }
+    stage_density<NA, NB, NC, ND, QB>(A, bra, bi, Dm, nc, qi, ds);
     for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
     __syncthreads();
     const double *dab_s = ds, *sq = ds + NAB + QB * DQ;
@@ -336,11 +350,11 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       continue;
     }
     // Digestion, every integral read once: each wave streams rows (a, b) of the block (RB rows
-    // loaded together), its lanes run over (c, d). J[a,b] is wave-reduced per row; J[c,d],
+    // loaded together: all NB rows of an a when they fit), its lanes run over (c, d). J[a,b] is wave-reduced per row; J[c,d],
     // K[a,c] and K[a,d] collect in registers; K[b,c] and K[b,d] in LDS. The per-quartet sums
     // are flushed below.
     const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    constexpr int RB = 4;
+    constexpr int RB = NB * CH <= 32 ? NB : 4;
     for (int q = 0; q < QB; ++q) {
       if (!qi[q * 8 + 6]) continue;
       const double s2 = 2.0 * sq[q];
