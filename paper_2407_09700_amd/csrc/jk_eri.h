@@ -37,6 +37,9 @@
 
 namespace jk {
 
+// Ket blocks of at least this many components use the streamed digestion in the workgroup body.
+constexpr int TEAM_STREAM_MIN = 24;
+
 // ================================================================== lane per quartet
 template <int LA, int LB, int LC, int LD>
 struct SmallCfg {
@@ -286,7 +289,10 @@ struct TeamCfg {
   // D[b,d] and the symmetry factor; they reuse the region of the 2D integrals and coefficients
   static constexpr int DQ = NC * ND + (NA + NB) * (NC + ND);
   static constexpr int DSTG = NA * NB + QB * (DQ + 1);
-  static constexpr int SGC = SG + CO > DSTG ? SG + CO : DSTG;
+  // streamed digestion (ket blocks of TEAM_STREAM_MIN or more components): partial K[b,c] and
+  // K[b,d] per (b, cd) after the density blocks
+  static constexpr int PBD = NC * ND >= TEAM_STREAM_MIN ? 2 * QB * NB * NC * ND : 0;
+  static constexpr int SGC = SG + CO > DSTG + PBD ? SG + CO : DSTG + PBD;
   static constexpr int LDS_DOUBLES = SGC + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;

@@ -241,10 +241,26 @@ __device__ __forceinline__ void stage_density(const JKArgs &A, const Pair &bra, 
   }
 }
 
+// Row sums of eight rows over the 64 lanes of a wave (p[r]: this lane's share of row r). Three
+// exchange steps halve the rows each lane carries (lane bit 2, 1, 0 picks the half it keeps),
+// three more add the eight lane groups: lane l returns the full sum of row l & 7. Ten shuffles
+// for eight rows instead of six per row.
+__device__ __forceinline__ double rows8_sum(const double (&p)[8], int lane) {
+  const bool b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+  double q4[4], q2[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) q4[j] = (b2 ? p[j + 4] : p[j]) + __shfl_xor(b2 ? p[j] : p[j + 4], 4);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) q2[j] = (b1 ? q4[j + 2] : q4[j]) + __shfl_xor(b1 ? q4[j] : q4[j + 2], 2);
+  double v = (b0 ? q2[1] : q2[0]) + __shfl_xor(b0 ? q2[0] : q2[1], 1);
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
 // ------------------------------------------------------------------ workgroup body
 // pool: TeamCfg::LDS_BYTES of LDS; jab_s: NA*NB doubles of LDS (bra Coulomb block).
-// Ket blocks of at least this many components use the streaming digestion.
-constexpr int TEAM_STREAM_MIN = 24;
 template <int LA, int LB, int LC, int LD, bool KLDS>
 __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                              double *jab_s, double *pool) {
@@ -279,6 +295,8 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     const double *Z = team_eri<LA, LB, LC, LD>(A.pp, sG, co, buf, qi, geo, smax);
     stage_density<NA, NB, NC, ND, QB>(A, bra, bi, Dm, nc, qi, ds);
     for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
+    double *pbc = ds + C::DSTG, *pbd = pbc + QB * NB * NCD;   // streamed digestion only
+    for (int t = tid; t < C::PBD; t += blockDim.x) pbc[t] = 0.0;
     __syncthreads();
     const double *dab_s = ds, *sq = ds + NAB + QB * DQ;
     if constexpr (NCD < TEAM_STREAM_MIN) {
@@ -350,9 +368,10 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       continue;
     }
     // Digestion, every integral read once: each wave streams rows (a, b) of the block (RB rows
-    // loaded together: all NB rows of an a when they fit), its lanes run over (c, d). J[a,b] is wave-reduced per row; J[c,d],
-    // K[a,c] and K[a,d] collect in registers; K[b,c] and K[b,d] in LDS. The per-quartet sums
-    // are flushed below.
+    // loaded together: all NB rows of an a when they fit), its lanes run over (c, d). J[a,b] is
+    // wave-reduced eight rows at a time; J[c,d], K[a,c] and K[a,d] collect in registers; K[b,c]
+    // and K[b,d] in LDS per (b, cd), summed over d or c afterwards (no two lanes of a wave add
+    // to the same address). The per-quartet sums are flushed below.
     const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     constexpr int RB = NB * CH <= 32 ? NB : 4;
     for (int q = 0; q < QB; ++q) {
@@ -361,8 +380,9 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       const double *g = Z + (size_t)q * NG;
       const double *Dcd = ds + NAB + q * DQ, *Dac = Dcd + NCD, *Dad = Dac + NA * NC, *Dbc = Dad + NA * ND,
                    *Dbd = Dbc + NB * NC;
-      double *kac = dg + q * C::DG, *kad = kac + NA * NC, *kbc = kad + NA * ND, *kbd = kbc + NB * NC;
-      double *jcd = kbd + NB * ND;
+      double *kac = dg + q * C::DG, *kad = kac + NA * NC;
+      double *jcd = kad + NA * ND + NB * NC + NB * ND;
+      double *pbcq = pbc + q * NB * NCD, *pbdq = pbd + q * NB * NCD;
       int cc[CH], dd[CH];
       bool on[CH];
       double dcd[CH], jcda[CH];
@@ -384,6 +404,10 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
           kacs[h] = 0.0;
           kads[h] = 0.0;
         }
+        constexpr int NB8 = (NB + 7) / 8 * 8;
+        double vr[NB8];
+#pragma unroll
+        for (int b = NB; b < NB8; ++b) vr[b] = 0.0;
 #pragma unroll
         for (int b0 = 0; b0 < NB; b0 += RB) {
           double xs[RB][CH];
@@ -406,13 +430,20 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
               jcda[h] = fma(x, dab, jcda[h]);
               kacs[h] = fma(x, Dbd[b * ND + dd[h]], kacs[h]);
               kads[h] = fma(x, Dbc[b * NC + cc[h]], kads[h]);
-              atomicAdd(&kbc[b * NC + cc[h]], x * dad[h]);
-              atomicAdd(&kbd[b * ND + dd[h]], x * dac[h]);
+              atomicAdd(&pbcq[b * NCD + h * 64 + lane], x * dad[h]);
+              atomicAdd(&pbdq[b * NCD + h * 64 + lane], x * dac[h]);
             }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) vab += __shfl_xor(vab, o);
-            if (lane == 0 && vab != 0.0) atomicAdd(&jab_s[a * NB + b], s2 * vab);
+            vr[b] = vab;
           }
+        }
+#pragma unroll
+        for (int b0 = 0; b0 < NB8; b0 += 8) {
+          double p8[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) p8[i] = vr[b0 + i];
+          const double v = rows8_sum(p8, lane);
+          const int b = b0 + lane;
+          if (lane < 8 && b < NB && v != 0.0) atomicAdd(&jab_s[a * NB + b], s2 * v);
         }
 #pragma unroll
         for (int h = 0; h < CH; ++h)
@@ -424,6 +455,25 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
 #pragma unroll
       for (int h = 0; h < CH; ++h)
         if (on[h]) atomicAdd(&jcd[h * 64 + lane], jcda[h]);
+    }
+    __syncthreads();
+    // K[b,c] = sum_d and K[b,d] = sum_c of the per-(b, cd) partials
+    for (int t = tid; t < QB * NB * (NC + ND); t += blockDim.x) {
+      const int q = t / (NB * (NC + ND)), r = t % (NB * (NC + ND));
+      const double *pq = pbc + q * NB * NCD, *pdq = pbd + q * NB * NCD;
+      double *kbc = dg + q * C::DG + NA * NC + NA * ND, *kbd = kbc + NB * NC;
+      double v = 0.0;
+      if (r < NB * NC) {
+        const int b = r / NC, c = r % NC;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) v += pq[b * NCD + c * ND + d];
+        kbc[r] = v;
+      } else {
+        const int b = (r - NB * NC) / ND, d = (r - NB * NC) % ND;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v += pdq[b * NCD + c * ND + d];
+        kbd[r - NB * NC] = v;
+      }
     }
     __syncthreads();
     for (int t = tid; t < QB * C::DG; t += blockDim.x) {
