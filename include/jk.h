@@ -159,10 +159,18 @@ int jk_schwarz(const jk_plan_t *plan, double *out);
  * (HOST out, (2l+1) x (l+1)(l+2)/2, row-major). Needs no device. l in 2..4. */
 int jk_sph_matrix(int l, double *out);
 
-/* Host-only test hook: the closed-form Rys rule the kernels use for 1 or 2 roots (Boys
- * moments F_0..F_(2N-1)(T) from a series or erf/exp, then the N-point Gauss rule), compiled
- * for the host from the same source. u, w: HOST arrays of nroots entries (u = t^2). */
+/* Host-only test hook: the closed-form Rys rule for 1 or 2 roots (paper section 2: the N-point
+ * Gauss rule of the weight whose moments are the Boys values F_0..F_(2N-1)(T), here from a
+ * series or erf/exp), compiled for the host from the kernels' source. u, w: HOST arrays of
+ * nroots entries (u = t^2). */
 int jk_rys_closed(int nroots, double T, double *u, double *w);
+
+/* Host-only test hook: the rule the lane-per-quartet kernels use for 1 or 2 roots: the same
+ * Gauss rule, with F_0..F_(2N-1)(T) from the Taylor series about the nearest point of a Boys
+ * grid (T_i = i/8, gen_boys_grid.py), compiled for the host from the kernels' source.
+ * Requires 0 <= T < 40 (one root) or 50 (two roots), beyond which the kernels take the
+ * Gauss-Hermite limit; else JK_EINVAL. u, w: HOST arrays of nroots entries (u = t^2). */
+int jk_rys_grid(int nroots, double T, double *u, double *w);
 
 /* ---- Batched build: many independent molecules in one pass.
  * The shell pairs of all molecules share the class work lists and the persistent

@@ -1172,11 +1172,35 @@ int plan_stats(const jk_plan *plan, jk_stats_t *out) {
   return JK_OK;
 }
 
+// host copy of the Boys grid for the test hook below
+namespace host_boys {
+#define BOYS_STORAGE static const
+#include "boys_grid.h"
+#undef BOYS_STORAGE
+}  // namespace host_boys
+
 }  // namespace
 
 extern "C" {
 
 const char *jk_last_error(void) { return g_err.c_str(); }
+
+int jk_rys_grid(int nroots, double T, double *u, double *w) {
+  if (!u || !w) return fail(JK_EINVAL, "NULL argument");
+  if (nroots != 1 && nroots != 2) return fail(JK_EINVAL, "the grid rule exists for 1 or 2 roots only");
+  if (!(T >= 0.0) || !(T < (double)RYS_TMAX[nroots]))
+    return fail(JK_EINVAL, "T must be in [0, %d) for %d roots", RYS_TMAX[nroots], nroots);
+  if (nroots == 1) {
+    double uu[1], ww[1];
+    rys_taylor<1>(T, host_boys::BOYS_GRID, uu, ww);
+    u[0] = uu[0]; w[0] = ww[0];
+  } else {
+    double uu[2], ww[2];
+    rys_taylor<2>(T, host_boys::BOYS_GRID, uu, ww);
+    u[0] = uu[0]; u[1] = uu[1]; w[0] = ww[0]; w[1] = ww[1];
+  }
+  return JK_OK;
+}
 
 int jk_rys_closed(int nroots, double T, double *u, double *w) {
   if (!u || !w) return fail(JK_EINVAL, "NULL argument");

@@ -21,6 +21,9 @@
 
 #define RYS_STORAGE static __device__ const
 #include "rys_table.h"
+#define BOYS_STORAGE static __device__ const
+#include "boys_grid.h"
+#undef BOYS_STORAGE
 
 namespace jk {
 
@@ -157,6 +160,64 @@ __host__ __device__ __forceinline__ void rys_closed(double T, double (&u)[N], do
     u[1] = big;
     w[0] = (F[1] - big * F[0]) / (small - big);
     w[1] = F[0] - w[0];
+  }
+}
+
+// One- and two-root rules for 0 <= T < RYS_TMAX[N] from the Boys moments F_0..F_(2N-1)(T),
+// each taken from the grid point T_i = i/8 nearest to T by its Taylor series (dF_m/dT =
+// -F_(m+1), nine terms, relative remainder < 5e-17), then the Gauss rule of those moments as
+// in rys_closed. grid: BOYS_GRID (device) or its host copy.
+template <int N>
+__host__ __device__ __forceinline__ void rys_taylor(double T, const double *grid, double (&u)[N], double (&w)[N]) {
+  static_assert(N == 1 || N == 2, "grid rule only for one or two roots");
+  constexpr int K = 9;                                // Taylor terms
+  const int i = (int)(T * BOYS_DT_INV + 0.5);         // T in [0, RYS_TMAX[N]) -> i <= 400
+  const double x = (double)i * (1.0 / BOYS_DT_INV) - T;
+  const double *f = grid + i * BOYS_NM;
+  double g[2 * N + K - 1];
+#pragma unroll
+  for (int k = 0; k < 2 * N + K - 1; ++k) g[k] = f[k];
+  double xk[K];
+#pragma unroll
+  for (int k = 1; k < K; ++k) xk[k] = x * (1.0 / k);
+  double F[2 * N];
+#pragma unroll
+  for (int m = 0; m < 2 * N; ++m) {
+    double v = g[m + K - 1];
+#pragma unroll
+    for (int k = K - 1; k >= 1; --k) v = fma(xk[k], v, g[m + k - 1]);
+    F[m] = v;
+  }
+  if constexpr (N == 1) {
+    u[0] = F[1] / F[0];
+    w[0] = F[0];
+  } else {
+    const double det = F[0] * F[2] - F[1] * F[1];
+    const double c1 = (F[1] * F[2] - F[0] * F[3]) / det;       // u^2 + c1 u + c0
+    const double c0 = (F[1] * F[3] - F[2] * F[2]) / det;
+    const double disc = sqrt(c1 * c1 - 4.0 * c0);
+    const double big = 0.5 * (-c1 + disc);
+    const double small = c0 / big;
+    u[0] = small;
+    u[1] = big;
+    w[0] = (F[1] - big * F[0]) / (small - big);
+    w[1] = F[0] - w[0];
+  }
+}
+
+// All N roots (N = 1, 2) by the grid rule, the Gauss-Hermite limit beyond RYS_TMAX[N].
+template <int N>
+__device__ __forceinline__ void rys_low(double T, double (&u)[N], double (&w)[N]) {
+  if (T >= (double)RYS_TMAX[N]) {
+    const double it = 1.0 / T;
+    const double isq = sqrt(it);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      u[n] = RYS_HERM_S2[RYS_HOFF[N] + n] * it;
+      w[n] = RYS_HERM_W[RYS_HOFF[N] + n] * isq;
+    }
+  } else {
+    rys_taylor<N>(T, BOYS_GRID, u, w);
   }
 }
 

@@ -25,14 +25,18 @@
 #ifndef JK_TEAM2_KB
 #define JK_TEAM2_KB 48
 #endif
+#ifndef JK_TEAM2_NEMAX
+#define JK_TEAM2_NEMAX 56     // largest [e0| component count of the one-stage body (0: not used)
+#endif
 #ifndef JK_TEAM2_PCMAX
 #define JK_TEAM2_PCMAX 4
 #endif
 
-// 1 and 2 roots from the closed-form rule (Boys moments) instead of the interpolation table
-// (off: the table measured faster for the light classes)
-#ifndef JK_CLOSED_LOW_ROOTS
-#define JK_CLOSED_LOW_ROOTS 0
+// Rule for 1 and 2 roots in the lane bodies: 0 the interpolation table, 1 the closed form
+// from erf/series Boys moments, 2 the closed form from Boys moments taken off a grid by Taylor
+// series (fewest memory loads: 10 or 12 doubles per primitive quartet against 24 per root)
+#ifndef JK_LOW_ROOTS
+#define JK_LOW_ROOTS 2
 #endif
 
 namespace jk {
@@ -92,9 +96,12 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
           }
         }
       };
-      if constexpr (N <= 2 && JK_CLOSED_LOW_ROOTS) {
+      if constexpr (N <= 2 && JK_LOW_ROOTS != 0) {
         double u[N], w[N];
-        rys_closed<N>(Q.T, u, w);
+        if constexpr (JK_LOW_ROOTS == 1)
+          rys_closed<N>(Q.T, u, w);
+        else
+          rys_low<N>(Q.T, u, w);
 #pragma unroll
         for (int n = 0; n < N; ++n) root(u[n], w[n]);
       } else {
@@ -575,7 +582,7 @@ struct Team2Cfg {
   static constexpr int NE = range_count(LA, E), NF = range_count(LC, F);
   static constexpr int GS1 = (E + 1) * (F + 1);
   static constexpr int GS = 3 * GS1;
-  static constexpr bool OK = NE <= 56 && NF <= 256;
+  static constexpr bool OK = NE <= JK_TEAM2_NEMAX && NF <= 256;
   static constexpr int YS = NA * NB * NF;
   static constexpr int QB0 = 256 / NF;
   // The 2D integrals of a primitive chunk and, once the primitive loop is done, the

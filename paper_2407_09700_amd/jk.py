@@ -18,7 +18,7 @@ JK_FP64, JK_MIXED = 0, 1
 
 # every symbol declared in include/jk.h
 EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_build", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
-           "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_rys_closed", "jk_batch_create",
+           "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_rys_closed", "jk_rys_grid", "jk_batch_create",
            "jk_batch_offsets", "jk_batch_execute", "jk_batch_stats", "jk_batch_graph_info", "jk_batch_destroy",
            "jk_last_error"]
 JK_FLAG_PROFILE, JK_FLAG_GRAPH, JK_FLAG_TUNE = 1, 2, 4
@@ -81,6 +81,8 @@ def lib():
         L.jk_sph_matrix.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.jk_rys_closed.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
+        L.jk_rys_grid.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
         L.jk_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.POINTER(Basis)),
                                       ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(Opts), ctypes.POINTER(vp)]
@@ -116,6 +118,14 @@ def rys_closed(nroots: int, T: float):
     w = np.zeros(nroots)
     dp = ctypes.POINTER(ctypes.c_double)
     check(lib().jk_rys_closed(int(nroots), float(T), u.ctypes.data_as(dp), w.ctypes.data_as(dp)))
+    return u, w
+
+
+def rys_grid(nroots: int, T: float):
+    u = np.zeros(nroots)
+    w = np.zeros(nroots)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().jk_rys_grid(int(nroots), float(T), u.ctypes.data_as(dp), w.ctypes.data_as(dp)))
     return u, w
 
 

@@ -112,3 +112,46 @@ def test_closed_form_matches_table(table, N):
         ut, wt = rys_eval(table, N, float(T))
         np.testing.assert_allclose(u, ut, rtol=2e-13)
         np.testing.assert_allclose(w, wt, rtol=2e-13)
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_grid_rule_moment_identity(table, N):
+    """The lane bodies' rule for one or two roots (Boys values from a Taylor series about the
+    nearest grid point, then the Gauss rule of the moments; compiled for the host) against the
+    moment identity with scipy's incomplete gamma, over [0, TMAX[N]) including grid points,
+    midpoints between them and the ends."""
+    from paper_2407_09700_amd import jk
+    rng = np.random.default_rng(70 + N)
+    tmax = table["tmax"][N]
+    Ts = np.concatenate([[0.0, 1e-12, 1e-6, 0.0625, 0.0625 + 1e-13, 0.125, 0.1875, 1.0, 7.3125, tmax - 1e-9,
+                          tmax - 0.0625], rng.uniform(0, 2, 60), rng.uniform(0, tmax, 200)])
+    worst = 0.0
+    for T in Ts:
+        u, w = jk.rys_grid(N, float(T))
+        assert np.all(u > 0) and np.all(u < 1) and np.all(w > 0) and np.all(np.diff(u) > 0)
+        for m in range(2 * N):
+            ref = boys(m, float(T))
+            worst = max(worst, abs(np.sum(w * u ** m) - ref) / ref)
+    assert worst < 2e-14, worst
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_grid_rule_matches_table(table, N):
+    """Two independent evaluations of the same rule: the grid rule and the interpolation table
+    (which the larger root counts use) agree to 1e-13 relative."""
+    from paper_2407_09700_amd import jk
+    for T in np.linspace(0.0, table["tmax"][N] - 1e-6, 397):
+        u, w = jk.rys_grid(N, float(T))
+        ut, wt = rys_eval(table, N, float(T))
+        np.testing.assert_allclose(u, ut, rtol=1e-13)
+        np.testing.assert_allclose(w, wt, rtol=1e-13)
+
+
+def test_grid_rule_rejects_out_of_range():
+    from paper_2407_09700_amd import jk
+    with pytest.raises(jk.JKError):
+        jk.rys_grid(1, 40.0)
+    with pytest.raises(jk.JKError):
+        jk.rys_grid(2, -1.0)
+    with pytest.raises(jk.JKError):
+        jk.rys_grid(3, 1.0)
