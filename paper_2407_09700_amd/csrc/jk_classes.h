@@ -21,7 +21,7 @@ struct ClassInfo {           // one quartet class (la lb | lc ld)
   mode_launch_fn launch_mode[3];
 };
 
-constexpr int NTIERS = 3;    // register tiers of the fused kernels
+constexpr int NTIERS = 4;    // register tiers of the fused kernels (NTIER)
 
 struct BraInfo {             // one bra class (la lb), per register tier
   int la, lb;

@@ -80,7 +80,7 @@ void register_tier(BraInfo &b) {
   if constexpr (bra_fusable<LA, LB, TIER>() && tier_mask<LA, LB, TIER>() != 0) {
     b.launch_bra[TIER] = launch_bra<LA, LB, TIER>;
     allow_dyn_lds(k_bra<LA, LB, TIER>);
-    if constexpr (TIER < 2 && JK_FP32_BODIES) {
+    if constexpr (TIER < TEAM_TIER && JK_FP32_BODIES) {
       b.launch_bra32[TIER] = launch_bra<LA, LB, TIER, true>;
       allow_dyn_lds(k_bra<LA, LB, TIER, true>);
     }
@@ -96,6 +96,8 @@ void register_bra(ClassInfo *classes, BraInfo *bras) {
   register_tier<LA, LB, 0>(b);
   register_tier<LA, LB, 1>(b);
   register_tier<LA, LB, 2>(b);
+  register_tier<LA, LB, 3>(b);
+  static_assert(NTIERS == NTIER && TEAM_TIER == 3, "tier tables and kernels disagree");
 }
 
 }  // namespace jk

@@ -44,14 +44,22 @@ constexpr bool use_team() {
   return C::REGS > SMALL_REG_LIMIT || C::NG + C::NA * C::NB > SMALL_OUT_LIMIT;
 }
 
-// Register tiers of the fused kernels: 0 light lane bodies, 1 heavy lane bodies, 2 team bodies.
-// Each tier is its own launch so that the heaviest body does not set the occupancy of all.
-constexpr int NTIER = 3;
+// Register tiers of the fused kernels: 0 light, 1 middle and 2 heavy lane bodies, 3 team
+// bodies (TEAM_TIER). Each tier is its own launch so that the heaviest body does not set the
+// occupancy of all: the compiler sizes a kernel's registers by its largest body.
+constexpr int NTIER = 4, TEAM_TIER = 3;
+#ifndef JK_TIER0_MAX
+#define JK_TIER0_MAX 64
+#endif
+#ifndef JK_TIER1_MAX
+#define JK_TIER1_MAX 150
+#endif
 template <int LA, int LB, int LC, int LD>
 constexpr int tier_of() {
   using C = SmallCfg<LA, LB, LC, LD>;
-  if (use_team<LA, LB, LC, LD>()) return 2;
-  return (C::REGS <= 100 && C::NG + C::NA * C::NB <= 100) ? 0 : 1;
+  if (use_team<LA, LB, LC, LD>()) return TEAM_TIER;
+  constexpr int big = C::REGS > C::NG + C::NA * C::NB ? C::REGS : C::NG + C::NA * C::NB;
+  return big <= JK_TIER0_MAX ? 0 : (big <= JK_TIER1_MAX ? 1 : 2);
 }
 
 constexpr int pc_la(int c) { int l = 0; while ((l + 1) * (l + 2) / 2 <= c) ++l; return l; }
@@ -756,7 +764,7 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
           const int rot = (int)((b0 - lo) % blockDim.x);
           if constexpr (F32)
             ket_dispatch<LA, LB, TIER, 0, float>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab, rot);
-          else if constexpr (TIER == 2 || !JK_FP32_BODIES)   // team bodies evaluate the FP32 part in double
+          else if constexpr (TIER == TEAM_TIER || !JK_FP32_BODIES)   // team bodies evaluate the FP32 part in double
             ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab, rot);
           else if (part == 0)
             ket_dispatch<LA, LB, TIER, 0>(ck, A, bi, kl, (int)(b1 - b0), Krow, jab_s, pool, jab, rot);
