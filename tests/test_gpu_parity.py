@@ -141,3 +141,12 @@ def test_edge_long_contraction():
     coords = [[0.0, 0.0, 0.0], [0.0, 1.4, 0.9]]
     mol = synth.custom(coords, [(0, 20), (1, 20), (2, 1)], 0.05, 5000.0, pure_from_l=2, nocc=3, seed=21)
     _check(mol, thresh=1e-12, tag="K=20")
+
+
+def test_edge_negligible_primitive_pairs():
+    # tight primitives: every primitive pair between the two far atoms has a Gaussian product
+    # factor below exp(-60) (the shell pair keeps no primitive and drops out even at tau = 0),
+    # the near pair keeps only its more diffuse combinations; the oracle keeps every primitive
+    coords = [[0.0, 0.0, 0.0], [12.0, 0.0, 0.0], [1.5, 0.4, 0.0]]
+    mol = synth.custom(coords, [(0, 3), (1, 2), (2, 1)], 20.0, 2000.0, pure_from_l=2, nocc=4, seed=31)
+    _check(mol, thresh=0.0, tag="negligible primitive pairs")
