@@ -23,13 +23,16 @@
 
 // LDS budget (KB) and largest primitive chunk of the one-stage workgroup body
 #ifndef JK_TEAM2_KB
-#define JK_TEAM2_KB 48
+#define JK_TEAM2_KB 64
+#endif
+#ifndef JK_TEAM2_VRR_PASSES
+#define JK_TEAM2_VRR_PASSES 2   // passes of the block over the recurrence tasks of one chunk
 #endif
 #ifndef JK_TEAM2_NEMAX
 #define JK_TEAM2_NEMAX 56     // largest [e0| component count of the one-stage body (0: not used)
 #endif
 #ifndef JK_TEAM2_PCMAX
-#define JK_TEAM2_PCMAX 4
+#define JK_TEAM2_PCMAX 8
 #endif
 
 // Rule for 1 and 2 roots in the lane bodies: 0 the interpolation table, 1 the closed form
@@ -591,7 +594,7 @@ struct Team2Cfg {
   static constexpr int QB1 = BUDGET / (YS > N * GS ? YS : N * GS);   // Y fits, and one primitive chunk
   static constexpr int QB = (QB0 < QB1 ? QB0 : QB1) < 1 ? 1 : (QB0 < QB1 ? QB0 : QB1);
   static constexpr int PCB = BUDGET / (QB * N * GS);
-  static constexpr int PCT = 256 / (QB * N * 3);                 // VRR items in one pass of the block
+  static constexpr int PCT = JK_TEAM2_VRR_PASSES * 256 / (QB * N * 3);   // VRR items in so many passes of the block
   static constexpr int PC0 = PCB < PCT ? PCB : PCT;
   static constexpr int PC = PC0 < 1 ? 1 : (PC0 > JK_TEAM2_PCMAX ? JK_TEAM2_PCMAX : PC0);
   static constexpr int SG = QB * PC * N * GS;
