@@ -212,7 +212,7 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); the J/K path "
+        print(f"bench.py: the J/K path runs on one GPU only (--gpus {args.gpus} requested); it "
               f"would shard by bra-pair tiles with one all-reduce of J and K, which is not built.", file=sys.stderr)
         sys.exit(2)
 
