@@ -192,15 +192,17 @@ __host__ __device__ __forceinline__ void rys_taylor(double T, const double *grid
     u[0] = F[1] / F[0];
     w[0] = F[0];
   } else {
-    const double det = F[0] * F[2] - F[1] * F[1];
-    const double c1 = (F[1] * F[2] - F[0] * F[3]) / det;       // u^2 + c1 u + c0
-    const double c0 = (F[1] * F[3] - F[2] * F[2]) / det;
+    // zeros of u^2 + c1 u + c0 (the monic quadratic orthogonal to 1 and u), two divisions:
+    // small = c0 / big and w0 = (big F0 - F1) / (big - small) share 1 / (big disc), big - small = disc
+    const double idet = 1.0 / (F[0] * F[2] - F[1] * F[1]);
+    const double c1 = (F[1] * F[2] - F[0] * F[3]) * idet;
+    const double c0 = (F[1] * F[3] - F[2] * F[2]) * idet;
     const double disc = sqrt(c1 * c1 - 4.0 * c0);
     const double big = 0.5 * (-c1 + disc);
-    const double small = c0 / big;
-    u[0] = small;
+    const double r = 1.0 / (big * disc);
+    u[0] = c0 * disc * r;
     u[1] = big;
-    w[0] = (F[1] - big * F[0]) / (small - big);
+    w[0] = (big * F[0] - F[1]) * big * r;
     w[1] = F[0] - w[0];
   }
 }
