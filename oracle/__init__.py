@@ -50,6 +50,8 @@ def lib():
         L.oracle_eri_tensor.argtypes = basis + [dp]
         L.oracle_jk.argtypes = basis + [dp, ctypes.c_double, dp, dp, ctypes.c_int]
         L.oracle_jk.restype = ctypes.c_longlong
+        L.oracle_jk_want.argtypes = basis + [dp, ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_int]
+        L.oracle_jk_want.restype = ctypes.c_longlong
         L.oracle_jk_block.argtypes = basis + [dp, ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_int,
                                               dp, dp, ctypes.c_int]
         L.oracle_screen_tables.argtypes = basis + [dp, dp, dp]
@@ -57,6 +59,8 @@ def lib():
         L.oracle_jk_sample.restype = ctypes.c_longlong
         L.oracle_count_kept.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double]
         L.oracle_count_kept.restype = ctypes.c_longlong
+        L.oracle_count_kept_want.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int]
+        L.oracle_count_kept_want.restype = ctypes.c_longlong
         _lib = L
     return _lib
 
@@ -129,12 +133,15 @@ class Oracle:
         lib().oracle_screen_tables(*self._b(), _p(D), _p(I), _p(P))
         return I, P
 
-    def jk(self, D=None, tau=None, nthreads=0):
+    def jk(self, D=None, tau=None, nthreads=0, want="jk"):
+        """J and K over the quartets the density-weighted screen keeps for the outputs `want`
+        ("jk", "j" or "k": which density blocks enter the screen)."""
         D = np.ascontiguousarray(self.mol.D if D is None else D, np.float64)
         tau = float(self.mol.thresh if tau is None else tau)
         J = np.zeros((self.nbf, self.nbf))
         K = np.zeros((self.nbf, self.nbf))
-        kept = lib().oracle_jk(*self._b(), _p(D), tau, _p(J), _p(K), int(nthreads))
+        w = {"jk": 3, "j": 1, "k": 2}[want]
+        kept = lib().oracle_jk_want(*self._b(), _p(D), tau, _p(J), _p(K), int(nthreads), w)
         self.kept = int(kept)
         return J, K
 
@@ -155,7 +162,8 @@ class Oracle:
         tau = float(self.mol.thresh if tau is None else tau)
         return int(lib().oracle_jk_sample(*self._b(), _p(D), tau, int(stride), int(offset), int(nthreads)))
 
-    def count_kept(self, I, P, tau):
+    def count_kept(self, I, P, tau, want="jk"):
         I = np.ascontiguousarray(I, np.float64)
         P = np.ascontiguousarray(P, np.float64)
-        return int(lib().oracle_count_kept(self.ns, _p(I), _p(P), float(tau)))
+        w = {"jk": 3, "j": 1, "k": 2}[want]
+        return int(lib().oracle_count_kept_want(self.ns, _p(I), _p(P), float(tau), w))

@@ -408,17 +408,30 @@ static void density_blockmax(const basis_t *B, const int *off, const double *D, 
   }
 }
 
-static inline int keep_quartet(const double *I, const double *P, int ns, int i, int j, int k, int l, double tau) {
+/* Density-weighted screen of paper section 3: keep (ij|kl) iff both pair factors exceed tau
+ * and I_ij I_kl P >= tau, P the largest |D_cart| over the density blocks the quartet's updates
+ * read. want = 3 (J and K): all six blocks D_ij, D_kl, D_ik, D_il, D_jk, D_jl. want = 1 (J only):
+ * the Coulomb blocks D_ij, D_kl. want = 2 (K only): the exchange blocks D_ik, D_il, D_jk, D_jl. */
+static inline int keep_quartet_want(const double *I, const double *P, int ns, int i, int j, int k, int l,
+                                    double tau, int want) {
   const double Iij = I[(size_t)i * ns + j], Ikl = I[(size_t)k * ns + l];
   if (!(Iij > tau) || !(Ikl > tau)) return 0;
-  double p = P[(size_t)i * ns + j];
-  double t;
-  t = P[(size_t)k * ns + l]; if (t > p) p = t;
-  t = P[(size_t)i * ns + k]; if (t > p) p = t;
-  t = P[(size_t)i * ns + l]; if (t > p) p = t;
-  t = P[(size_t)j * ns + k]; if (t > p) p = t;
-  t = P[(size_t)j * ns + l]; if (t > p) p = t;
+  double p = 0.0, t;
+  if (want & 1) {
+    t = P[(size_t)i * ns + j]; if (t > p) p = t;
+    t = P[(size_t)k * ns + l]; if (t > p) p = t;
+  }
+  if (want & 2) {
+    t = P[(size_t)i * ns + k]; if (t > p) p = t;
+    t = P[(size_t)i * ns + l]; if (t > p) p = t;
+    t = P[(size_t)j * ns + k]; if (t > p) p = t;
+    t = P[(size_t)j * ns + l]; if (t > p) p = t;
+  }
   return Iij * Ikl * p >= tau;
+}
+
+static inline int keep_quartet(const double *I, const double *P, int ns, int i, int j, int k, int l, double tau) {
+  return keep_quartet_want(I, P, ns, i, j, k, l, tau, 3);
 }
 
 /* Apply J[i,j] += (ij|kl) D[k,l], K[i,k] += (ij|kl) D[j,l] for one ordered tuple.
@@ -456,10 +469,13 @@ static void permute_block(const double *in, const int n[4], const int perm[4], d
 static const int PERMS[8][4] = {{0, 1, 2, 3}, {1, 0, 2, 3}, {0, 1, 3, 2}, {1, 0, 3, 2},
                                 {2, 3, 0, 1}, {3, 2, 0, 1}, {2, 3, 1, 0}, {3, 2, 1, 0}};
 
-/* Full J and K (nbf x nbf, final basis). Returns the number of kept unique quartets. */
-long long oracle_jk(const double *coords, int nshell, const int *sh_atom, const int *sh_l, const int *sh_nprim,
-                    const int *sh_off, const int *sh_pure, const double *pexp, const double *pcoef,
-                    const double *tsph, const double *D, double tau, double *J, double *K, int nthreads) {
+/* Full J and K (nbf x nbf, final basis) over the quartets the screen keeps for the outputs
+ * `want` (bit 0 J, bit 1 K; both are always accumulated). Returns the number of kept unique
+ * quartets. */
+long long oracle_jk_want(const double *coords, int nshell, const int *sh_atom, const int *sh_l, const int *sh_nprim,
+                         const int *sh_off, const int *sh_pure, const double *pexp, const double *pcoef,
+                         const double *tsph, const double *D, double tau, double *J, double *K, int nthreads,
+                         int want) {
   init_tables();
   basis_t B; make_basis(&B, coords, nshell, sh_atom, sh_l, sh_nprim, sh_off, sh_pure, pexp, pcoef, tsph);
   int *off = (int *)malloc(sizeof(int) * (nshell + 1));
@@ -492,7 +508,7 @@ long long oracle_jk(const double *coords, int nshell, const int *sh_atom, const 
         while ((long long)k * (k + 1) / 2 > kl) --k;
         while ((long long)(k + 1) * (k + 2) / 2 <= kl) ++k;
         const int l = (int)(kl - (long long)k * (k + 1) / 2);
-        if (!keep_quartet(I, P, nshell, i, j, k, l, tau)) continue;
+        if (!keep_quartet_want(I, P, nshell, i, j, k, l, tau, want)) continue;
         ++kept;
         const int sh[4] = {i, j, k, l};
         eri_cart(&B, i, j, k, l, &w, cart);
@@ -522,6 +538,13 @@ long long oracle_jk(const double *coords, int nshell, const int *sh_atom, const 
   }
   free(I); free(P); free(off);
   return kept;
+}
+
+long long oracle_jk(const double *coords, int nshell, const int *sh_atom, const int *sh_l, const int *sh_nprim,
+                    const int *sh_off, const int *sh_pure, const double *pexp, const double *pcoef,
+                    const double *tsph, const double *D, double tau, double *J, double *K, int nthreads) {
+  return oracle_jk_want(coords, nshell, sh_atom, sh_l, sh_nprim, sh_off, sh_pure, pexp, pcoef, tsph, D, tau, J, K,
+                        nthreads, 3);
 }
 
 /* Sampled rows: for shells si, sj, the J block J[si,sj] = sum over ALL shells k,l of
@@ -613,8 +636,8 @@ int oracle_screen_tables(const double *coords, int nshell, const int *sh_atom, c
   return 0;
 }
 
-/* Number of unique quartets kept by the predicate (counts only; no integrals). */
-long long oracle_count_kept(int nshell, const double *I, const double *P, double tau) {
+/* Number of unique quartets kept by the predicate for the outputs `want` (counts only). */
+long long oracle_count_kept_want(int nshell, const double *I, const double *P, double tau, int want) {
   const long long npair = (long long)nshell * (nshell + 1) / 2;
   long long kept = 0;
 #pragma omp parallel for reduction(+ : kept) schedule(dynamic, 16)
@@ -628,10 +651,14 @@ long long oracle_count_kept(int nshell, const double *I, const double *P, double
       while ((long long)k * (k + 1) / 2 > kl) --k;
       while ((long long)(k + 1) * (k + 2) / 2 <= kl) ++k;
       const int l = (int)(kl - (long long)k * (k + 1) / 2);
-      kept += keep_quartet(I, P, nshell, i, j, k, l, tau);
+      kept += keep_quartet_want(I, P, nshell, i, j, k, l, tau, want);
     }
   }
   return kept;
+}
+
+long long oracle_count_kept(int nshell, const double *I, const double *P, double tau) {
+  return oracle_count_kept_want(nshell, I, P, tau, 3);
 }
 
 /* Full ERI tensor in the final basis, out[mu][nu][la][si] (nbf^4, small inputs only). */

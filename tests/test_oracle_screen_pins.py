@@ -89,6 +89,42 @@ def test_kept_count_matches_six_block_predicate(cfg2_small, tau):
         assert np.count_nonzero(two) < n_np
 
 
+@pytest.mark.parametrize("want", ["j", "k"])
+@pytest.mark.parametrize("tau", [1e-9, 1e-5])
+def test_kept_count_matches_output_predicate(cfg2_small, want, tau):
+    # J-only builds weigh the quartet by the Coulomb blocks D_ij, D_kl only; K-only builds by
+    # the exchange blocks D_ik, D_il, D_jk, D_jl only (the blocks each build's updates read)
+    mol, o, I, P = cfg2_small
+    pr = np.array(_pairs(mol.nshell))
+    a, b = np.tril_indices(len(pr))
+    i, j = pr[a, 0], pr[a, 1]
+    k, l = pr[b, 0], pr[b, 1]
+    Iij, Ikl = I[i, j], I[k, l]
+    if want == "j":
+        p = np.maximum(P[i, j], P[k, l])
+    else:
+        p = np.maximum.reduce([P[i, k], P[i, l], P[j, k], P[j, l]])
+    keep = (Iij > tau) & (Ikl > tau) & (Iij * Ikl * p >= tau)
+    n_np = int(np.count_nonzero(keep))
+    assert o.count_kept(I, P, tau, want=want) == n_np
+    o.jk(tau=tau, want=want)
+    assert o.kept == n_np
+    assert n_np < o.count_kept(I, P, tau)          # fewer than the six-block screen keeps
+
+
+def test_output_screen_exact_at_zero_threshold(cfg2_small):
+    # with tau = 0 every quartet is kept whatever the outputs: the same J and K (up to the
+    # order in which the threads' partial sums are added)
+    mol, o, I, P = cfg2_small
+    J3, K3 = o.jk(tau=0.0)
+    n3 = o.kept
+    for want in ("j", "k"):
+        J1, K1 = o.jk(tau=0.0, want=want)
+        assert o.kept == n3
+        assert np.max(np.abs(J1 - J3)) <= 1e-13 * np.max(np.abs(J3))
+        assert np.max(np.abs(K1 - K3)) <= 1e-13 * np.max(np.abs(K3))
+
+
 def test_screened_minus_exact_within_dropped_bounds(cfg2_small):
     # |J(tau) - J(0)| and |K(tau) - K(0)| per element stay within the sum, over the
     # ordered quartets the predicate drops, of n_c n_d I_ab I_cd P_block (every integral
