@@ -57,6 +57,9 @@ def lib():
         L.oracle_screen_tables.argtypes = basis + [dp, dp, dp]
         L.oracle_jk_sample.argtypes = basis + [dp, ctypes.c_double, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int]
         L.oracle_jk_sample.restype = ctypes.c_longlong
+        L.oracle_grad.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, dp, dp, dp, dp, ctypes.c_double,
+                                  dp, ctypes.c_int]
+        L.oracle_grad.restype = ctypes.c_longlong
         L.oracle_count_kept.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double]
         L.oracle_count_kept.restype = ctypes.c_longlong
         L.oracle_count_kept_want.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int]
@@ -161,6 +164,19 @@ class Oracle:
         D = np.ascontiguousarray(self.mol.D if D is None else D, np.float64)
         tau = float(self.mol.thresh if tau is None else tau)
         return int(lib().oracle_jk_sample(*self._b(), _p(D), tau, int(stride), int(offset), int(nthreads)))
+
+    def grad(self, D=None, tau=None, nthreads=0):
+        """d/dR of E = tr(D (J - K/2)) with D held fixed, natom x 3 (shells up to l = 3)."""
+        D = np.ascontiguousarray(self.mol.D if D is None else D, np.float64)
+        tau = float(self.mol.thresh if tau is None else tau)
+        natom = int(self.coords.shape[0])
+        g = np.zeros((natom, 3))
+        b = self._b()
+        kept = lib().oracle_grad(b[0], natom, *b[1:], _p(D), tau, _p(g), int(nthreads))
+        if kept < 0:
+            raise ValueError("oracle gradient: shells up to l = 3 only")
+        self.kept = int(kept)
+        return g
 
     def count_kept(self, I, P, tau, want="jk"):
         I = np.ascontiguousarray(I, np.float64)

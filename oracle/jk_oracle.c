@@ -661,6 +661,149 @@ long long oracle_count_kept(int nshell, const double *I, const double *P, double
   return oracle_count_kept_want(nshell, I, P, tau, 3);
 }
 
+/* ------------------------------------------------------------------ nuclear gradient */
+/* Gradient of E = sum over ordered quartets (ij|kl) [D_ij D_kl - D_ik D_jl / 2] with respect to
+ * the atomic coordinates, D held fixed (the two-electron part of the nuclear gradient, paper
+ * section 4; E is tr(D (J - K/2)) of the J/K build). Every derivative integral comes from the
+ * differentiation of a primitive Cartesian Gaussian,
+ *   d/dA_x [x_A^a exp(-alpha r_A^2)] = 2 alpha x_A^(a+1) exp(...) - a x_A^(a-1) exp(...),
+ * so that d(ij|kl)/dA_x = (i+1_x j|kl) with coefficients 2 alpha c - a_x (i-1_x j|kl), and the
+ * same on each of the four centres (no translational invariance used). The shifted shells
+ * are extra shells of an extended basis evaluated with the same ERI routine. A unique quartet
+ * stands for the 8s distinct ordered quartets of its orbit (s = 1/|stabiliser|), whose weights
+ * add up to W_abcd = s [8 D_ab D_cd - 2 D_ac D_bd - 2 D_ad D_bc]. The screen is the J/K
+ * build's (six density blocks). Shells up to l = 3 (the raised shell must stay within l = 4).
+ * grad: natom x 3, overwritten. Returns the number of kept unique quartets, or -1 if a shell
+ * has l > 3. */
+long long oracle_grad(const double *coords, int natom, int nshell, const int *sh_atom, const int *sh_l,
+                      const int *sh_nprim, const int *sh_off, const int *sh_pure, const double *pexp,
+                      const double *pcoef, const double *tsph, const double *D, double tau, double *grad,
+                      int nthreads) {
+  init_tables();
+  if (nshell <= 0 || natom <= 0) return -1;
+  for (int s = 0; s < nshell; ++s)
+    if (sh_l[s] > LMAX - 1) return -1;
+  /* extended basis: shells 0..ns-1 as given, ns + s raised (l+1, coefficients 2 alpha c),
+   * 2 ns + s lowered (l-1, coefficients c; unused for l = 0) */
+  int nprim_tot = 0;
+  for (int s = 0; s < nshell; ++s)
+    if (sh_off[s] + sh_nprim[s] > nprim_tot) nprim_tot = sh_off[s] + sh_nprim[s];
+  const int ns3 = 3 * nshell;
+  int *xa = (int *)malloc(sizeof(int) * ns3), *xl = (int *)malloc(sizeof(int) * ns3);
+  int *xn = (int *)malloc(sizeof(int) * ns3), *xo = (int *)malloc(sizeof(int) * ns3);
+  int *xp = (int *)calloc((size_t)ns3, sizeof(int));
+  double *xe = (double *)malloc(sizeof(double) * 2 * nprim_tot), *xc = (double *)malloc(sizeof(double) * 2 * nprim_tot);
+  for (int k = 0; k < nprim_tot; ++k) {
+    xe[k] = pexp[k]; xc[k] = pcoef[k];
+    xe[nprim_tot + k] = pexp[k]; xc[nprim_tot + k] = 2.0 * pexp[k] * pcoef[k];
+  }
+  for (int s = 0; s < nshell; ++s) {
+    for (int v = 0; v < 3; ++v) {
+      const int t = v * nshell + s;
+      xa[t] = sh_atom[s]; xn[t] = sh_nprim[s];
+      xl[t] = sh_l[s] + (v == 1 ? 1 : v == 2 ? -1 : 0);
+      if (xl[t] < 0) xl[t] = 0;
+      xo[t] = sh_off[s] + (v == 1 ? nprim_tot : 0);
+      xp[t] = 0;                                  /* derivative blocks stay Cartesian */
+    }
+  }
+  basis_t B; make_basis(&B, coords, nshell, sh_atom, sh_l, sh_nprim, sh_off, sh_pure, pexp, pcoef, tsph);
+  basis_t X; make_basis(&X, coords, ns3, xa, xl, xn, xo, xp, xe, xc, tsph);
+  int *off = (int *)malloc(sizeof(int) * (nshell + 1));
+  ao_offsets(&B, off);
+  const int nbf = off[nshell];
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  double *I = (double *)malloc(sizeof(double) * nshell * nshell);
+  double *P = (double *)malloc(sizeof(double) * nshell * nshell);
+  oracle_schwarz(coords, nshell, sh_atom, sh_l, sh_nprim, sh_off, sh_pure, pexp, pcoef, tsph, I);
+  density_blockmax(&B, off, D, nbf, P);
+  memset(grad, 0, sizeof(double) * 3 * natom);
+  const long long npair = (long long)nshell * (nshell + 1) / 2;
+  long long kept = 0;
+#pragma omp parallel reduction(+ : kept)
+  {
+    work_t w; work_alloc(&w);
+    double *raised = (double *)malloc(sizeof(double) * 21 * BLK_MAX / 15);
+    double *lowered = (double *)malloc(sizeof(double) * BLK_MAX);
+    double *dcart = (double *)malloc(sizeof(double) * BLK_MAX), *fin = (double *)malloc(sizeof(double) * BLK_MAX);
+    double *tmp = (double *)malloc(sizeof(double) * BLK_MAX);
+    double *g = (double *)calloc((size_t)3 * natom, sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+    for (long long ij = 0; ij < npair; ++ij) {
+      int i = (int)((sqrt(8.0 * ij + 1) - 1) / 2);
+      while ((long long)i * (i + 1) / 2 > ij) --i;
+      while ((long long)(i + 1) * (i + 2) / 2 <= ij) ++i;
+      const int j = (int)(ij - (long long)i * (i + 1) / 2);
+      for (long long kl = 0; kl <= ij; ++kl) {
+        int k = (int)((sqrt(8.0 * kl + 1) - 1) / 2);
+        while ((long long)k * (k + 1) / 2 > kl) --k;
+        while ((long long)(k + 1) * (k + 2) / 2 <= kl) ++k;
+        const int l = (int)(kl - (long long)k * (k + 1) / 2);
+        if (!keep_quartet(I, P, nshell, i, j, k, l, tau)) continue;
+        ++kept;
+        const int sh[4] = {i, j, k, l};
+        const int nc[4] = {ncart(sh_l[i]), ncart(sh_l[j]), ncart(sh_l[k]), ncart(sh_l[l])};
+        const int nf[4] = {nsph(sh_l[i], sh_pure[i]), nsph(sh_l[j], sh_pure[j]), nsph(sh_l[k], sh_pure[k]),
+                           nsph(sh_l[l], sh_pure[l])};
+        const double s = (i == j ? 0.5 : 1.0) * (k == l ? 0.5 : 1.0) * (ij == kl ? 0.5 : 1.0);
+        for (int q = 0; q < 4; ++q) {
+          const int lq = sh_l[sh[q]];
+          int shp[4] = {i, j, k, l}, shm[4] = {i, j, k, l};
+          shp[q] = nshell + sh[q];
+          shm[q] = 2 * nshell + sh[q];
+          eri_cart(&X, shp[0], shp[1], shp[2], shp[3], &w, raised);
+          if (lq > 0) eri_cart(&X, shm[0], shm[1], shm[2], shm[3], &w, lowered);
+          int np[4] = {nc[0], nc[1], nc[2], nc[3]}, nm[4] = {nc[0], nc[1], nc[2], nc[3]};
+          np[q] = ncart(lq + 1);
+          nm[q] = lq > 0 ? ncart(lq - 1) : 0;
+          for (int x = 0; x < 3; ++x) {
+            int idx[4];
+            for (idx[0] = 0; idx[0] < nc[0]; ++idx[0])
+              for (idx[1] = 0; idx[1] < nc[1]; ++idx[1])
+                for (idx[2] = 0; idx[2] < nc[2]; ++idx[2])
+                  for (idx[3] = 0; idx[3] < nc[3]; ++idx[3]) {
+                    /* component of shell q and its raised / lowered neighbours in direction x */
+                    const int cf = g_level_start[lq] + idx[q];
+                    int cv[3] = {g_comp[cf][0], g_comp[cf][1], g_comp[cf][2]};
+                    int pi[4] = {idx[0], idx[1], idx[2], idx[3]};
+                    cv[x] += 1;
+                    pi[q] = g_flat[cv[0]][cv[1]][cv[2]] - g_level_start[lq + 1];
+                    double v = raised[(((size_t)pi[0] * np[1] + pi[1]) * np[2] + pi[2]) * np[3] + pi[3]];
+                    cv[x] -= 2;
+                    if (cv[x] >= 0) {
+                      int mi[4] = {idx[0], idx[1], idx[2], idx[3]};
+                      mi[q] = g_flat[cv[0]][cv[1]][cv[2]] - g_level_start[lq - 1];
+                      v -= (cv[x] + 1) * lowered[(((size_t)mi[0] * nm[1] + mi[1]) * nm[2] + mi[2]) * nm[3] + mi[3]];
+                    }
+                    dcart[(((size_t)idx[0] * nc[1] + idx[1]) * nc[2] + idx[2]) * nc[3] + idx[3]] = v;
+                  }
+            to_final(&B, sh, dcart, fin, tmp);
+            double acc = 0.0;
+            for (int a = 0; a < nf[0]; ++a)
+              for (int b = 0; b < nf[1]; ++b)
+                for (int c = 0; c < nf[2]; ++c)
+                  for (int d = 0; d < nf[3]; ++d) {
+                    const int A_ = off[i] + a, B_ = off[j] + b, C_ = off[k] + c, D_ = off[l] + d;
+                    const double Wt = 8.0 * D[(size_t)A_ * nbf + B_] * D[(size_t)C_ * nbf + D_] -
+                                      2.0 * D[(size_t)A_ * nbf + C_] * D[(size_t)B_ * nbf + D_] -
+                                      2.0 * D[(size_t)A_ * nbf + D_] * D[(size_t)B_ * nbf + C_];
+                    acc += Wt * fin[(((size_t)a * nf[1] + b) * nf[2] + c) * nf[3] + d];
+                  }
+            g[3 * sh_atom[sh[q]] + x] += s * acc;
+          }
+        }
+      }
+    }
+#pragma omp critical(oracle_reduce_grad)
+    {
+      for (int t = 0; t < 3 * natom; ++t) grad[t] += g[t];
+    }
+    free(g); free(raised); free(lowered); free(dcart); free(fin); free(tmp); work_free(&w);
+  }
+  free(I); free(P); free(off); free(xa); free(xl); free(xn); free(xo); free(xp); free(xe); free(xc);
+  return kept;
+}
+
 /* Full ERI tensor in the final basis, out[mu][nu][la][si] (nbf^4, small inputs only). */
 int oracle_eri_tensor(const double *coords, int nshell, const int *sh_atom, const int *sh_l, const int *sh_nprim,
                       const int *sh_off, const int *sh_pure, const double *pexp, const double *pcoef,
