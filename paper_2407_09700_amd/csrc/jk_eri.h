@@ -58,7 +58,8 @@ struct SmallCfg {
 };
 
 // R: type of the 2D integrals, their products and the transfer (double, or float for the
-// FP32 quartets of mixed precision; roots, weights and the per-primitive scalars stay double).
+// FP32 quartets of mixed precision; roots, weights, the per-primitive scalars and the sum over
+// primitive quartets and roots stay double).
 template <int LA, int LB, int LC, int LD, typename R = double>
 __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, const PrimPair *__restrict__ pp,
                                           R (&g)[SmallCfg<LA, LB, LC, LD>::NG]) {
@@ -66,9 +67,11 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
-  R acc[NE * NF];
+  // the contraction over primitive quartets and roots is accumulated in double for both
+  // types: an FP32 product is widened before it is added
+  double acc[NE * NF];
 #pragma unroll
-  for (int i = 0; i < NE * NF; ++i) acc[i] = (R)0;
+  for (int i = 0; i < NE * NF; ++i) acc[i] = 0.0;
 
   // ket primitives outside: their loads differ from lane to lane, the bra's are the same for
   // every lane of the workgroup (one cache line per wave)
@@ -94,8 +97,11 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
         for (int ie = 0; ie < NE; ++ie) {
 #pragma unroll
           for (int jf = 0; jf < NF; ++jf) {
-            acc[ie * NF + jf] = fma(Gx[CT.x[E0 + ie]][CT.x[F0 + jf]] * Gy[CT.y[E0 + ie]][CT.y[F0 + jf]],
-                                    Gz[CT.z[E0 + ie]][CT.z[F0 + jf]], acc[ie * NF + jf]);
+            const R gxy = Gx[CT.x[E0 + ie]][CT.x[F0 + jf]] * Gy[CT.y[E0 + ie]][CT.y[F0 + jf]];
+            if constexpr (sizeof(R) == sizeof(double))
+              acc[ie * NF + jf] = fma(gxy, Gz[CT.z[E0 + ie]][CT.z[F0 + jf]], acc[ie * NF + jf]);
+            else
+              acc[ie * NF + jf] += (double)(gxy * Gz[CT.z[E0 + ie]][CT.z[F0 + jf]]);
           }
         }
       };
@@ -154,7 +160,7 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
             const int ie = CT.idx[ax + kx][ay + ky][az + kz] - E0;
 #pragma unroll
             for (int jf = 0; jf < NF; ++jf)
-              hb[(a * NB + b) * NF + jf] = fma(cf, acc[ie * NF + jf], hb[(a * NB + b) * NF + jf]);
+              hb[(a * NB + b) * NF + jf] = fma(cf, (R)acc[ie * NF + jf], hb[(a * NB + b) * NF + jf]);
           }
         }
       }
