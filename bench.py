@@ -1,12 +1,17 @@
 """Benchmark of the integral-direct J/K build on one MI355X.
 
-A step is one jk_plan_execute on the 64-atom clustered 3s2p1d molecule (spherical d,
-896 AOs, Schwarz threshold 1e-12): density transform, block maxima, screening into
+A step is one jk_plan_execute on the 256-atom clustered 3s2p1d molecule (spherical d,
+3584 AOs, Schwarz threshold 1e-12): density transform, block maxima, screening into
 class work lists, every class kernel (Rys ERIs + contraction + digestion) and the final
-symmetrise/transform. Inputs are resident in HBM; the plan (pairs + Schwarz factors) is
-built once before the timed region, as an SCF would reuse it across iterations.
+symmetrise/transform. Inputs are resident in HBM; the plan (pairs + Schwarz factors) and the
+first build (which sizes the work lists) come before the timed region, as an SCF reuses a plan
+across iterations. Per-launch HIP events are recorded inside every timed build and read after
+the timed loop (the roofline of the launch with the largest time, averaged over the steps).
 
-Prints ONE JSON line. value = kept (screened) unique shell quartets per second.
+Prints ONE JSON line. value = kept (screened) unique shell quartets per second. Extras: the
+mixed-precision build of the same molecule (energies against the oracle's FP64 fixture), the
+32-atom g-function molecule and the 64-atom molecule with their per-launch rooflines, and the
+64-molecule batch.
 """
 from __future__ import annotations
 
@@ -77,31 +82,38 @@ def copy_probe(nbytes):
 
 
 def cpu_baseline(mol, target_s=12.0):
+    """The oracle (all host cores) on every stride-th bra shell pair of the same molecule and
+    threshold: the unique quartets of those bras, screened, evaluated and digested."""
     import oracle
     o = oracle.Oracle(mol)
     ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    t = time.perf_counter()
-    n = o.jk_sample(256, 0, nthreads=ncores)
-    probe = time.perf_counter() - t
-    rate = max(n, 1) / max(probe, 1e-3)
     npair = mol.nshell * (mol.nshell + 1) // 2
-    total_est = rate and (n * 256)                      # rough kept count of the full build
-    stride = max(1, int(round(256 * probe / target_s)))
+    stride = 4096
     t = time.perf_counter()
-    kept = o.jk_sample(stride, 1, nthreads=ncores)
+    kept = o.jk_sample(stride, 0, nthreads=ncores)
     dt = time.perf_counter() - t
-    if dt < 0.4 * target_s and stride > 1:          # the small probe overstated the cost: sample more
-        stride = max(1, int(stride * dt / target_s))
+    while dt < 0.4 * target_s and stride > 1:      # sample more until the run is long enough
+        stride = max(1, int(stride * max(dt, 1e-3) / target_s))
         t = time.perf_counter()
-        kept = o.jk_sample(stride, 1, nthreads=ncores)
+        kept = o.jk_sample(stride, 0, nthreads=ncores)
         dt = time.perf_counter() - t
-    log(f"cpu baseline: stride {stride} of {npair} bra pairs, {kept} quartets in {dt:.1f}s (est. full {total_est})")
+    log(f"cpu baseline: stride {stride} of {npair} bra pairs, {kept} quartets in {dt:.1f}s")
+    what = "every bra shell pair" if stride == 1 else f"every {stride}-th bra shell pair (index 0, {stride}, ...)"
     return {"value": kept / dt, "unit": "screened quartets/s", "cores": ncores, "kind": "oracle",
-            "sample": f"unique quartets of every {stride}-th bra shell pair ({kept} kept quartets, {dt:.1f} s, "
+            "sample": f"unique quartets of {what} of the headline molecule ({kept} kept quartets, {dt:.1f} s, "
                       f"includes the oracle's own Schwarz/block-max setup)"}
 
 
-def _timed(fn, steps, warmup):
+def golden_cfg4():
+    """Oracle fixture of the 256-atom molecule (tests/golden/make_oracle_fixtures.py)."""
+    path = os.path.join(ROOT, "tests", "golden", "cfg4_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def _timed(fn, steps, warmup, check=None):
     import torch
     for _ in range(warmup):
         fn()
@@ -110,80 +122,166 @@ def _timed(fn, steps, warmup):
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t) * 1e3 / steps
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    if check is not None:
+        check()
+    return ms
 
 
 def _energy(D, J, K):
     return float((D * (J - 0.5 * K)).sum())
 
 
-def mixed_extra(steps=2, warmup=1):
-    """256-atom clustered 3s2p1d molecule: FP64 build vs mixed build (FP32 below 1e-6)."""
+def kernel_name(e):
+    if e["team"] == 2:
+        return "k_bra<%d,%d,%d>" % (e["la"], e["lb"], e["ld"])
+    if e["team"] == 3:
+        return "k_bra32<%d,%d,%d>" % (e["la"], e["lb"], e["ld"])
+    return "k_cls<%d,%d,%d,%d>" % (e["la"], e["lb"], e["lc"], e["ld"])
+
+
+def class_name(e):
+    if e["lc"] < 0:
+        return "(%d%d|**) tier %d%s" % (e["la"], e["lb"], e["ld"], " FP32" if e["team"] == 3 else "")
+    return "(%d%d|%d%d)" % (e["la"], e["lb"], e["lc"], e["ld"])
+
+
+def launch_table(prof):
+    """Per-launch entries of a profile: time, algorithmic TFLOP/s, fraction of the FP64 peak."""
+    rows = []
+    for e in prof:
+        if e["kind"] != 0:
+            continue
+        tf = e["flops"] / (e["ms"] * 1e-3) / 1e12 if e["ms"] > 0 else 0.0
+        rows.append({"class": class_name(e), "kernel": kernel_name(e), "ms": round(e["ms"], 4),
+                     "quartets": e["quartets"], "tflops": round(tf, 3), "frac": round(tf / PEAK_FP64_TFLOPS, 4),
+                     "flops": e["flops"]})
+    rows.sort(key=lambda r: -r["ms"])
+    return rows
+
+
+def run_config(mol, steps, warmup, precision=None, profile=True):
+    """Times `steps` builds of one molecule after `warmup` (HIP events recorded inside each build
+    when profile is set; read after the timed loop, averaged over its builds)."""
     import torch
-    from paper_2407_09700_amd import jk, synth
-    mol = synth.make_config(4)
+    from paper_2407_09700_amd import jk
+    prec = jk.JK_FP64 if precision is None else precision
+    t0 = time.perf_counter()
+    plan = jk.Plan.from_molecule(mol, profile=profile, precision=prec, fp32_cutoff=1e-6)
     D = torch.from_numpy(mol.D).cuda()
-    out = {"workload": f"cfg4: {mol.natom}-atom clustered 3s2p1d, {mol.nbf} AOs, tau {mol.thresh:g}, "
-                       f"FP32 below bound 1e-6"}
-    res = {}
-    for name, prec in (("fp64", jk.JK_FP64), ("mixed", jk.JK_MIXED)):
-        plan = jk.Plan.from_molecule(mol, precision=prec, fp32_cutoff=1e-6)
-        J = torch.empty_like(D)
-        K = torch.empty_like(D)
-        ms = _timed(lambda: plan.execute(D, J, K), steps, warmup)
-        st = plan.stats()
-        res[name] = (ms, _energy(D, J, K), st)
-        plan.close()
-        log(f"cfg4 {name}: {ms:.1f} ms kept {st['kept_quartets']} fp32 {st['kept_fp32']}")
-    out.update({"fp64_ms": res["fp64"][0], "mixed_ms": res["mixed"][0],
-                "speedup": res["fp64"][0] / res["mixed"][0],
-                "fp32_fraction": res["mixed"][2]["kept_fp32"] / max(1, res["mixed"][2]["kept_quartets"]),
-                "kept_quartets": res["fp64"][2]["kept_quartets"],
-                "E_fp64": res["fp64"][1], "dE_mixed_vs_fp64": abs(res["mixed"][1] - res["fp64"][1])})
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+    plan.execute(D, J, K)                          # sizes the work lists (one wait), not timed
+    plan.check()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    for w in range(warmup):
+        plan.execute(D, J, K)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile()                             # drop the warm-up events
+    t = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(D, J, K)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    plan.check()
+    prof = plan.profile() if profile else []
+    st = plan.stats()
+    E = _energy(D, J, K)
+    plan.close()
+    return {"ms": ms, "plan_ms": plan_ms, "stats": st, "E": E, "prof": prof}
+
+
+def roofline_of(prof):
+    rows = launch_table(prof)
+    dom = rows[0]
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": dom["kernel"], "class": dom["class"], "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": measured_traffic(dom["kernel"]), "kernel_ms": dom["ms"]}
+
+
+def breakdown_of(prof, steps_note=""):
+    rows = launch_table(prof)
+    class_ms = sum(r["ms"] for r in rows)
+    flops = sum(r["flops"] for r in rows)
+    prep = sum(e["ms"] for e in prof if e["kind"] == 1)
+    fin = sum(e["ms"] for e in prof if e["kind"] == 2)
+    top = [{k: v for k, v in r.items() if k != "flops"} for r in rows[:10]]
+    return {"prep_ms": prep, "class_kernels_ms": class_ms, "finalize_ms": fin,
+            "all_classes_tflops": flops / (class_ms * 1e-3) / 1e12 if class_ms > 0 else 0.0,
+            "all_classes_frac": flops / (class_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS if class_ms > 0 else 0.0,
+            "top_launches": top}
+
+
+def mixed_extra(mol, fp64, steps=3):
+    """FP64 build vs mixed build (FP32 below a bound of 1e-6) of the same molecule; energies
+    against the oracle's FP64 build when its fixture is present."""
+    from paper_2407_09700_amd import jk
+    r = run_config(mol, steps, 1, precision=jk.JK_MIXED, profile=False)
+    st = r["stats"]
+    out = {"workload": f"{mol.natom}-atom clustered 3s2p1d, {mol.nbf} AOs, tau {mol.thresh:g}, FP32 below bound 1e-6",
+           "fp64_ms": fp64["ms"], "mixed_ms": r["ms"], "speedup": fp64["ms"] / r["ms"],
+           "fp32_fraction": st["kept_fp32"] / max(1, st["kept_quartets"]), "kept_quartets": st["kept_quartets"],
+           "E_fp64": fp64["E"], "E_mixed": r["E"], "dE_mixed_vs_fp64_gpu": abs(r["E"] - fp64["E"])}
+    g = golden_cfg4()
+    if g is not None and mol.nbf == 3584:
+        out["E_oracle"] = g["E"]
+        out["dE_fp64_vs_oracle"] = abs(fp64["E"] - g["E"])
+        out["dE_mixed_vs_oracle"] = abs(r["E"] - g["E"])
+        out["kept_matches_oracle"] = st["kept_quartets"] == g["kept_quartets"]
+    log(f"mixed: {r['ms']:.1f} ms vs FP64 {fp64['ms']:.1f} ms, fp32 {st['kept_fp32']} of {st['kept_quartets']}")
     return out
 
 
 def batched_extra(steps=1, warmup=1):
-    """64 molecules of 10-120 atoms (3s2p1d1f): one batched graph-replayed build (FP64 and
+    """64 molecules of 10-120 atoms (3s2p1d1f): one batched graph-launched build (FP64 and
     mixed) vs 64 sequential single-molecule FP64 builds."""
     import torch
     from paper_2407_09700_amd import jk, synth
     mols = synth.make_batch()
-    out = {"workload": f"cfg5: {len(mols)} molecules, {sum(m.natom for m in mols)} atoms, "
+    out = {"workload": f"64 molecules, {sum(m.natom for m in mols)} atoms, "
                        f"{sum(m.nbf for m in mols)} AOs, 3s2p1d1f, tau 1e-12"}
     t = time.perf_counter()
     plans = [jk.Plan.from_molecule(m) for m in mols]
     Ds = [torch.from_numpy(m.D).cuda() for m in mols]
     Js = [torch.empty_like(d) for d in Ds]
     Ks = [torch.empty_like(d) for d in Ds]
-    log(f"cfg5 sequential plans in {time.perf_counter() - t:.1f}s")
+    for p, d, j, k in zip(plans, Ds, Js, Ks):      # sizes every plan's lists (one wait each), not timed
+        p.execute(d, j, k)
+    log(f"batch: sequential plans in {time.perf_counter() - t:.1f}s")
 
     def seq():
         for p, d, j, k in zip(plans, Ds, Js, Ks):
             p.execute(d, j, k)
-    seq_ms = _timed(seq, steps, warmup)
+
+    def seq_check():
+        for p in plans:
+            p.check()
+    seq_ms = _timed(seq, steps, warmup, seq_check)
     kept = sum(p.stats()["kept_quartets"] for p in plans)
     E_seq = sum(_energy(d, j, k) for d, j, k in zip(Ds, Js, Ks))
     for p in plans:
         p.close()
     out["sequential_fp64_ms"] = seq_ms
     out["kept_quartets"] = kept
-    log(f"cfg5 sequential: {seq_ms:.1f} ms, {kept} quartets")
+    log(f"batch: sequential {seq_ms:.1f} ms, {kept} quartets")
     import tempfile
-    cache = os.path.join(tempfile.gettempdir(), f"jk_tune_cfg5_{os.getpid()}.txt")   # FP64 tunes, mixed reuses
+    cache = os.path.join(tempfile.gettempdir(), f"jk_tune_batch_{os.getpid()}.txt")   # FP64 tunes, mixed reuses
     for name, prec in (("fp64", jk.JK_FP64), ("mixed", jk.JK_MIXED)):
         t = time.perf_counter()
         b = jk.Batch(mols, precision=prec, graph=True, tune=True, tune_cache=cache)
         D = b.pack([m.D for m in mols])
         J = torch.empty_like(D)
         K = torch.empty_like(D)
-        ms = _timed(lambda: b.execute(D, J, K), steps, warmup + 1)   # +1: the first execute records the graph
+        b.execute(D, J, K)                         # sizes, tunes, records the graph: not timed
+        b.check()
+        ms = _timed(lambda: b.execute(D, J, K), steps, warmup, b.check)
         E = _energy(D, J, K)
         info = b.graph_info()
         st = b.stats()
         b.close()
-        log(f"cfg5 batched {name}: {ms:.1f} ms (setup {time.perf_counter() - t:.1f}s) graph {info} "
-            f"fp32 {st['kept_fp32']}")
+        log(f"batch {name}: {ms:.1f} ms (setup {time.perf_counter() - t:.1f}s) graph {info} fp32 {st['kept_fp32']}")
         out[f"batched_{name}_ms"] = ms
         out[f"batched_{name}_speedup_vs_sequential"] = seq_ms / ms
         out[f"dE_batched_{name}_vs_sequential"] = abs(E - E_seq)
@@ -191,9 +289,18 @@ def batched_extra(steps=1, warmup=1):
     if os.path.exists(cache):
         w = open(cache).read().split()
         out["tuned_grids"] = {w[i]: int(w[i + 1]) for i in range(0, len(w) - 1, 2)}
-    if os.path.exists(cache):
         os.remove(cache)
     return out
+
+
+def config_extra(mol, steps, warmup, label):
+    r = run_config(mol, steps, warmup)
+    st = r["stats"]
+    b = breakdown_of(r["prof"])
+    log(f"{label}: {r['ms']:.1f} ms, {st['kept_quartets']} quartets, all launches {b['all_classes_tflops']:.2f} TF")
+    return {"workload": label, "build_ms": r["ms"], "steps": steps, "kept_quartets": st["kept_quartets"],
+            "quartets_per_s": st["kept_quartets"] / (r["ms"] * 1e-3), "E": r["E"], "roofline": roofline_of(r["prof"]),
+            "breakdown": b}
 
 
 def main():
@@ -203,8 +310,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--natom", type=int, default=None, help="smaller molecule of the same recipe (debug)")
-    ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and batched measurements")
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision, g-function, 64-atom and batched measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -216,93 +324,35 @@ def main():
               f"would shard by bra-pair tiles with one all-reduce of J and K, which is not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-    from paper_2407_09700_amd import jk, synth
+    from paper_2407_09700_amd import synth
 
     mol = synth.make_config(args.config, natom=args.natom)
     log(f"workload: config {args.config}, natom {mol.natom}, nao {mol.nbf}, nshell {mol.nshell}, tau {mol.thresh}")
-    t0 = time.perf_counter()
-    plan = jk.Plan.from_molecule(mol, profile=True)
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    D = torch.from_numpy(mol.D).cuda()
-    J = torch.empty_like(D)
-    K = torch.empty_like(D)
-    stream = torch.cuda.current_stream()
-
-    for w in range(args.warmup):
-        plan.execute(D, J, K)
-        torch.cuda.synchronize()
-        log(f"warmup {w} done")
-
-    per_class = {}
-    prep_ms = fin_ms = 0.0
-    t = time.perf_counter()
-    for k in range(args.steps):
-        plan.execute(D, J, K)
-        if args.steps <= 3:
-            log(f"step {k} enqueued")
-        for e in plan.profile():          # HIP events recorded on this stream inside the step
-            if e["kind"] == 1:
-                prep_ms += e["ms"]
-            elif e["kind"] == 2:
-                fin_ms += e["ms"]
-            else:
-                key = (e["la"], e["lb"], e["lc"], e["ld"], e["team"])
-                acc = per_class.setdefault(key, dict(ms=0.0, flops=0.0, quartets=0, prim=0, team=e["team"]))
-                acc["ms"] += e["ms"]
-                acc["flops"] += e["flops"]
-                acc["quartets"] += e["quartets"]
-                acc["prim"] += e["prim_quartets"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t
-    ms_per_step = elapsed * 1e3 / args.steps
-    st = plan.stats()
+    r = run_config(mol, args.steps, args.warmup)
+    ms_per_step = r["ms"]
+    st = r["stats"]
     kept = st["kept_quartets"]
-    value = kept / (ms_per_step / 1e3)
-
-    # dominant kernel: the class launch with the largest total time
-    dom_key, dom = max(per_class.items(), key=lambda kv: kv[1]["ms"])
-    dom_ms = dom["ms"] / args.steps
-    achieved = dom["flops"] / args.steps / (dom_ms * 1e-3) / 1e12
-    tot_flops = sum(v["flops"] for v in per_class.values()) / args.steps
-    class_ms = sum(v["ms"] for v in per_class.values()) / args.steps
-    top = sorted(per_class.items(), key=lambda kv: -kv[1]["ms"])[:8]
-    def cname(k):
-        if k[2] < 0:
-            return "(%d%d|**) tier %d%s" % (k[0], k[1], k[3], " FP32" if k[4] == 3 else "")
-        return "(%d%d|%d%d)" % k[:4]
-
-    def kname(k, v):
-        if v["team"] == 2:
-            return "k_bra<%d,%d,%d>" % (k[0], k[1], k[3])
-        if v["team"] == 3:
-            return "k_bra32<%d,%d,%d>" % (k[0], k[1], k[3])
-        return "k_cls<%d,%d,%d,%d>" % k[:4] + (" team" if v["team"] else " lane")
-
-    classes = [{"class": cname(k), "kernel": kname(k, v),
-                "ms": round(v["ms"] / args.steps, 4), "quartets": v["quartets"] // args.steps,
-                "tflops": round(v["flops"] / v["ms"] * 1e-9, 3) if v["ms"] > 0 else 0.0} for k, v in top]
-
     out = {
-        "metric": METRIC, "value": value, "unit": "screened quartets/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded)",
-        "config": {"workload": f"cfg{args.config}: {mol.natom} atoms, {WORKLOAD_BASIS.get(args.config, '')}, "
-                               f"{mol.nbf} AOs, Schwarz tau {mol.thresh:g}, FP64",
+        "metric": METRIC, "value": kept / (ms_per_step / 1e3), "unit": "screened quartets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded)",
+        "config": {"workload": f"{mol.natom} atoms, {WORKLOAD_BASIS.get(args.config, '')}, "
+                               f"{mol.nbf} AOs, Schwarz tau {mol.thresh:g}, FP64 J+K build",
                    "natom": mol.natom, "nao": mol.nbf, "nshell": mol.nshell, "tau": mol.thresh,
-                   "kept_quartets": kept, "prim_quartets": st["prim_quartets"], "plan_ms": round(plan_ms, 2)},
-        "roofline": {"bound": "alu", "kernel": kname(dom_key, dom),
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kname(dom_key, dom)),
-                     "kernel_ms": dom_ms},
-        "breakdown": {"prep_ms": prep_ms / args.steps, "class_kernels_ms": class_ms,
-                      "finalize_ms": fin_ms / args.steps, "all_classes_tflops": tot_flops / (class_ms * 1e-3) / 1e12,
-                      "top_classes": classes},
+                   "kept_quartets": kept, "prim_quartets": st["prim_quartets"],
+                   "plan_and_first_build_ms": round(r["plan_ms"], 2)},
+        "roofline": roofline_of(r["prof"]),
+        "breakdown": breakdown_of(r["prof"]),
     }
-    plan.close()
+    log(f"headline: {ms_per_step:.1f} ms per build, {out['value']:.3e} quartets/s, dominant "
+        f"{out['roofline']['kernel']} frac {out['roofline']['frac']:.3f}")
     if not args.no_extras and args.natom is None:
-        out["mixed"] = mixed_extra()
+        if args.config == 4:
+            out["mixed"] = mixed_extra(mol, r)
+        out["g_functions"] = config_extra(synth.make_config(3), 1, 1,
+                                          "32 atoms, uniform cube, 4s3p2d1f1g spherical, 1248 AOs, tau 1e-12, FP64")
+        out["cfg_64_atoms"] = config_extra(synth.make_config(2), 10, 2,
+                                           "64 atoms, 3-atom clusters, 3s2p1d (spherical d), 896 AOs, tau 1e-12, FP64")
         out["batched"] = batched_extra()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mol)

@@ -47,6 +47,7 @@ extern "C" {
 #define JK_ENOMEM (-3)        /* host or device allocation failed */
 #define JK_EDEVICE (-4)       /* a HIP call failed; the message carries its string */
 #define JK_ENODEV (-5)        /* no HIP device */
+#define JK_EOVERFLOW (-6)     /* jk_plan_check: the last build's work lists overflowed (see there) */
 
 #define JK_FP64 0
 #define JK_MIXED 1
@@ -56,6 +57,12 @@ extern "C" {
                                  execute and replay it afterwards (no host round trip inside) */
 #define JK_FLAG_TUNE 4        /* jk_opts_t.flags: pick the workgroup count of every integral
                                  launch by timing candidates on the first execute */
+#define JK_FLAG_J_ONLY 8      /* jk_opts_t.flags: build J only (K is not written and may be NULL);
+                                 the density-weighted screen takes the two Coulomb blocks D[a,b],
+                                 D[c,d] only */
+#define JK_FLAG_K_ONLY 16     /* jk_opts_t.flags: build K only (J is not written and may be NULL);
+                                 the screen takes the four exchange blocks D[a,c], D[a,d], D[b,c],
+                                 D[b,d] only */
 
 typedef struct {
   int nshell;
@@ -79,6 +86,11 @@ typedef struct {
   int flags;             /* OR of JK_FLAG_* (0: none) */
   const char *tune_cache; /* JK_FLAG_TUNE: HOST path of a text file that keeps the choices
                              between runs (read if present, written after tuning); NULL: none */
+  double dmax;           /* > 0: jk_plan_create sizes the screened work lists for densities whose
+                            largest element in the Cartesian components is at most dmax, so that
+                            no execute waits for the device. 0 (default): the first execute
+                            sizes them for twice its own density's largest element, waiting once
+                            for the device; later executes never wait */
 } jk_opts_t;
 
 typedef struct jk_plan jk_plan_t;
@@ -92,6 +104,8 @@ typedef struct {
   int npairs_kept;              /* shell pairs with I_ab > tau */
   int nao, nao_cart, nshell;
   double plan_ms;               /* host wall time of jk_plan_create */
+  int overflow;                 /* 1 if the last execute's work lists overflowed (jk_plan_check) */
+  long long list_capacity;      /* entries of the screened work lists */
 } jk_stats_t;
 
 /* Create a plan for one molecule: validates the basis on the host, builds the shell
@@ -102,14 +116,37 @@ typedef struct {
 int jk_plan_create(const jk_basis_t *basis, const double *coords, int natom, const jk_opts_t *opts,
                    jk_plan_t **out);
 
-/* J and K for the density D (DEVICE, nao x nao, symmetric, caller-owned). J and K are
- * OVERWRITTEN (DEVICE, nao x nao). Work is enqueued on `stream` (a hipStream_t, NULL =
- * default stream); results are valid after the stream synchronises. One small
- * device-to-host read of the density maximum sizes the screened work lists, so the
- * call blocks until the screen has run. A plan must not be executed concurrently. */
+/* J and K for the density D (DEVICE, nao x nao, symmetric, caller-owned): the Coulomb and
+ * exchange sums of section 3 (Algorithms 2 and 3: ERIs of the kept shell quartets evaluated
+ * and digested with D in the same pass). J and K are OVERWRITTEN (DEVICE, nao x nao; with
+ * JK_FLAG_J_ONLY / JK_FLAG_K_ONLY the other may be NULL). Asynchronous: the build is
+ * enqueued on `stream` (a hipStream_t, NULL = default stream) and the call returns without
+ * waiting for it, except on a plan's first execute when the plan was created with dmax = 0
+ * (that one call sizes the work lists from D and waits for the device once). Results are
+ * valid after the stream synchronises. A density whose density-weighted screen keeps more
+ * candidates than the lists hold leaves J and K incomplete; jk_plan_check reports this.
+ * A plan must not be executed concurrently on two streams. */
 int jk_plan_execute(jk_plan_t *plan, const double *D, double *J, double *K, void *stream);
 
-/* jk_plan_create + jk_plan_execute + jk_plan_destroy; thresh overrides opts->thresh. */
+/* Waits for the plan's last execute and returns JK_OK, or JK_EOVERFLOW if its work lists
+ * overflowed (its J and K are then incomplete). On JK_EOVERFLOW the plan has already grown
+ * its lists (for twice that density's largest element) and a new execute with the same
+ * density completes. */
+int jk_plan_check(jk_plan_t *plan);
+
+/* Nuclear gradient of the two-electron energy E = tr(D (J - K/2)) with the density held fixed
+ * (section 4, Algorithm 4: derivative integrals of each kept quartet, from the raised and
+ * lowered primitive Gaussians of the differentiated centre in the Rys form of section 2,
+ * contracted with W = s [8 D_ab D_cd - 2 D_ac D_bd - 2 D_ad D_bc] at once; the fourth centre
+ * by translational invariance). D: DEVICE nao x nao, symmetric. grad: DEVICE natom x 3
+ * doubles (atoms as given to jk_plan_create), OVERWRITTEN. The quartets are those the J/K
+ * screen keeps for D (six density blocks). Single-molecule plans made for J and K, shells up
+ * to l = 2 (else JK_EUNSUPPORTED / JK_EINVAL). Asynchronous as jk_plan_execute; jk_plan_check
+ * reports an overflow of the work lists the same way. */
+int jk_grad(jk_plan_t *plan, const double *D, double *grad, void *stream);
+
+/* jk_plan_create + jk_plan_execute + jk_plan_check (executing again after an overflow) +
+ * jk_plan_destroy; thresh overrides opts->thresh. Waits for the build. */
 int jk_build(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh,
              double *J, double *K, const jk_opts_t *opts, void *stream);
 
@@ -121,18 +158,20 @@ int jk_plan_sizes(const jk_plan_t *plan, int *nao, int *nao_cart);
 /* Statistics of the plan and its last execute (HOST struct). */
 int jk_stats(const jk_plan_t *plan, jk_stats_t *out);
 
-/* Per-launch profile of the last jk_plan_execute of a plan created with JK_FLAG_PROFILE.
- * One entry per integral launch (kind 0): either one quartet class (lc, ld >= 0) or one
- * register tier of a bra class fused over its ket classes (lc = -1, ld = tier, team = 2),
- * plus the preparation launches (kind 1: density transform, block maxima, screening) and
- * the final symmetrise and transform (kind 2). ms is the HIP-event time of the launch on the
- * caller's stream. flops is the algorithmic operation count of the launch's quartets (an FMA
- * counts 2), from the steps of the method: per primitive quartet the pair-quartet scalars,
- * and per Rys root (section 2) the root and weight, the recurrence coefficients, the 2D
- * recurrences in x, y, z and the three-operand product per [e0|f0] element; per contracted
- * quartet the two transfers and the six multiply-adds per integral of the digestion
- * (Algorithm 2). out is HOST memory of max_entries entries; *n_entries receives the count.
- * Synchronises the plan's last stream. Graph replays are not profiled. */
+/* Per-launch profile of the executes of a plan created with JK_FLAG_PROFILE, averaged over
+ * the executes since the previous jk_profile call (at most the last 32). One entry per
+ * integral launch (kind 0): either one quartet class (lc, ld >= 0) or one register tier of a
+ * bra class fused over its ket classes (lc = -1, ld = tier, team = 2), plus the preparation
+ * launches (kind 1: density transform, block maxima, screening) and the final symmetrise and
+ * transform (kind 2). ms is the mean HIP-event time of the launch on the caller's stream (the
+ * events are recorded inside each execute; reading them here waits for the stream). quartets,
+ * prim_quartets and flops are those of the last execute. flops is the algorithmic operation
+ * count of the launch's quartets (an FMA counts 2), from the steps of the method: per
+ * primitive quartet the pair-quartet scalars, and per Rys root (section 2) the root and
+ * weight, the recurrence coefficients, the 2D recurrences in x, y, z and the three-operand
+ * product per [e0|f0] element; per contracted quartet the two transfers and the multiply-adds
+ * of the digestion (Algorithm 2: two per integral for J, four for K). out is HOST memory of
+ * max_entries entries; *n_entries receives the count. Graph launches are not profiled. */
 typedef struct {
   int kind;                     /* 0 class kernel, 1 preparation, 2 finalisation */
   int la, lb, lc, ld;           /* class (kind 0); lc = -1, ld = tier for a fused launch */
@@ -179,9 +218,10 @@ int jk_rys_grid(int nroots, double T, double *u, double *w);
  * batching of shell quartets (section 3) across molecules. */
 
 /* Create a batch of nmol molecules: basis[m], coords[m] (HOST, natom[m] x 3) as for
- * jk_plan_create. opts (may be NULL) applies to every molecule. With JK_FLAG_GRAPH the
- * first execute runs eagerly, then records the whole build (density transform, screen,
- * integral launches, finalisation) in a HIP graph that later executes replay. */
+ * jk_plan_create. opts (may be NULL) applies to every molecule. With JK_FLAG_GRAPH an
+ * execute records the whole build (density transform, screen, integral launches,
+ * finalisation) in a HIP graph and launches it; later executes with the same D, J, K
+ * pointers launch the recorded graph again. (JK_FLAG_GRAPH acts the same way on a plan.) */
 int jk_batch_create(int nmol, const jk_basis_t *const *basis, const double *const *coords, const int *natom,
                     const jk_opts_t *opts, jk_batch_t **out);
 
@@ -191,19 +231,21 @@ int jk_batch_create(int nmol, const jk_basis_t *const *basis, const double *cons
 int jk_batch_offsets(const jk_batch_t *batch, long long *off, int *nao);
 
 /* J and K of every molecule (DEVICE, packed as jk_batch_offsets says, overwritten) for the
- * packed densities D (DEVICE). Work is enqueued on `stream`. Without JK_FLAG_GRAPH this
- * behaves as jk_plan_execute (one mid-build read of the work-list sizes). With it, a replay
- * runs with the work-list capacity fixed at recording time (the first execute's need plus
- * headroom); the call then waits for the stream and checks a device flag: if a density
- * needed more room, the build is redone eagerly with larger lists and the graph is
- * recorded again, so the outputs are always complete when the call returns. */
+ * packed densities D (DEVICE). Asynchronous on `stream`, as jk_plan_execute (including the
+ * one wait of a first execute with dmax = 0, and the overflow report of jk_batch_check).
+ * Graph launches wait for nothing either. */
 int jk_batch_execute(jk_batch_t *batch, const double *D, double *J, double *K, void *stream);
+
+/* jk_plan_check for a batch: waits for its last execute; JK_EOVERFLOW if that build's work
+ * lists overflowed (the lists have grown, a graph is recorded again on the next execute). */
+int jk_batch_check(jk_batch_t *batch);
 
 /* Statistics of the batch and its last execute, summed over the molecules. */
 int jk_batch_stats(const jk_batch_t *batch, jk_stats_t *out);
 
-/* Graph status: *recorded = 1 once a graph exists, *replays = executes served by it,
- * *rerecords = times a capacity overflow forced a new recording. HOST ints, may be NULL. */
+/* Graph status: *recorded = 1 once a graph exists, *replays = executes that launched an
+ * already recorded graph, *rerecords = recordings after the first (grown work lists or new
+ * D, J, K pointers). HOST ints, may be NULL. */
 int jk_batch_graph_info(const jk_batch_t *batch, int *recorded, long long *replays, int *rerecords);
 
 void jk_batch_destroy(jk_batch_t *batch);

@@ -15,6 +15,7 @@
 #include "../../include/jk.h"
 #include "jk_aux.h"
 #include "jk_classes.h"
+#include "jk_grad.h"
 #include "jk_kernels.h"
 
 using namespace jk;
@@ -44,6 +45,7 @@ int fail(int code, const char *fmt, ...) {
 
 ClassInfo g_classes[NQCLASS];
 BraInfo g_bras[NPAIRCLASS];
+grad_launch_fn g_grad[NQCLASS];
 bool g_classes_ready = false;
 
 void ensure_classes() {
@@ -53,6 +55,7 @@ void ensure_classes() {
   register_bra_30(g_classes, g_bras); register_bra_31(g_classes, g_bras); register_bra_32(g_classes, g_bras);
   register_bra_33(g_classes, g_bras); register_bra_40(g_classes, g_bras); register_bra_41(g_classes, g_bras);
   register_bra_42(g_classes, g_bras); register_bra_43(g_classes, g_bras); register_bra_44(g_classes, g_bras);
+  register_grad(g_grad);
   g_classes_ready = true;
 }
 
@@ -120,7 +123,8 @@ void solid_harmonics(int l, double *T) {
 //                          three directions, and the Rys product over the [e0|f0] elements
 //                          (one multiply and one FMA = 3 per element, the paper's count);
 //  per contracted quartet: the two binomial transfers and the digestion (six FMAs per
-//                          integral, Algorithm 2).
+//                          integral, Algorithm 2: two for J, four for K, so a J-only or
+//                          K-only build counts only its own).
 double vrr_ops(int E, int F) {
   double n = E > 0 ? 1 : 0;                                  // G[1][0]
   for (int e = 1; e < E; ++e) n += (e > 1 ? 1 : 0) + 1 + 2;  // e*b10, *G, fma
@@ -146,14 +150,15 @@ int transfer_terms(int l) {
   return n;
 }
 
-void class_ops(int la, int lb, int lc, int ld, double *per_prim, double *per_quartet) {
+void class_ops(int la, int lb, int lc, int ld, int want, double *per_prim, double *per_quartet) {
   const int E = la + lb, F = lc + ld, N = (E + F) / 2 + 1;
   const int NE = range_count_h(la, E), NF = range_count_h(lc, F);
   const int na = ncart(la), nb = ncart(lb), nc = ncart(lc), nd = ncart(ld);
   *per_prim = 24.0 + N * (44.0 + 14.0 + 3.0 * vrr_ops(E, F) + 3.0 * NE * NF);
   const double bra = (double)na * transfer_terms(lb) * (3.0 + 2.0 * NF);
   const double ket = (double)nc * transfer_terms(ld) * (3.0 + 2.0 * na * nb);
-  *per_quartet = bra + ket + 12.0 * na * nb * nc * nd;
+  const double digest = (want & 1 ? 4.0 : 0.0) + (want & 2 ? 8.0 : 0.0);   // two J and four K FMAs per integral
+  *per_quartet = bra + ket + digest * na * nb * nc * nd;
 }
 
 template <class T>
@@ -196,6 +201,7 @@ struct jk_plan {
   std::vector<int> sbase, cbase, abase;          // [nmol+1] first shell / Cartesian AO / AO of each molecule
   std::vector<long long> mc_off, mf_off, ps_off; // [nmol+1] first element of each molecule's nc^2 / nao^2 / ns^2 block
   std::vector<int> mnc;                          // [nmol] Cartesian AO count of each molecule
+  std::vector<int> lseg;                         // [nmol * 6] start of each momentum's columns in the molecule's lcols
   // Molecules are kept in ascending Cartesian size (so that, inside a pair class, the pairs
   // of the molecules whose exchange rows fit in LDS come first); perm[i] is the caller's
   // index of molecule i, user_off/user_nao describe the caller's packed D, J, K.
@@ -216,6 +222,10 @@ struct jk_plan {
   int *d_l = nullptr, *d_pure = nullptr, *d_cart_off = nullptr, *d_ao_off = nullptr;
   int *d_cart2shell = nullptr, *d_ao2shell = nullptr;
   int *d_sbase = nullptr, *d_cbase = nullptr, *d_abase = nullptr, *d_mnc = nullptr;
+  int *d_lcol = nullptr, *d_lcols = nullptr, *d_lseg = nullptr;   // compacted exchange rows (JKArgs)
+  double *d_ppab = nullptr;            // exponents of the two primitives of every primitive pair
+  int *d_shell_atom = nullptr;         // per shell: its atom (nuclear gradient)
+  int natom = 0, lmax = 0;
   long long *d_mc_off = nullptr, *d_mf_off = nullptr, *d_ps_off = nullptr, *d_mf_user = nullptr;
   double *d_tsph = nullptr;
   double *d_Dc = nullptr, *d_Jc = nullptr, *d_Kc = nullptr, *d_Pblk = nullptr, *d_gmax = nullptr;
@@ -230,12 +240,22 @@ struct jk_plan {
   std::vector<int> slice, units_est;   // per launch slot: kets per unit, expected units (last eager build)
   long long *d_class_off = nullptr, *d_jp_off = nullptr, *d_room = nullptr;
   int *d_overflow = nullptr;
-  int *h_overflow = nullptr;                     // pinned host copy of the overflow flag
+  // work-list sizing: class regions are laid out once (plan creation with a density bound, or
+  // the first execute) and grow only when a build reports an overflow
+  double dmax = 0.0;
+  bool sized = false;
+  std::vector<long long> capc, class_off_h;      // [120] capacity and first entry of each class region
+  long long *d_capc = nullptr;
+  bool active[NQCLASS] = {};                     // classes launched by every build (capacity > 0)
+  long long overflows = 0;                       // builds reported incomplete by jk_plan_check
   double *d_Jpair = nullptr;
   long long jp_total = 0;
   std::vector<long long> jp_off;                 // [15]
   hipStream_t last_stream = nullptr;
-  std::vector<hipEvent_t> events;      // 2 per launch slot (15 x 3 fused + 120 per class) + prep + tail
+  // profile events: EV_SETS sets of 2 per launch slot + prep + tail; execute n records into set
+  // n mod EV_SETS, jk_profile averages the sets recorded since its last call
+  std::vector<hipEvent_t> events;
+  int ev_next = 0, ev_count = 0;
   std::vector<int> launched;           // launch slots used by the last eager execute
   std::vector<int> grid;               // per launch slot: workgroups (0 = default)
   bool tuned = false;
@@ -274,8 +294,6 @@ void plan_free(jk_plan *p) {
   graph_free(p);
   if (p->rec_stream) (void)hipStreamDestroy(p->rec_stream);
   p->rec_stream = nullptr;
-  if (p->h_overflow) (void)hipHostFree(p->h_overflow);
-  p->h_overflow = nullptr;
   dfree(p->d_pairs); dfree(p->d_pp); dfree(p->d_pairI); dfree(p->d_pair_cls); dfree(p->d_pair_sa);
   dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_pair_mol); dfree(p->d_bin_beg); dfree(p->d_cm_bin); dfree(p->d_l);
   dfree(p->d_pure); dfree(p->d_cart_off); dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell);
@@ -285,17 +303,25 @@ void plan_free(jk_plan *p) {
   dfree(p->d_kets); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
   dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
   dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair);
-  dfree(p->d_room); dfree(p->d_overflow); dfree(p->d_units); dfree(p->d_nunits); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
+  dfree(p->d_room); dfree(p->d_overflow); dfree(p->d_capc);
+  dfree(p->d_lcol); dfree(p->d_lcols); dfree(p->d_lseg); dfree(p->d_ppab); dfree(p->d_shell_atom); dfree(p->d_units); dfree(p->d_nunits); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
 }
 
+// per-class launches of the lane bodies keep the unit's exchange rows in LDS (compacted to the
+// ket class's momenta) when they fit; 0 sends every exchange update to global memory
+#ifndef JK_CLS_LDS_ROWS
+#define JK_CLS_LDS_ROWS 1
+#endif
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
 constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels (default)
 constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
 constexpr int NFUSED = NPAIRCLASS * NTIERS;     // launch slots of the fused kernels
 constexpr int NF32_BASE = NFUSED + NQCLASS;    // slots of the FP32-only fused launches (mixed precision)
 constexpr int NSLOT = NF32_BASE + NFUSED;
+constexpr int EV_PER_SET = 2 * NSLOT + 4;          // profile events of one execute
+constexpr int EV_SETS = 32;                        // executes a profile can average over
 const int TUNE_GRIDS[] = {256, 512, 1024, 2048};   // candidates of the grid tuner
 
 int ensure_scratch(jk_plan *p, long long doubles) {
@@ -318,7 +344,7 @@ constexpr double PRIM_EXP_CUT = 60.0;
 // order l_a >= l_b inside the pair). s0: first shell of the molecule in the batch; shell
 // indices of the records are batch-wide, Cartesian offsets are inside the molecule.
 void build_pairs(const jk_basis_t *B, const double *coords, const int *cart_off, int s0, int mol,
-                 std::vector<Pair> &pairs, std::vector<PrimPair> &pps) {
+                 std::vector<Pair> &pairs, std::vector<PrimPair> &pps, std::vector<double> &ppab) {
   const int ns = B->nshell;
   for (int i = 0; i < ns; ++i)
     for (int j = 0; j <= i; ++j) {
@@ -350,6 +376,8 @@ void build_pairs(const jk_basis_t *B, const double *coords, const int *cart_off,
           q.K = ca * cb * std::exp(-ea * eb / q.p * ab2);
           q.ip = 1.0 / q.p;
           pps.push_back(q);
+          ppab.push_back(ea);      // exponents of the two primitives (nuclear gradient)
+          ppab.push_back(eb);
         }
       P.npp = (int)pps.size() - P.pp_off;
       pairs.push_back(P);
@@ -412,13 +440,19 @@ int parse_opts(const jk_opts_t *opts, jk_plan *p) {
   p->precision = JK_FP64;
   p->fp32_cutoff = 1e-6;
   p->flags = 0;
+  p->dmax = 0.0;
   if (!opts) return JK_OK;
   if (!(opts->thresh >= 0.0) || !std::isfinite(opts->thresh)) return fail(JK_EINVAL, "thresh must be finite and >= 0");
   if (opts->precision != JK_FP64 && opts->precision != JK_MIXED)
     return fail(JK_EINVAL, "unknown precision %d", opts->precision);
   if (!(opts->fp32_cutoff >= 0.0) || !std::isfinite(opts->fp32_cutoff))
     return fail(JK_EINVAL, "fp32_cutoff must be finite and >= 0");
-  if (opts->flags & ~(JK_FLAG_PROFILE | JK_FLAG_GRAPH | JK_FLAG_TUNE)) return fail(JK_EINVAL, "unknown flags 0x%x", opts->flags);
+  if (opts->flags & ~(JK_FLAG_PROFILE | JK_FLAG_GRAPH | JK_FLAG_TUNE | JK_FLAG_J_ONLY | JK_FLAG_K_ONLY))
+    return fail(JK_EINVAL, "unknown flags 0x%x", opts->flags);
+  if ((opts->flags & JK_FLAG_J_ONLY) && (opts->flags & JK_FLAG_K_ONLY))
+    return fail(JK_EINVAL, "JK_FLAG_J_ONLY and JK_FLAG_K_ONLY exclude each other");
+  if (!(opts->dmax >= 0.0) || !std::isfinite(opts->dmax)) return fail(JK_EINVAL, "dmax must be finite and >= 0");
+  p->dmax = opts->dmax;
   p->tau = opts->thresh;
   p->precision = opts->precision;
   p->fp32_cutoff = opts->fp32_cutoff;
@@ -426,6 +460,8 @@ int parse_opts(const jk_opts_t *opts, jk_plan *p) {
   if (opts->tune_cache) p->tune_cache = opts->tune_cache;
   return JK_OK;
 }
+
+int size_lists(jk_plan *p, hipStream_t st, double gfix, double gscale);
 
 // Plan of nmol molecules (a single-molecule plan is the batch of one).
 int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *coords_in, const int *natom,
@@ -453,6 +489,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   p->precision = tmp.precision;
   p->fp32_cutoff = tmp.fp32_cutoff;
   p->flags = tmp.flags;
+  p->dmax = tmp.dmax;
   p->tune_cache = tmp.tune_cache;
   p->nmol = nmol;
   (void)hipGetDevice(&p->device);
@@ -491,6 +528,8 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   const double *const *coords = Cv.data();
 
   // per-molecule layout
+  std::vector<int> shell_atom;
+  p->natom = natom[p->perm[0]];
   p->sbase.assign(nmol + 1, 0); p->cbase.assign(nmol + 1, 0); p->abase.assign(nmol + 1, 0);
   p->mc_off.assign(nmol + 1, 0); p->mf_off.assign(nmol + 1, 0); p->ps_off.assign(nmol + 1, 0);
   p->mnc.assign(nmol, 0);
@@ -499,6 +538,8 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
     int nc = 0, na = 0;
     for (int s = 0; s < B->nshell; ++s) {
       const int l = B->l[s];
+      shell_atom.push_back(B->atom[s]);
+      p->lmax = std::max(p->lmax, l);
       p->l.push_back(l);
       p->pure.push_back(B->pure[s]);
       p->cart_off.push_back(nc);
@@ -528,7 +569,26 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
       for (int k = 0; k < ncart(l); ++k) c2s[p->cbase[m] + p->cart_off[s] + k] = s;
       for (int k = 0; k < nf; ++k) a2s[p->abase[m] + p->ao_off[s] + k] = s;
     }
+  // columns by momentum: per molecule, the Cartesian columns of its s shells, then p, ..., g
+  // shells (lcols), where each momentum starts (lseg), and each shell's first column inside
+  // its momentum's segment (lcol)
+  std::vector<int> lcol(ns), lcols(p->nc);
+  p->lseg.assign((size_t)nmol * 6, 0);
+  for (int m = 0; m < nmol; ++m) {
+    int *seg = p->lseg.data() + (size_t)m * 6;
+    int pos = 0;
+    for (int l = 0; l <= LMAX; ++l) {
+      seg[l] = pos;
+      for (int s = p->sbase[m]; s < p->sbase[m + 1]; ++s) {
+        if (p->l[s] != l) continue;
+        lcol[s] = pos - seg[l];
+        for (int k = 0; k < ncart(l); ++k) lcols[p->cbase[m] + pos++] = p->cart_off[s] + k;
+      }
+    }
+    seg[LMAX + 1] = pos;
+  }
   std::vector<double> tsph(5 * 6 + 7 * 10 + 9 * 15);
+
   solid_harmonics(2, tsph.data());
   solid_harmonics(3, tsph.data() + 30);
   solid_harmonics(4, tsph.data() + 100);
@@ -539,7 +599,9 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
       (rc = dupload(&p->d_cbase, p->cbase)) || (rc = dupload(&p->d_abase, p->abase)) ||
       (rc = dupload(&p->d_mnc, p->mnc)) || (rc = dupload(&p->d_mc_off, p->mc_off)) ||
       (rc = dupload(&p->d_mf_off, p->mf_off)) || (rc = dupload(&p->d_ps_off, p->ps_off)) ||
-      (rc = dupload(&p->d_mf_user, p->mf_user)))
+      (rc = dupload(&p->d_mf_user, p->mf_user)) || (rc = dupload(&p->d_lcol, lcol)) ||
+      (rc = dupload(&p->d_lcols, lcols)) || (rc = dupload(&p->d_lseg, p->lseg)) ||
+      (rc = dupload(&p->d_shell_atom, shell_atom)))
     return cleanup(rc);
   ShellInfo &S = p->S;
   S.l = p->d_l; S.pure = p->d_pure; S.cart_off = p->d_cart_off; S.ao_off = p->d_ao_off;
@@ -553,8 +615,9 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   // all shell pairs of every molecule
   std::vector<Pair> all;
   std::vector<PrimPair> pps;
+  std::vector<double> ppab;
   for (int m = 0; m < nmol; ++m)
-    build_pairs(Bs[m], coords[m], p->cart_off.data() + p->sbase[m], p->sbase[m], m, all, pps);
+    build_pairs(Bs[m], coords[m], p->cart_off.data() + p->sbase[m], p->sbase[m], m, all, pps, ppab);
   const int nall = (int)all.size();
   if (pps.size() > 0x7fffffffULL) return cleanup(fail(JK_EUNSUPPORTED, "more than 2^31 primitive pairs"));
   if ((rc = dupload(&p->d_pairs, all)) || (rc = dupload(&p->d_pp, pps))) return cleanup(rc);
@@ -637,6 +700,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   p->npairs = (int)order.size();
   std::vector<Pair> kept(p->npairs);
   std::vector<PrimPair> kpp;
+  std::vector<double> kppab;
   std::vector<double> kI(p->npairs);
   std::vector<int> kcls(p->npairs), ksa(p->npairs), ksb(p->npairs), knpp(p->npairs), kca(p->npairs),
       kcb(p->npairs), kla(p->npairs), klb(p->npairs), kmol(p->npairs);
@@ -646,7 +710,11 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   for (int k = 0; k < p->npairs; ++k) {
     Pair P = all[order[k]];
     const int off = (int)kpp.size();
-    for (int q = 0; q < P.npp; ++q) kpp.push_back(pps[P.pp_off + q]);
+    for (int q = 0; q < P.npp; ++q) {
+      kpp.push_back(pps[P.pp_off + q]);
+      kppab.push_back(ppab[2 * ((size_t)P.pp_off + q)]);
+      kppab.push_back(ppab[2 * ((size_t)P.pp_off + q) + 1]);
+    }
     P.pp_off = off;
     kept[k] = P;
     kI[k] = std::sqrt(smax[order[k]]);
@@ -687,6 +755,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   dfree(p->d_pairs);
   dfree(p->d_pp);
   if ((rc = dupload(&p->d_pairs, kept)) || (rc = dupload(&p->d_pp, kpp)) || (rc = dupload(&p->d_pairI, kI)) ||
+      (rc = dupload(&p->d_ppab, kppab)) ||
       (rc = dupload(&p->d_pair_cls, kcls)) || (rc = dupload(&p->d_pair_sa, ksa)) ||
       (rc = dupload(&p->d_pair_sb, ksb)) || (rc = dupload(&p->d_cls_beg, p->cls_beg)) ||
       (rc = dupload(&p->d_pair_npp, knpp)) || (rc = dupload(&p->d_pair_ca, kca)) ||
@@ -716,19 +785,17 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
       (rc = dalloc(&p->d_Pblk, (size_t)p->ps_off[nmol])) || (rc = dalloc(&p->d_gmax, 1)) ||
       (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
       (rc = dalloc(&p->d_nprim, 2 * NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
-      (rc = dalloc(&p->d_room, NQCLASS)) || (rc = dalloc(&p->d_overflow, 1)) ||
+      (rc = dalloc(&p->d_room, NQCLASS)) || (rc = dalloc(&p->d_overflow, 1)) || (rc = dalloc(&p->d_capc, NQCLASS)) ||
       (rc = dalloc(&p->d_next, NSLOT)) || (rc = dalloc(&p->d_nunits, NSLOT)))
     return cleanup(rc);
-  if (hipHostMalloc((void **)&p->h_overflow, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-    p->h_overflow = nullptr;
-    return cleanup(fail(JK_ENOMEM, "hipHostMalloc of the overflow flag failed"));
-  }
-  *p->h_overflow = 0;
+  if (hipMemset(p->d_overflow, 0, sizeof(int)) != hipSuccess) return cleanup(fail(JK_EDEVICE, "hipMemset failed"));
+  p->capc.assign(NQCLASS, 0);
+  p->class_off_h.assign(NQCLASS, 0);
   p->grid.assign(NSLOT, 0);
   p->slice.assign(NSLOT, 0);
   p->units_est.assign(NSLOT, 0);
   if (p->flags & (JK_FLAG_PROFILE | JK_FLAG_TUNE)) {
-    p->events.resize(2 * NSLOT + 4, nullptr);
+    p->events.resize((size_t)EV_SETS * EV_PER_SET, nullptr);
     for (auto &e : p->events)
       if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(JK_EDEVICE, "hipEventCreate failed"));
   }
@@ -739,6 +806,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
     }
   }
   HIPCHK(hipDeviceSynchronize());
+  if (p->dmax > 0.0 && (rc = size_lists(p, nullptr, p->dmax, 0.0))) return cleanup(rc);
   p->stats.npairs_kept = p->npairs;
   p->stats.nao = p->nao;
   p->stats.nao_cart = p->nc;
@@ -761,6 +829,7 @@ struct Launch {
   int nc_max;        // fused: largest Cartesian size among the launch's molecules
   size_t lds;        // dynamic LDS bytes
   long long scratch_per_wg;
+  int kw;            // per class with compacted LDS exchange rows: their length (0: global exchange)
 };
 
 // Launches of one build. active[qc]: the class has work (eager) or may have work (recording).
@@ -779,23 +848,24 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
       bool any = false;
       for (int ck = 0; ck <= cb; ++ck) any = any || (((bi.tier_mask[tier] >> ck) & 1) && active[qclass_index(cb, ck)]);
       if (!any) continue;
-      int split = beg;
+      int split = beg, m_split = 0;
       if (bi.fusable[tier]) {
         const size_t fixed = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)bi.pool_bytes[tier];   // jab_s, pool
         const long long fit = fixed < FUSED_LDS_MAX ? (long long)((FUSED_LDS_MAX - fixed) / ((size_t)(na + nbb) * 8)) : 0;
         int m = 0;
         while (m < nmol && p->mnc[m] <= fit) ++m;      // molecules are in ascending size
         split = p->cm_beg[(size_t)cb * (nmol + 1) + m];
+        m_split = m;
         if (split > beg) {
           const int ncm = p->mnc[m - 1];
           const size_t lds = (size_t)(na + nbb) * ncm * 8 + fixed;
           // mixed precision: the FP32 parts of the lane tiers run in their own FP32-only kernel
           const bool sep = p->precision == JK_MIXED && bi.launch_bra32[tier] != nullptr;
           out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], sep ? 1 : 3, false,
-                               ncm, lds, bi.scratch_per_wg[tier]});
+                               ncm, lds, bi.scratch_per_wg[tier], 0});
           if (sep)
             out.push_back(Launch{NF32_BASE + cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], 2, true,
-                                 ncm, lds, bi.scratch_per_wg[tier]});
+                                 ncm, lds, bi.scratch_per_wg[tier], 0});
         }
       }
       if (split == end) continue;
@@ -803,8 +873,21 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         const int qc = qclass_index(cb, ck);
         if (!((bi.tier_mask[tier] >> ck) & 1) || !active[qc]) continue;
         const ClassInfo &ci = g_classes[qc];
-        const size_t lds = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)ci.team_lds;   // jab_s, pool
-        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 3, false, 0, lds, ci.scratch_per_wg});
+        const size_t jab = (size_t)((na * nbb + 1) & ~1) * 8;
+        const size_t lds = jab + (size_t)ci.team_lds;   // jab_s, pool
+        // lane bodies: the exchange rows of the unit in LDS, compacted to the columns of the
+        // ket class's momenta, when they fit for every molecule of the launch
+        int kw = 0;
+        if (JK_CLS_LDS_ROWS && ci.launch_clsl) {
+          for (int m = m_split; m < nmol; ++m) {
+            const int *seg = p->lseg.data() + (size_t)m * 6;
+            const int w = seg[ci.lc + 1] - seg[ci.lc] + (ci.lc != ci.ld ? seg[ci.ld + 1] - seg[ci.ld] : 0);
+            kw = std::max(kw, w);
+          }
+          if (kw == 0 || jab + (size_t)(na + nbb) * kw * 8 > FUSED_LDS_MAX) kw = 0;
+        }
+        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 3, false, 0,
+                             kw ? jab + (size_t)(na + nbb) * kw * 8 : lds, ci.scratch_per_wg, kw});
       }
     }
   }
@@ -832,32 +915,12 @@ void size_units(jk_plan *p, const Launch &L, long long cand, long long *units_ne
   *units_need = std::max(*units_need, est + 1);
 }
 
-// Enqueue one build on `st`. Eager (record = false): reads the class capacities back to size
-// the work list, launches the classes that have work, records profile events. Recording
-// (record = true): no host round trip, the list keeps its size (overflow flag instead),
-// every class that may have work is launched; nothing here allocates.
-int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t st, bool record) {
-  const size_t nc2 = (size_t)p->mc_off[p->nmol];
-  const bool prof = !record && !p->events.empty();
-  if (!record) {
-    p->last_stream = st;
-    p->launched.clear();
-  }
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT], st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jc, (long long)nc2, 0ull, st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Kc, (long long)nc2, 0ull, st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jpair, p->jp_total, 0ull, st));
-  HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
-  HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
-  HIPCHK(launch_fill_u64(p->d_nprim, 2 * NQCLASS, 0ull, st));
-  HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
-  HIPCHK(launch_fill_i32(p->d_count32, NQCLASS, 0, st));
-  HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
-  HIPCHK(launch_fill_i32(p->d_nunits, NSLOT, 0, st));
-  HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
-  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
-  HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+// outputs of a build: bit 0 J, bit 1 K
+int plan_want(const jk_plan *p) {
+  return (p->flags & JK_FLAG_J_ONLY) ? 1 : (p->flags & JK_FLAG_K_ONLY) ? 2 : 3;
+}
 
+ScreenArgs screen_args(const jk_plan *p) {
   ScreenArgs A{};
   A.pairI = p->d_pairI;
   A.pair_cls = p->d_pair_cls;
@@ -871,6 +934,8 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   A.ps_off = p->d_ps_off;
   A.sbase = p->d_sbase;
   A.gmax = p->d_gmax;
+  A.gfix = 0.0;
+  A.gscale = 1.0;
   A.cap = p->d_cap;
   A.segoff = p->d_segoff;
   A.segcnt = p->d_segcnt;
@@ -885,70 +950,118 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   A.nprim = p->d_nprim;
   A.class_off = p->d_class_off;
   A.room = p->d_room;
+  A.kets = p->d_kets;
   A.tau = p->tau;
   A.npairs = p->npairs;
   A.nmol = p->nmol;
-  if (p->npairs > 0) HIPCHK(launch_capacity(A, st));
-  bool active[NQCLASS];
-  unsigned long long cap_host[NQCLASS] = {};
-  if (!record) {
-    unsigned long long *cap = cap_host;
-    HIPCHK(hipMemcpyAsync(cap, p->d_cap, sizeof(cap_host), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+  A.want = plan_want(p);
+  return A;
+}
+
+// Team scratch for the launches of a build at the current workgroup counts.
+int ensure_launch_scratch(jk_plan *p) {
+  std::vector<Launch> launches;
+  plan_launches(p, p->active, launches);
+  long long need = 0;
+  for (const Launch &L : launches) need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
+  return need > 0 ? ensure_scratch(p, need) : JK_OK;
+}
+
+// Work-list layout. Counts, for every class, the candidate quartets under a density bound
+// (gfix, or gscale times the largest |D_cart| of the density already on the device), lays the
+// class regions out one after another, and sizes the work-unit list and the team scratch of
+// the launches. Regions only grow. Waits for the stream: this runs at plan creation (with a
+// caller's bound), on a plan's first execute, and when a check finds an overflow.
+int size_lists(jk_plan *p, hipStream_t st, double gfix, double gscale) {
+  unsigned long long cap[NQCLASS] = {};
+  if (p->npairs > 0) {
+    HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
+    ScreenArgs A = screen_args(p);
+    A.gfix = gfix;
+    A.gscale = gscale;
+    HIPCHK(launch_capacity(A, st));
+    HIPCHK(hipMemcpyAsync(cap, p->d_cap, sizeof(cap), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  bool grew = !p->sized;
+  for (int c = 0; c < NQCLASS; ++c) {
+    if (cap[c] > 0x7fffffffULL) return fail(JK_EUNSUPPORTED, "class %d: %llu candidate quartets exceed 2^31", c, cap[c]);
+    if ((long long)cap[c] > p->capc[c]) {
+      p->capc[c] = (long long)cap[c];
+      grew = true;
+    }
+  }
+  if (grew) {
     long long total = 0;
     for (int c = 0; c < NQCLASS; ++c) {
-      if (cap[c] > 0x7fffffffULL) return fail(JK_EUNSUPPORTED, "class %d: %llu candidate quartets exceed 2^31", c, cap[c]);
-      total += (long long)cap[c];
-      active[c] = cap[c] > 0;
+      p->class_off_h[c] = total;
+      total += p->capc[c];
+      p->active[c] = p->capc[c] > 0;
     }
-    if (total > p->list_capacity || !p->d_kets) {
-      // graph replays reuse this list: leave room for densities that keep a few more quartets
-      const long long want = (p->flags & JK_FLAG_GRAPH) ? total + total / 4 + 4096 : total;
-      dfree(p->d_kets);
-      p->list_capacity = 0;
-      p->graph_stale = true;
-      int rc = dalloc(&p->d_kets, (size_t)want + 1);
-      if (rc) return rc;
-      p->list_capacity = want;
-    }
-    p->stats.candidate_quartets = total;
-  } else {
-    for (int c = 0; c < NQCLASS; ++c) active[c] = p->possible[c] != 0;
+    dfree(p->d_kets);
+    p->list_capacity = 0;
+    int rc = dalloc(&p->d_kets, (size_t)total + 1);
+    if (rc) return rc;
+    p->list_capacity = total;
+    HIPCHK(hipMemcpy(p->d_class_off, p->class_off_h.data(), sizeof(long long) * NQCLASS, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->d_capc, p->capc.data(), sizeof(long long) * NQCLASS, hipMemcpyHostToDevice));
+    p->graph_stale = true;
   }
-  HIPCHK(launch_class_off(p->d_cap, p->d_class_off, p->d_room, p->list_capacity, p->d_overflow, st));
-  A.kets = p->d_kets;
-  if (p->npairs > 0) HIPCHK(launch_screen(A, st));
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 1], st));
+  std::vector<Launch> launches;
+  plan_launches(p, p->active, launches);
+  long long units_need = 1;
+  for (const Launch &L : launches) {
+    long long cand = 0;
+    for (int ck = 0; ck <= L.cb; ++ck)
+      if ((L.mask >> ck) & 1) cand += p->capc[qclass_index(L.cb, ck)];
+    size_units(p, L, cand, &units_need);
+  }
+  if (units_need > 0x7fffffffLL) return fail(JK_EUNSUPPORTED, "%lld work units exceed 2^31", units_need);
+  if (units_need > p->units_cap) {
+    dfree(p->d_units);
+    p->units_cap = 0;
+    int rc = dalloc(&p->d_units, (size_t)units_need);
+    if (rc) return rc;
+    p->units_cap = (int)units_need;
+    p->graph_stale = true;
+  }
+  p->sized = true;
+  return ensure_launch_scratch(p);
+}
+
+// Enqueue one build on `st`: density transform and block maxima, the screen into the class
+// regions, every integral launch, fold and finalisation. Nothing here waits for the device or
+// allocates, so the same sequence is recorded into a graph (record = true: no profile events).
+// A class whose kept candidates exceed its region raises the device overflow flag.
+int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t st, bool record) {
+  const size_t nc2 = (size_t)p->mc_off[p->nmol];
+  const bool prof = !record && !p->events.empty();
+  if (!record) p->launched.clear();
+  hipEvent_t *ev = prof ? p->events.data() + (size_t)p->ev_next * EV_PER_SET : nullptr;
+  if (prof) HIPCHK(hipEventRecord(ev[2 * NSLOT], st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jc, (long long)nc2, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Kc, (long long)nc2, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_Jpair, p->jp_total, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_nprim, 2 * NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
+  HIPCHK(launch_fill_i32(p->d_count32, NQCLASS, 0, st));
+  HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
+  HIPCHK(launch_fill_i32(p->d_nunits, NSLOT, 0, st));
+  HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
+  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+  HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+  ScreenArgs A = screen_args(p);
+  if (p->npairs > 0) {
+    HIPCHK(launch_capacity(A, st));
+    HIPCHK(launch_class_room(p->d_cap, p->d_capc, p->d_room, p->d_overflow, st));
+    HIPCHK(launch_screen(A, st));
+  }
+  if (prof) HIPCHK(hipEventRecord(ev[2 * NSLOT + 1], st));
 
   std::vector<Launch> launches;
-  plan_launches(p, active, launches);
-  if (!record) {
-    long long units_need = 1;
-    for (const Launch &L : launches) {
-      long long cand = 0;
-      for (int ck = 0; ck <= L.cb; ++ck)
-        if ((L.mask >> ck) & 1) cand += (long long)cap_host[qclass_index(L.cb, ck)];
-      size_units(p, L, cand, &units_need);
-    }
-    if (units_need > 0x7fffffffLL) return fail(JK_EUNSUPPORTED, "%lld work units exceed 2^31", units_need);
-    if (units_need > p->units_cap) {
-      // graph replays reuse this buffer: leave room for densities that keep a few more quartets
-      const long long want = (p->flags & JK_FLAG_GRAPH) ? std::min(units_need + units_need / 4 + 1024, 0x7fffffffLL)
-                                                         : units_need;
-      dfree(p->d_units);
-      p->units_cap = 0;
-      p->graph_stale = true;
-      int rc = dalloc(&p->d_units, (size_t)want);
-      if (rc) return rc;
-      p->units_cap = (int)want;
-    }
-    long long need = 0;
-    for (const Launch &L : launches) need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
-    if (need > 0) {
-      int rc = ensure_scratch(p, need);
-      if (rc) return rc;
-    }
-  }
+  plan_launches(p, p->active, launches);
   JKArgs J_{};
   J_.pairs = p->d_pairs;
   J_.pp = p->d_pp;
@@ -966,6 +1079,11 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   J_.jp_off = p->d_jp_off;
   J_.cls_beg = p->d_cls_beg;
   J_.scratch = p->d_scratch;
+  J_.want = plan_want(p);
+  J_.lcol = p->d_lcol;
+  J_.lcols = p->d_lcols;
+  J_.lseg = p->d_lseg;
+  J_.cbase = p->d_cbase;
   for (const Launch &L : launches) {
     const int grid = launch_grid(p, L);
     if (L.scratch_per_wg * (long long)grid > p->scratch_doubles)
@@ -982,15 +1100,18 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
                         p->units_cap, p->d_nunits + L.slot, p->d_overflow, st));
     J_.scratch_per_wg = L.scratch_per_wg;
     J_.next = p->d_next + L.slot;
-    if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot], st));
+    if (prof) HIPCHK(hipEventRecord(ev[2 * L.slot], st));
+    J_.kw = L.kw;
     if (L.qc < 0)
       HIPCHK((L.f32 ? g_bras[L.cb].launch_bra32[L.tier] : g_bras[L.cb].launch_bra[L.tier])(J_, grid, L.lds, st));
+    else if (L.kw > 0)
+      HIPCHK(g_classes[L.qc].launch_clsl(J_, grid, L.lds, st));
     else
       HIPCHK(g_classes[L.qc].launch_cls(J_, grid, L.lds, st));
-    if (prof) HIPCHK(hipEventRecord(p->events[2 * L.slot + 1], st));
+    if (prof) HIPCHK(hipEventRecord(ev[2 * L.slot + 1], st));
     if (!record) p->launched.push_back(L.slot);
   }
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 2], st));
+  if (prof) HIPCHK(hipEventRecord(ev[2 * NSLOT + 2], st));
   FoldArgs F{};
   F.pair_cls = p->d_pair_cls;
   F.pair_ca = p->d_pair_ca;
@@ -1005,38 +1126,23 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   F.Jpair = p->d_Jpair;
   F.Jc = p->d_Jc;
   F.npairs = p->npairs;
-  if (p->npairs > 0) HIPCHK(launch_fold(F, st));
-  HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, J, K, st));
-  if (prof) HIPCHK(hipEventRecord(p->events[2 * NSLOT + 3], st));
+  if (p->npairs > 0 && (J_.want & 1)) HIPCHK(launch_fold(F, st));
+  HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, (J_.want & 1) ? J : nullptr, (J_.want & 2) ? K : nullptr, st));
+  if (prof) {
+    HIPCHK(hipEventRecord(ev[2 * NSLOT + 3], st));
+    p->ev_next = (p->ev_next + 1) % EV_SETS;
+    p->ev_count = std::min(p->ev_count + 1, EV_SETS);
+  }
   return JK_OK;
 }
 
 // Record the build into a HIP graph (on the plan's own stream: the caller's may be the
-// legacy default stream, which cannot be recorded). The list and scratch buffers must
-// already have the sizes the replay will use.
-int record_graph(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
-  HIPCHK(hipStreamSynchronize(st));
-  bool active[NQCLASS];
-  for (int c = 0; c < NQCLASS; ++c) active[c] = p->possible[c] != 0;
-  std::vector<Launch> launches;
-  plan_launches(p, active, launches);
-  long long need = 0, units_need = 1;
-  for (const Launch &L : launches) {
-    need = std::max(need, L.scratch_per_wg * (long long)launch_grid(p, L));
-    const long long u = p->slice[L.slot] > 0 ? p->units_est[L.slot] : L.bra_end - L.bra_beg;
-    units_need = std::max(units_need, u + 1);
-  }
-  int rc = ensure_scratch(p, need);
-  if (rc) return rc;
-  if (units_need > p->units_cap) {
-    dfree(p->d_units);
-    p->units_cap = 0;
-    if ((rc = dalloc(&p->d_units, (size_t)units_need))) return rc;
-    p->units_cap = (int)units_need;
-  }
+// legacy default stream, which cannot be recorded). Every buffer already has its size, so
+// recording neither allocates nor waits.
+int record_graph(jk_plan *p, const double *D, double *J, double *K) {
   graph_free(p);
   HIPCHK(hipStreamBeginCapture(p->rec_stream, hipStreamCaptureModeThreadLocal));
-  rc = enqueue_build(p, D, J, K, p->rec_stream, true);
+  int rc = enqueue_build(p, D, J, K, p->rec_stream, true);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(p->rec_stream, &g);
   if (rc) {
@@ -1107,12 +1213,14 @@ int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st
   std::vector<int> pick(NSLOT, 0);
   for (int g : TUNE_GRIDS) {
     std::fill(p->grid.begin(), p->grid.end(), g);
-    int rc = enqueue_build(p, D, J, K, st, false);
+    int rc = ensure_launch_scratch(p);
+    const hipEvent_t *ev = p->events.data() + (size_t)p->ev_next * EV_PER_SET;   // the set this build records
+    if (!rc) rc = enqueue_build(p, D, J, K, st, false);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(st));
     for (int slot : p->launched) {
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, p->events[2 * slot], p->events[2 * slot + 1]));
+      HIPCHK(hipEventElapsedTime(&ms, ev[2 * slot], ev[2 * slot + 1]));
       if (ms < best[slot]) {
         best[slot] = ms;
         pick[slot] = g;
@@ -1121,53 +1229,168 @@ int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st
   }
   p->grid = pick;
   save_tune_cache(p);
-  return JK_OK;
+  return ensure_launch_scratch(p);
 }
 
+constexpr double SIZE_HEADROOM = 2.0;   // first-execute sizing: lists hold densities up to twice its largest element
+
 int plan_run(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
-  if (!D || !J || !K) return fail(JK_EINVAL, "D, J and K must be device pointers");
+  const int want = plan_want(p);
+  if (!D || (!J && (want & 1)) || (!K && (want & 2)))
+    return fail(JK_EINVAL, "D and the requested outputs (J, K) must be device pointers");
+  p->last_stream = st;
+  if (!p->sized) {
+    // the first execute sizes the lists from its own density: transform, block maxima, then
+    // the candidate counts under twice its largest element (one wait for the device)
+    HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
+    HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+    HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+    int rc = size_lists(p, st, 0.0, SIZE_HEADROOM);
+    if (rc) return rc;
+  }
   if ((p->flags & JK_FLAG_TUNE) && !p->tuned) {
-    if (!load_tune_cache(p)) {
-      int rc = tune_grids(p, D, J, K, st);
-      if (rc) return rc;
-    }
+    int rc = load_tune_cache(p) ? ensure_launch_scratch(p) : tune_grids(p, D, J, K, st);
+    if (rc) return rc;
     p->tuned = true;
     p->graph_stale = true;
   }
   if (!(p->flags & JK_FLAG_GRAPH)) return enqueue_build(p, D, J, K, st, false);
   if (p->gexec && !p->graph_stale && D == p->gD && J == p->gJ && K == p->gK) {
-    HIPCHK(hipGraphLaunch(p->gexec, st));
-    HIPCHK(hipMemcpyAsync(p->h_overflow, p->d_overflow, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    p->last_stream = st;
-    if (!*p->h_overflow) {
-      ++p->replays;
-      return JK_OK;
-    }
-    ++p->rerecords;   // the density needed a longer work list: redo eagerly, then record again
+    ++p->replays;
+  } else {
+    if (p->gexec) ++p->rerecords;
+    int rc = record_graph(p, D, J, K);
+    if (rc) return rc;
   }
-  int rc = enqueue_build(p, D, J, K, st, false);
+  p->launched.clear();
+  HIPCHK(hipGraphLaunch(p->gexec, st));
+  return JK_OK;
+}
+
+// Waits for the plan's last build and reports whether its work lists overflowed. On overflow
+// the lists grow (sized for twice the largest density element of that build) and the caller
+// runs the build again.
+int plan_check(jk_plan *p) {
+  HIPCHK(hipStreamSynchronize(p->last_stream));
+  int ov = 0;
+  HIPCHK(hipMemcpy(&ov, p->d_overflow, sizeof(int), hipMemcpyDeviceToHost));
+  if (!ov) return JK_OK;
+  ++p->overflows;
+  int rc = size_lists(p, p->last_stream, 0.0, SIZE_HEADROOM);
   if (rc) return rc;
-  return record_graph(p, D, J, K, st);
+  HIPCHK(hipMemset(p->d_overflow, 0, sizeof(int)));
+  return fail(JK_EOVERFLOW, "the last build needed longer work lists than the plan held, so its J and K are "
+              "incomplete; the lists have grown and a new execute completes");
+}
+
+// ------------------------------------------------------------------ nuclear gradient
+// The screen of the J/K build (six density blocks), then one k_grad launch per quartet class
+// over the kept quartets of its work list. grad (natom x 3) is overwritten.
+int plan_grad(jk_plan *p, const double *D, double *grad, hipStream_t st) {
+  if (!D || !grad) return fail(JK_EINVAL, "D and grad must be device pointers");
+  if (p->nmol != 1) return fail(JK_EUNSUPPORTED, "the gradient is built for single-molecule plans");
+  if (p->lmax > GRAD_LMAX) return fail(JK_EUNSUPPORTED, "gradient kernels exist for shells up to l = %d (plan has %d)",
+                                       GRAD_LMAX, p->lmax);
+  if (plan_want(p) != 3) return fail(JK_EINVAL, "the gradient needs a plan made for J and K (no J-only/K-only flag)");
+  p->last_stream = st;
+  if (!p->sized) {
+    HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
+    HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+    HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+    int rc = size_lists(p, st, 0.0, SIZE_HEADROOM);
+    if (rc) return rc;
+  }
+  // work units of each class launch: slices sized from the class capacity as for the J/K launches
+  std::vector<int> gslice(NQCLASS, 0), gest(NQCLASS, 0);
+  long long need = 1;
+  for (int qc = 0; qc < NQCLASS; ++qc) {
+    if (!p->active[qc] || !g_grad[qc]) continue;
+    const int cb = (int)((std::sqrt(8.0 * qc + 1) - 1) / 2);
+    const long long nbra = p->cls_beg[cb + 1] - p->cls_beg[cb];
+    long long sl = (p->capc[qc] + TARGET_UNITS - 1) / TARGET_UNITS;
+    sl = std::max<long long>(SLICE_MIN, (sl + SLICE_MIN - 1) / SLICE_MIN * SLICE_MIN);
+    gslice[qc] = (int)std::min<long long>(sl, 1LL << 30);
+    gest[qc] = (int)std::min<long long>(nbra + (p->capc[qc] + sl - 1) / sl, 1LL << 30);
+    need = std::max(need, (long long)gest[qc] + 1);
+  }
+  if (need > p->units_cap) {
+    HIPCHK(hipStreamSynchronize(st));
+    dfree(p->d_units);
+    p->units_cap = 0;
+    int rc = dalloc(&p->d_units, (size_t)need);
+    if (rc) return rc;
+    p->units_cap = (int)need;
+    p->graph_stale = true;
+  }
+  HIPCHK(launch_fill_u64((unsigned long long *)grad, 3LL * p->natom, 0ull, st));
+  HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_cap, NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_u64(p->d_nprim, 2 * NQCLASS, 0ull, st));
+  HIPCHK(launch_fill_i32(p->d_count, NQCLASS, 0, st));
+  HIPCHK(launch_fill_i32(p->d_count32, NQCLASS, 0, st));
+  HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
+  HIPCHK(launch_fill_i32(p->d_nunits, NSLOT, 0, st));
+  HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
+  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+  HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+  ScreenArgs A = screen_args(p);
+  A.fp32_cut = 0.0;                       // every kept quartet in the FP64 part of its segment
+  if (p->npairs > 0) {
+    HIPCHK(launch_capacity(A, st));
+    HIPCHK(launch_class_room(p->d_cap, p->d_capc, p->d_room, p->d_overflow, st));
+    HIPCHK(launch_screen(A, st));
+  }
+  GradArgs G{};
+  G.pairs = p->d_pairs;
+  G.pp = p->d_pp;
+  G.ppab = p->d_ppab;
+  G.kets = p->d_kets;
+  G.class_off = p->d_class_off;
+  G.segoff = p->d_segoff;
+  G.segcnt = p->d_segcnt;
+  G.Dc = p->d_Dc;
+  G.nc = p->nc;
+  G.shell_atom = p->d_shell_atom;
+  G.grad = grad;
+  G.units = p->d_units;
+  G.units_cap = p->units_cap;
+  for (int qc = 0; qc < NQCLASS; ++qc) {
+    if (!p->active[qc] || !g_grad[qc]) continue;
+    const int cb = (int)((std::sqrt(8.0 * qc + 1) - 1) / 2), ck = qc - cb * (cb + 1) / 2;
+    const int slot = NFUSED + qc;
+    G.slice = gslice[qc];
+    G.nunits = p->d_nunits + slot;
+    G.next = p->d_next + slot;
+    HIPCHK(launch_units(p->d_segcnt, nullptr, p->cls_beg[cb], p->cls_beg[cb + 1], 1 << ck, 1, G.slice, p->d_units,
+                        p->units_cap, p->d_nunits + slot, p->d_overflow, st));
+    HIPCHK(g_grad[qc](G, std::max(1, std::min(gest[qc], GRID_TEAM_MAX)), st));
+  }
+  return JK_OK;
 }
 
 int plan_stats(const jk_plan *plan, jk_stats_t *out) {
   *out = plan->stats;
   if (plan->d_count) {
-    int cnt[NQCLASS], c32[NQCLASS];
-    unsigned long long np[NQCLASS];
+    int cnt[NQCLASS], c32[NQCLASS], ov = 0;
+    unsigned long long np[NQCLASS], cap[NQCLASS];
     HIPCHK(hipStreamSynchronize(plan->last_stream));
     HIPCHK(hipMemcpy(cnt, plan->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(c32, plan->d_count32, sizeof(c32), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(np, plan->d_nprim, sizeof(np), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cap, plan->d_cap, sizeof(cap), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&ov, plan->d_overflow, sizeof(int), hipMemcpyDeviceToHost));
     out->kept_quartets = 0;
     out->kept_fp32 = 0;
     out->prim_quartets = 0;
+    out->candidate_quartets = 0;
     for (int c = 0; c < NQCLASS; ++c) {
       out->kept_quartets += cnt[c];
       out->kept_fp32 += c32[c];
       out->prim_quartets += (long long)np[c];
+      out->candidate_quartets += (long long)cap[c];
     }
+    out->overflow = ov;
+    out->list_capacity = plan->list_capacity;
   }
   return JK_OK;
 }
@@ -1241,8 +1464,22 @@ int jk_stats(const jk_plan_t *plan, jk_stats_t *out) {
 int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries) {
   if (!p || !out || !n_entries) return fail(JK_EINVAL, "NULL argument");
   if (!(p->flags & JK_FLAG_PROFILE)) return fail(JK_EINVAL, "plan was not created with JK_FLAG_PROFILE");
-  if (p->launched.empty() && p->replays > 0) return fail(JK_EINVAL, "graph replays are not profiled");
+  if (p->launched.empty() || p->ev_count == 0)
+    return fail(JK_EINVAL, "no profiled build since the last profile (graph launches are not profiled)");
   HIPCHK(hipStreamSynchronize(p->last_stream));
+  // mean HIP-event time of events (i0, i1) over the executes recorded since the last call
+  const int nsets = p->ev_count;
+  auto mean_ms = [&](int i0, int i1, double *out_ms) -> int {
+    double sum = 0.0;
+    for (int k = 1; k <= nsets; ++k) {
+      const hipEvent_t *ev = p->events.data() + (size_t)((p->ev_next - k + EV_SETS) % EV_SETS) * EV_PER_SET;
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[i0], ev[i1]));
+      sum += ms;
+    }
+    *out_ms = sum / nsets;
+    return JK_OK;
+  };
   int cnt[NQCLASS], c32[NQCLASS];
   unsigned long long np[2 * NQCLASS];
   HIPCHK(hipMemcpy(cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost));
@@ -1257,7 +1494,7 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
   auto class_flops = [&](int qc, jk_profile_t &r, int parts) {
     const ClassInfo &ci = g_classes[qc];
     double fp = 0.0, fq = 0.0;
-    class_ops(ci.la, ci.lb, ci.lc, ci.ld, &fp, &fq);
+    class_ops(ci.la, ci.lb, ci.lc, ci.ld, plan_want(p), &fp, &fq);
     const double q = parts == 3 ? cnt[qc] : parts == 2 ? c32[qc] : cnt[qc] - c32[qc];
     const double pq = parts == 3 ? (double)np[qc] : parts == 2 ? (double)np[NQCLASS + qc]
                                                                : (double)(np[qc] - np[NQCLASS + qc]);
@@ -1265,11 +1502,10 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
     r.prim_quartets += (long long)pq;
     r.flops += pq * fp + q * fq;
   };
-  float ms = 0.f;
+  int rc;
   jk_profile_t e{};
   e.kind = 1;
-  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NSLOT], p->events[2 * NSLOT + 1]));
-  e.ms = ms;
+  if ((rc = mean_ms(2 * NSLOT, 2 * NSLOT + 1, &e.ms))) return rc;
   push(e);
   for (int slot : p->launched) {
     jk_profile_t r{};
@@ -1291,15 +1527,14 @@ int jk_profile(jk_plan_t *p, jk_profile_t *out, int max_entries, int *n_entries)
       r.nroots = (ci.la + ci.lb + ci.lc + ci.ld) / 2 + 1;
       class_flops(slot - NFUSED, r, 3);
     }
-    HIPCHK(hipEventElapsedTime(&ms, p->events[2 * slot], p->events[2 * slot + 1]));
-    r.ms = ms;
+    if ((rc = mean_ms(2 * slot, 2 * slot + 1, &r.ms))) return rc;
     push(r);
   }
   e = jk_profile_t{};
   e.kind = 2;
-  HIPCHK(hipEventElapsedTime(&ms, p->events[2 * NSLOT + 2], p->events[2 * NSLOT + 3]));
-  e.ms = ms;
+  if ((rc = mean_ms(2 * NSLOT + 2, 2 * NSLOT + 3, &e.ms))) return rc;
   push(e);
+  p->ev_count = 0;
   *n_entries = n;
   return JK_OK;
 }
@@ -1327,6 +1562,16 @@ int jk_plan_execute(jk_plan_t *p, const double *D, double *J, double *K, void *s
   return plan_run(p, D, J, K, (hipStream_t)stream);
 }
 
+int jk_plan_check(jk_plan_t *p) {
+  if (!p) return fail(JK_EINVAL, "plan is NULL");
+  return plan_check(p);
+}
+
+int jk_grad(jk_plan_t *p, const double *D, double *grad, void *stream) {
+  if (!p) return fail(JK_EINVAL, "plan is NULL");
+  return plan_grad(p, D, grad, (hipStream_t)stream);
+}
+
 int jk_build(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh, double *J,
              double *K, const jk_opts_t *opts, void *stream) {
   jk_opts_t o{};
@@ -1336,9 +1581,10 @@ int jk_build(const jk_basis_t *basis, const double *coords, int natom, const dou
   int rc = jk_plan_create(basis, coords, natom, &o, &p);
   if (rc) return rc;
   rc = jk_plan_execute(p, D, J, K, stream);
-  if (!rc) {
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  if (!rc) rc = plan_check(p);
+  if (rc == JK_EOVERFLOW) {     // the lists have grown: build again
+    rc = jk_plan_execute(p, D, J, K, stream);
+    if (!rc) rc = plan_check(p);
   }
   jk_plan_destroy(p);
   return rc;
@@ -1409,6 +1655,11 @@ int jk_batch_offsets(const jk_batch_t *b, long long *off, int *nao) {
 int jk_batch_execute(jk_batch_t *b, const double *D, double *J, double *K, void *stream) {
   if (!b || !b->p) return fail(JK_EINVAL, "batch is NULL");
   return plan_run(b->p, D, J, K, (hipStream_t)stream);
+}
+
+int jk_batch_check(jk_batch_t *b) {
+  if (!b || !b->p) return fail(JK_EINVAL, "batch is NULL");
+  return plan_check(b->p);
 }
 
 int jk_batch_stats(const jk_batch_t *b, jk_stats_t *out) {

@@ -33,6 +33,7 @@ struct ScreenArgs {           // device pointers
   const long long *ps_off;    // [nmol+1] first element of each molecule's block in Pblk
   const int *sbase;           // [nmol+1] first shell of each molecule
   const double *gmax;         // global maximum of |D_cart|
+  double gfix, gscale;        // k_capacity's density bound: gfix if > 0, else gscale * (*gmax) (k_screen: *gmax)
   unsigned long long *cap;    // [120] size of each class region (k_capacity)
   int *segoff;                // [npairs * 15] segment offset in the class region (k_capacity)
   int *segcnt;                // [npairs * 15] kept FP64 kets of the segment (k_screen)
@@ -41,12 +42,13 @@ struct ScreenArgs {           // device pointers
   int *count32;               // [120] of those, evaluated in FP32
   unsigned long long *nprim;  // [240] primitive quartets of the kept quartets, then of the FP32 ones (k_screen)
   const long long *class_off; // [120] first entry of each class region in kets
-  const long long *room;      // [120] entries available to each class region (k_class_off)
+  const long long *room;      // [120] entries available to each class region (k_class_room)
   int *kets;
   double tau;
   double fp32_cut;            // quartets with I_ab I_cd P below this go to FP32 (0: none) ...
   unsigned long long f32_classes[2];   // ... if their class (bit qc) has an FP32 body
   int npairs, nmol;
+  int want;                   // outputs: bit 0 J (Coulomb blocks in the test), bit 1 K (exchange blocks)
 };
 
 struct FoldArgs {             // Coulomb pair buffer -> Cartesian Jt of each molecule
@@ -62,8 +64,8 @@ struct FoldArgs {             // Coulomb pair buffer -> Cartesian Jt of each mol
 
 hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, hipStream_t st);
 hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, double *gmax, hipStream_t st);
-hipError_t launch_class_off(const unsigned long long *cap, long long *class_off, long long *room, long long limit,
-                            int *overflow, hipStream_t st);
+hipError_t launch_class_room(const unsigned long long *cap, const long long *capc, long long *room, int *overflow,
+                             hipStream_t st);
 hipError_t launch_capacity(const ScreenArgs &A, hipStream_t st);
 hipError_t launch_screen(const ScreenArgs &A, hipStream_t st);
 hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,

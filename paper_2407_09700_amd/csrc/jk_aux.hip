@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_capacity(ScreenArgs A) {
     cb = A.pair_cls[i];
     const int m = A.pair_mol[i];
     const double Ib = A.pairI[i];
-    const double pglob = *A.gmax;
+    const double pglob = A.gfix > 0.0 ? A.gfix : *A.gmax * A.gscale;
     for (int ck = 0; ck < NPAIRCLASS; ++ck) {
       loc[ck] = 0;
       if (ck > cb) continue;
@@ -134,22 +134,16 @@ __global__ __launch_bounds__(256) void k_capacity(ScreenArgs A) {
     for (int ck = 0; ck <= cb; ++ck) A.segoff[(size_t)i * NPAIRCLASS + ck] = (int)(s_base[qclass_index(cb, ck)] + loc[ck]);
 }
 
-// Class regions of the work list, laid out one after another in class order. The list has
-// `limit` entries; a class that does not fit keeps what room is left (possibly none) and
-// the overflow flag is raised (only graph replays, whose list was sized at recording
-// time, can see this: an eager build sizes the list from cap first).
-__global__ void k_class_off(const unsigned long long *cap, long long *class_off, long long *room, long long limit,
-                            int *overflow) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  long long off = 0;
-  for (int c = 0; c < NQCLASS; ++c) {
-    const long long n = (long long)cap[c];
-    class_off[c] = off < limit ? off : limit;
-    const long long left = limit - class_off[c];
-    room[c] = n < left ? n : left;
-    off += n;
-  }
-  if (off > limit) *overflow = 1;
+// Room of every class region of the work list for this build. The regions (offsets and
+// capacities) were laid out when the plan sized its lists; a class whose candidates exceed its
+// capacity keeps what fits and raises the overflow flag (the build is then incomplete, which
+// the host reports when it checks the plan).
+__global__ void k_class_room(const unsigned long long *cap, const long long *capc, long long *room, int *overflow) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= NQCLASS) return;
+  const long long n = (long long)cap[c];
+  room[c] = n < capc[c] ? n : capc[c];
+  if (n > capc[c]) *overflow = 1;
 }
 
 // One wave per bra pair: tests the candidates of every ket class with the exact
@@ -217,12 +211,11 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
           }
           kg = A.bin_beg[b0 + lo_b] + (k - pref[lo_b]);
           const int sc = A.pair_sa[kg] - sb0, sd = A.pair_sb[kg] - sb0;
-          double p = pab;
-          p = fmax(p, Pm[(size_t)sc * ns + sd]);
-          p = fmax(p, Pa[sc]);
-          p = fmax(p, Pa[sd]);
-          p = fmax(p, Pb[sc]);
-          p = fmax(p, Pb[sd]);
+          // largest density block the quartet's updates read: D[a,b], D[c,d] (Coulomb),
+          // D[a,c], D[a,d], D[b,c], D[b,d] (exchange)
+          double p = 0.0;
+          if (A.want & 1) p = fmax(pab, Pm[(size_t)sc * ns + sd]);
+          if (A.want & 2) p = fmax(fmax(p, fmax(Pa[sc], Pa[sd])), fmax(Pb[sc], Pb[sd]));
           const double bound = Ib * A.pairI[kg] * p;
           keep = bound >= tau;
           lo = keep && bound < cut;            // mixed precision: evaluated in FP32
@@ -323,8 +316,8 @@ __global__ void k_finalize(ShellInfo S, const double *__restrict__ Jc, const dou
       vj = fma(ta, rj, vj);
       vk = fma(ta, rk, vk);
     }
-    J[S.mf_user[m] + r] = vj;
-    K[S.mf_user[m] + r] = vk;
+    if (J) J[S.mf_user[m] + r] = vj;
+    if (K) K[S.mf_user[m] + r] = vk;
   }
 }
 
@@ -397,9 +390,9 @@ hipError_t launch_screen(const ScreenArgs &A, hipStream_t st) {
   hipLaunchKernelGGL(k_screen, dim3((A.npairs + 3) / 4), dim3(256), 0, st, A);
   return hipGetLastError();
 }
-hipError_t launch_class_off(const unsigned long long *cap, long long *class_off, long long *room, long long limit,
-                            int *overflow, hipStream_t st) {
-  hipLaunchKernelGGL(k_class_off, dim3(1), dim3(64), 0, st, cap, class_off, room, limit, overflow);
+hipError_t launch_class_room(const unsigned long long *cap, const long long *capc, long long *room, int *overflow,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_class_room, dim3(1), dim3(128), 0, st, cap, capc, room, overflow);
   return hipGetLastError();
 }
 hipError_t launch_fold(const FoldArgs &F, hipStream_t st) {

@@ -17,7 +17,8 @@ struct ClassInfo {           // one quartet class (la lb | lc ld)
   int per_block;             // quartets one k_mode workgroup consumes per pass
   int team_lds;              // bytes of team LDS (pool)
   long long scratch_per_wg;  // doubles of global team buffer per workgroup
-  jk_launch_fn launch_cls;   // k_cls
+  jk_launch_fn launch_cls;   // k_cls (exchange to global memory)
+  jk_launch_fn launch_clsl;  // k_cls with compacted LDS exchange rows (lane bodies; null for team classes)
   mode_launch_fn launch_mode[3];
 };
 

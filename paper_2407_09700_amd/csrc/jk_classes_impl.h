@@ -15,9 +15,9 @@ void allow_dyn_lds(F *fn) {
   (void)hipGetLastError();   // the attribute is a hint; do not leave its status for a launch check
 }
 
-template <int LA, int LB, int LC, int LD>
+template <int LA, int LB, int LC, int LD, bool KL = false>
 hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((k_cls<LA, LB, LC, LD>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), lds, stream, args);
+  hipLaunchKernelGGL((k_cls<LA, LB, LC, LD, KL>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), lds, stream, args);
   return hipGetLastError();
 }
 
@@ -57,6 +57,12 @@ void register_one(ClassInfo *table) {
   }
   ci.launch_cls = launch_cls<LA, LB, LC, LD>;
   allow_dyn_lds(k_cls<LA, LB, LC, LD>);
+  if constexpr (!use_team<LA, LB, LC, LD>()) {
+    ci.launch_clsl = launch_cls<LA, LB, LC, LD, true>;
+    allow_dyn_lds(k_cls<LA, LB, LC, LD, true>);
+  } else {
+    ci.launch_clsl = nullptr;
+  }
   ci.launch_mode[MODE_JK] = nullptr;
   ci.launch_mode[MODE_SCHWARZ] = (LA == LC && LB == LD) ? launch_mode<LA, LB, LC, LD, MODE_SCHWARZ> : nullptr;
   ci.launch_mode[MODE_ERI] = launch_mode<LA, LB, LC, LD, MODE_ERI>;

@@ -93,6 +93,15 @@ struct JKArgs {
   int parts;                    // segment parts of the launch: 1 FP64, 2 FP32, 3 both (k_bra)
   double *scratch;              // global buffers of the largest team classes
   long long scratch_per_wg;
+  int want;                     // outputs of the build: bit 0 J, bit 1 K (both: the full digestion)
+  // compacted exchange rows of the per-class kernel (k_cls with KL): for the ket class (lc, ld)
+  // a row holds the Cartesian columns of the molecule's shells of angular momentum lc, then
+  // (lc != ld) those of momentum ld
+  const int *lcol;              // per shell: first column of the shell inside its momentum's segment
+  const int *lcols;             // per molecule (from cbase[m]): Cartesian columns ordered by momentum
+  const int *lseg;              // [nmol * 6] start of each momentum's segment in lcols (l = 0..4, end)
+  const int *cbase;             // [nmol + 1] first Cartesian AO of each molecule
+  int kw;                       // LDS row length of the launch (largest over its molecules)
 };
 
 __device__ __forceinline__ double *jp_elem(const JKArgs &A, int cls, int pair, int e) {
@@ -100,22 +109,27 @@ __device__ __forceinline__ double *jp_elem(const JKArgs &A, int cls, int pair, i
   return A.Jpair + A.jp_off[cls] + (long long)e * (A.cls_beg[cls + 1] - beg) + (pair - beg);
 }
 
-// exchange update into row `r` of the unit: LDS rows (KLDS; r < NA+NB) or the global matrix
-// Km: the molecule's exchange block in global memory; nc: its row length.
+// exchange update into row `r` of the unit: LDS rows (KLDS; r < NA+NB, row length kst, column
+// kcol) or the global matrix Km (the molecule's exchange block, row grow, column gcol, row
+// length nc).
 template <bool KLDS>
-__device__ __forceinline__ void k_update(double *Krow, double *Km, int nc, int r, int grow, int col, double v) {
+__device__ __forceinline__ void k_update(double *Krow, double *Km, int kst, int nc, int r, int grow, int kcol, int gcol,
+                                         double v) {
   if constexpr (KLDS)
-    atomicAdd(&Krow[(size_t)r * nc + col], v);
+    atomicAdd(&Krow[(size_t)r * kst + kcol], v);
   else
-    atomic_add(&Km[(size_t)grow * nc + col], v);
+    atomic_add(&Km[(size_t)grow * nc + gcol], v);
 }
 
 // ------------------------------------------------------------------ lane-per-quartet body
 // R: arithmetic type of the integral evaluation (double, or float for the FP32 quartets of
 // mixed precision); the digestion always runs in double.
-template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double>
+// KMAP: the LDS rows are the compacted rows of k_cls (row length kst, ket class columns from
+// kdofs); otherwise full rows of the molecule's Cartesian columns (row length nc).
+template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double, bool KMAP = false>
 __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
-                                              double (&jab)[ncart(LA) * ncart(LB)], int rot) {
+                                              double (&jab)[ncart(LA) * ncart(LB)], int rot, int kdofs = 0,
+                                              int kst_map = 0) {
   using C = SmallCfg<LA, LB, LC, LD>;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int ck = pair_class(LC, LD);
@@ -137,25 +151,30 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
     small_eri<LA, LB, LC, LD, R>(bra, ket, A.pp, g);
     const double s = sym_factor(bra, ket, bi, ki);
     const int oc = ket.ca, od = ket.cb;
-    double Dcd[NC * ND];
+    if (A.want & 1) {
+      double Dcd[NC * ND];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int d = 0; d < ND; ++d) Dcd[c * ND + d] = Dm[(size_t)(oc + c) * nc + od + d];
+        for (int d = 0; d < ND; ++d) Dcd[c * ND + d] = Dm[(size_t)(oc + c) * nc + od + d];
 #pragma unroll
-    for (int ab = 0; ab < NA * NB; ++ab) {
-      double v = 0.0;
+      for (int ab = 0; ab < NA * NB; ++ab) {
+        double v = 0.0;
 #pragma unroll
-      for (int cd = 0; cd < NC * ND; ++cd) v = fma((double)g[ab * NC * ND + cd], Dcd[cd], v);
-      jab[ab] = fma(2.0 * s, v, jab[ab]);
+        for (int cd = 0; cd < NC * ND; ++cd) v = fma((double)g[ab * NC * ND + cd], Dcd[cd], v);
+        jab[ab] = fma(2.0 * s, v, jab[ab]);
+      }
+#pragma unroll
+      for (int cd = 0; cd < NC * ND; ++cd) {
+        double v = 0.0;
+#pragma unroll
+        for (int ab = 0; ab < NA * NB; ++ab) v = fma((double)g[ab * NC * ND + cd], Dab[ab], v);
+        atomic_add(jp_elem(A, ck, ki, cd), 2.0 * s * v);
+      }
     }
-#pragma unroll
-    for (int cd = 0; cd < NC * ND; ++cd) {
-      double v = 0.0;
-#pragma unroll
-      for (int ab = 0; ab < NA * NB; ++ab) v = fma((double)g[ab * NC * ND + cd], Dab[ab], v);
-      atomic_add(jp_elem(A, ck, ki, cd), 2.0 * s * v);
-    }
+    if (!(A.want & 2)) continue;
+    const int kc = KMAP ? A.lcol[ket.sa] : oc, kd = KMAP ? kdofs + A.lcol[ket.sb] : od;
+    const int kst = KMAP ? kst_map : nc;
     // exchange: rows a (K[a,c] with D[b,d], K[a,d] with D[b,c]), rows b (K[b,c] with D[a,d], K[b,d] with D[a,c])
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
@@ -166,7 +185,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + od + d], v);
-        k_update<KLDS>(Krow, Km, nc, a, bra.ca + a, oc + c, s * v);
+        k_update<KLDS>(Krow, Km, kst, nc, a, bra.ca + a, kc + c, oc + c, s * v);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -175,7 +194,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + oc + c], v);
-        k_update<KLDS>(Krow, Km, nc, a, bra.ca + a, od + d, s * v);
+        k_update<KLDS>(Krow, Km, kst, nc, a, bra.ca + a, kd + d, od + d, s * v);
       }
     }
 #pragma unroll
@@ -187,7 +206,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + od + d], v);
-        k_update<KLDS>(Krow, Km, nc, NA + b, bra.cb + b, oc + c, s * v);
+        k_update<KLDS>(Krow, Km, kst, nc, NA + b, bra.cb + b, kc + c, oc + c, s * v);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -196,7 +215,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + oc + c], v);
-        k_update<KLDS>(Krow, Km, nc, NA + b, bra.cb + b, od + d, s * v);
+        k_update<KLDS>(Krow, Km, kst, nc, NA + b, bra.cb + b, kd + d, od + d, s * v);
       }
     }
   }
@@ -310,7 +329,8 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     if constexpr (NCD < TEAM_STREAM_MIN) {
       // Small ket blocks: one task per output element, one loop per kind of output (no
       // divergence between kinds), integrals and densities read from LDS (or the buffer).
-      for (int t = tid; t < QB * NAB; t += blockDim.x) {          // J[a,b] += 2s sum_cd g D[c,d]
+      const int nj = (A.want & 1) ? 1 : 0, nk = (A.want & 2) ? 1 : 0;
+      for (int t = tid; t < nj * QB * NAB; t += blockDim.x) {     // J[a,b] += 2s sum_cd g D[c,d]
         const int q = t / NAB, r = t % NAB;
         if (!qi[q * 8 + 6]) continue;
         const double *gr = Z + (size_t)q * NG + r * NCD, *dcd = ds + NAB + q * DQ;
@@ -319,7 +339,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         for (int i = 0; i < NCD; ++i) v = fma(gr[i], dcd[i], v);
         atomicAdd(&jab_s[r], 2.0 * sq[q] * v);
       }
-      for (int t = tid; t < QB * NCD; t += blockDim.x) {          // J[c,d] += 2s sum_ab g D[a,b]
+      for (int t = tid; t < nj * QB * NCD; t += blockDim.x) {     // J[c,d] += 2s sum_ab g D[a,b]
         const int q = t / NCD, r = t % NCD;
         if (!qi[q * 8 + 6]) continue;
         const double *g = Z + (size_t)q * NG + r;
@@ -328,7 +348,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         for (int i = 0; i < NAB; ++i) v = fma(g[i * NCD], dab_s[i], v);
         atomic_add(jp_elem(A, ck, qi[q * 8 + 1], r), 2.0 * sq[q] * v);
       }
-      for (int t = tid; t < QB * NA * NC; t += blockDim.x) {      // K[a,c] += s sum_bd g D[b,d]
+      for (int t = tid; t < nk * QB * NA * NC; t += blockDim.x) { // K[a,c] += s sum_bd g D[b,d]
         const int q = t / (NA * NC), a = (t / NC) % NA, c = t % NC;
         if (!qi[q * 8 + 6]) continue;
         const double *g = Z + (size_t)q * NG + a * NB * NCD + c * ND;
@@ -337,9 +357,9 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
 #pragma unroll
         for (int i = 0; i < NB * ND; ++i) v = fma(g[(i / ND) * NCD + i % ND], dbd[i], v);
         const int oc = A.pairs[qi[q * 8 + 1]].ca;
-        k_update<KLDS>(Krow, Km, nc, a, oa + a, oc + c, sq[q] * v);
+        k_update<KLDS>(Krow, Km, nc, nc, a, oa + a, oc + c, oc + c, sq[q] * v);
       }
-      for (int t = tid; t < QB * NA * ND; t += blockDim.x) {      // K[a,d] += s sum_bc g D[b,c]
+      for (int t = tid; t < nk * QB * NA * ND; t += blockDim.x) { // K[a,d] += s sum_bc g D[b,c]
         const int q = t / (NA * ND), a = (t / ND) % NA, d = t % ND;
         if (!qi[q * 8 + 6]) continue;
         const double *g = Z + (size_t)q * NG + a * NB * NCD + d;
@@ -348,9 +368,9 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
 #pragma unroll 16
         for (int i = 0; i < NB * NC; ++i) v = fma(g[(i / NC) * NCD + (i % NC) * ND], dbc[i], v);
         const int od = A.pairs[qi[q * 8 + 1]].cb;
-        k_update<KLDS>(Krow, Km, nc, a, oa + a, od + d, sq[q] * v);
+        k_update<KLDS>(Krow, Km, nc, nc, a, oa + a, od + d, od + d, sq[q] * v);
       }
-      for (int t = tid; t < QB * NB * NC; t += blockDim.x) {      // K[b,c] += s sum_ad g D[a,d]
+      for (int t = tid; t < nk * QB * NB * NC; t += blockDim.x) { // K[b,c] += s sum_ad g D[a,d]
         const int q = t / (NB * NC), b = (t / NC) % NB, c = t % NC;
         if (!qi[q * 8 + 6]) continue;
         const double *g = Z + (size_t)q * NG + b * NCD + c * ND;
@@ -359,9 +379,9 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
 #pragma unroll 16
         for (int i = 0; i < NA * ND; ++i) v = fma(g[(i / ND) * NB * NCD + i % ND], dad[i], v);
         const int oc = A.pairs[qi[q * 8 + 1]].ca;
-        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, oc + c, sq[q] * v);
+        k_update<KLDS>(Krow, Km, nc, nc, NA + b, ob + b, oc + c, oc + c, sq[q] * v);
       }
-      for (int t = tid; t < QB * NB * ND; t += blockDim.x) {      // K[b,d] += s sum_ac g D[a,c]
+      for (int t = tid; t < nk * QB * NB * ND; t += blockDim.x) { // K[b,d] += s sum_ac g D[a,c]
         const int q = t / (NB * ND), b = (t / ND) % NB, d = t % ND;
         if (!qi[q * 8 + 6]) continue;
         const double *g = Z + (size_t)q * NG + b * NCD + d;
@@ -370,7 +390,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
 #pragma unroll 16
         for (int i = 0; i < NA * NC; ++i) v = fma(g[(i / NC) * NB * NCD + (i % NC) * ND], dac[i], v);
         const int od = A.pairs[qi[q * 8 + 1]].cb;
-        k_update<KLDS>(Krow, Km, nc, NA + b, ob + b, od + d, sq[q] * v);
+        k_update<KLDS>(Krow, Km, nc, nc, NA + b, ob + b, od + d, od + d, sq[q] * v);
       }
       __syncthreads();
       continue;
@@ -381,6 +401,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     // and K[b,d] in LDS per (b, cd), summed over d or c afterwards (no two lanes of a wave add
     // to the same address). The per-quartet sums are flushed below.
     const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const bool wj = A.want & 1, wk = A.want & 2;
     constexpr int RB = NB * CH <= 32 ? NB : 4;
     for (int q = 0; q < QB; ++q) {
       if (!qi[q * 8 + 6]) continue;
@@ -434,12 +455,16 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
             for (int h = 0; h < CH; ++h) {
               if (!on[h]) continue;
               const double x = xs[i][h];
-              vab = fma(x, dcd[h], vab);
-              jcda[h] = fma(x, dab, jcda[h]);
-              kacs[h] = fma(x, Dbd[b * ND + dd[h]], kacs[h]);
-              kads[h] = fma(x, Dbc[b * NC + cc[h]], kads[h]);
-              atomicAdd(&pbcq[b * NCD + h * 64 + lane], x * dad[h]);
-              atomicAdd(&pbdq[b * NCD + h * 64 + lane], x * dac[h]);
+              if (wj) {
+                vab = fma(x, dcd[h], vab);
+                jcda[h] = fma(x, dab, jcda[h]);
+              }
+              if (wk) {
+                kacs[h] = fma(x, Dbd[b * ND + dd[h]], kacs[h]);
+                kads[h] = fma(x, Dbc[b * NC + cc[h]], kads[h]);
+                atomicAdd(&pbcq[b * NCD + h * 64 + lane], x * dad[h]);
+                atomicAdd(&pbdq[b * NCD + h * 64 + lane], x * dac[h]);
+              }
             }
             vr[b] = vab;
           }
@@ -494,22 +519,22 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       const double s = sq[q];
       const int oc = ket.ca, od = ket.cb;
       if (r < NA * NC) {                                // K[a,c] += s sum_bd g D[b,d]
-        k_update<KLDS>(Krow, Km, nc, r / NC, oa + r / NC, oc + r % NC, s * v);
+        k_update<KLDS>(Krow, Km, nc, nc, r / NC, oa + r / NC, oc + r % NC, oc + r % NC, s * v);
         continue;
       }
       r -= NA * NC;
       if (r < NA * ND) {                                // K[a,d] += s sum_bc g D[b,c]
-        k_update<KLDS>(Krow, Km, nc, r / ND, oa + r / ND, od + r % ND, s * v);
+        k_update<KLDS>(Krow, Km, nc, nc, r / ND, oa + r / ND, od + r % ND, od + r % ND, s * v);
         continue;
       }
       r -= NA * ND;
       if (r < NB * NC) {                                // K[b,c] += s sum_ad g D[a,d]
-        k_update<KLDS>(Krow, Km, nc, NA + r / NC, ob + r / NC, oc + r % NC, s * v);
+        k_update<KLDS>(Krow, Km, nc, nc, NA + r / NC, ob + r / NC, oc + r % NC, oc + r % NC, s * v);
         continue;
       }
       r -= NB * NC;
       if (r < NB * ND) {                                // K[b,d] += s sum_ac g D[a,c]
-        k_update<KLDS>(Krow, Km, nc, NA + r / ND, ob + r / ND, od + r % ND, s * v);
+        k_update<KLDS>(Krow, Km, nc, nc, NA + r / ND, ob + r / ND, od + r % ND, od + r % ND, s * v);
         continue;
       }
       r -= NB * ND;                                     // J[c,d] += 2s sum_ab g D[a,b]
@@ -556,7 +581,7 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
     // contributing lane)
     auto kadd = [&](int q, int r, int grow, int lc, int gcol, double v) {
       if constexpr (KLDS)
-        k_update<true>(Krow, Km, nc, r, grow, gcol, v);
+        k_update<true>(Krow, Km, nc, nc, r, grow, gcol, gcol, v);
       else
         atomicAdd(&kq[q * C::KQ + r * (NC + ND) + lc], v);
     };
@@ -570,14 +595,17 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
       team2_ket<LA, LB, LC, LD>(Y, geo, q, cd, g);
       const int c = cd / ND, d = cd % ND;
       const int cc = ket.ca + c, dd = ket.cb + d;
-      const double dcd = Dm[(size_t)cc * nc + dd];
-      double vj = 0.0;
+      if (A.want & 1) {
+        const double dcd = Dm[(size_t)cc * nc + dd];
+        double vj = 0.0;
 #pragma unroll
-      for (int ab = 0; ab < NA * NB; ++ab) {
-        jab[ab] = fma(2.0 * s * dcd, g[ab], jab[ab]);
-        vj = fma(g[ab], Dm[(size_t)(oa + ab / NB) * nc + ob + ab % NB], vj);
+        for (int ab = 0; ab < NA * NB; ++ab) {
+          jab[ab] = fma(2.0 * s * dcd, g[ab], jab[ab]);
+          vj = fma(g[ab], Dm[(size_t)(oa + ab / NB) * nc + ob + ab % NB], vj);
+        }
+        atomic_add(jp_elem(A, ck, ki, cd), 2.0 * s * vj);
       }
-      atomic_add(jp_elem(A, ck, ki, cd), 2.0 * s * vj);
+      if (!(A.want & 2)) continue;
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         double kc = 0.0, kd = 0.0;
@@ -796,16 +824,22 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
 template <int LA, int LB, int LC, int LD>
 constexpr int cls_block() { return team_block<LA, LB, LC, LD>(); }
 
-// Dynamic LDS: jab_s NA*NB (padded to even) | team pool (team classes).
-template <int LA, int LB, int LC, int LD>
+// Dynamic LDS: jab_s NA*NB (padded to even) | team pool (team classes) or, with KL (lane
+// bodies), the unit's exchange rows K[a,:], K[b,:] compacted to the columns of the ket class's
+// momenta ((NA+NB) x A.kw), flushed once per unit with one global atomic per nonzero element.
+template <int LA, int LB, int LC, int LD, bool KL = false>
 __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB), ck = pair_class(LC, LD);
+  static_assert(!KL || !use_team<LA, LB, LC, LD>(), "compacted LDS rows are for the lane bodies");
   extern __shared__ double smem[];
   __shared__ int s_unit;
   double *jab_s = smem;
   double *pool = smem + ((NA * NB + 1) & ~1);
+  double *Krow = pool;
   const int nunits = min(*A.nunits, A.units_cap);
   const int tid = threadIdx.x;
+  if constexpr (KL)   // the rows start at zero; each unit's flush puts back the zeros it reads
+    for (int t = tid; t < (NA + NB) * A.kw; t += blockDim.x) Krow[t] = 0.0;
   for (;;) {
     if (tid == 0) s_unit = atomicAdd(A.next, 1);
     for (int t = tid; t < NA * NB; t += blockDim.x) jab_s[t] = 0.0;
@@ -841,6 +875,37 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
                                                 jab_s, pool, jab);
         }
         jab_reduce<NA * NB>(jab, jab_s);
+      } else if constexpr (KL) {
+        const Pair &bra = A.pairs[bi];
+        const int m = bra.mol;
+        const int *lseg = A.lseg + m * 6;
+        const int ncl = lseg[LC + 1] - lseg[LC];
+        const int kw = ncl + (LC != LD ? lseg[LD + 1] - lseg[LD] : 0);   // this molecule's row length
+        const int kdofs = LC != LD ? ncl : 0;
+        double jab[NA * NB];
+#pragma unroll
+        for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
+        if (cnt)
+          jk_small_body<LA, LB, LC, LD, true, double, true>(A, bi, cls_kets + A.segoff[sg], cnt, Krow, jab, 0, kdofs,
+                                                            kw);
+        if (cnt32)
+          jk_small_body<LA, LB, LC, LD, true, float, true>(A, bi, cls_kets32 + A.segoff32[sg], cnt32, Krow, jab, 0,
+                                                           kdofs, kw);
+        jab_reduce<NA * NB>(jab, jab_s);
+        __syncthreads();
+        const int nc = A.mnc[m];
+        double *Km = A.Kc + A.mbase[m];
+        const int *cols = A.lcols + A.cbase[m];
+        for (int t = tid; t < (NA + NB) * kw; t += blockDim.x) {
+          const double v = Krow[t];
+          if (v != 0.0) {
+            Krow[t] = 0.0;
+            const int r = t / kw, j = t % kw;
+            const int col = cols[j < ncl ? lseg[LC] + j : lseg[LD] + (j - ncl)];
+            const int row = r < NA ? bra.ca + r : bra.cb + (r - NA);
+            atomic_add(&Km[(size_t)row * nc + col], v);
+          }
+        }
       } else {
         double jab[NA * NB];
 #pragma unroll

@@ -13,15 +13,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("JK_LIB", os.path.join(_HERE, "libjk.so"))
 
-JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE, JK_ENODEV = 0, -1, -2, -3, -4, -5
+JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE, JK_ENODEV, JK_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
 JK_FP64, JK_MIXED = 0, 1
 
 # every symbol declared in include/jk.h
-EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_build", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
+EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_plan_check", "jk_grad", "jk_build", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
            "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_rys_closed", "jk_rys_grid", "jk_batch_create",
-           "jk_batch_offsets", "jk_batch_execute", "jk_batch_stats", "jk_batch_graph_info", "jk_batch_destroy",
+           "jk_batch_offsets", "jk_batch_execute", "jk_batch_check", "jk_batch_stats", "jk_batch_graph_info", "jk_batch_destroy",
            "jk_last_error"]
-JK_FLAG_PROFILE, JK_FLAG_GRAPH, JK_FLAG_TUNE = 1, 2, 4
+JK_FLAG_PROFILE, JK_FLAG_GRAPH, JK_FLAG_TUNE, JK_FLAG_J_ONLY, JK_FLAG_K_ONLY = 1, 2, 4, 8, 16
 
 
 class JKError(RuntimeError):
@@ -39,7 +39,7 @@ class Basis(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("thresh", ctypes.c_double), ("precision", ctypes.c_int), ("fp32_cutoff", ctypes.c_double),
-                ("flags", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+                ("flags", ctypes.c_int), ("tune_cache", ctypes.c_char_p), ("dmax", ctypes.c_double)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -53,7 +53,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("kept_quartets", ctypes.c_longlong), ("candidate_quartets", ctypes.c_longlong),
                 ("kept_fp32", ctypes.c_longlong), ("prim_quartets", ctypes.c_longlong),
                 ("npairs_kept", ctypes.c_int), ("nao", ctypes.c_int), ("nao_cart", ctypes.c_int),
-                ("nshell", ctypes.c_int), ("plan_ms", ctypes.c_double)]
+                ("nshell", ctypes.c_int), ("plan_ms", ctypes.c_double), ("overflow", ctypes.c_int),
+                ("list_capacity", ctypes.c_longlong)]
 
 
 _lib = None
@@ -64,11 +65,16 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2407_09700_amd.build")
+        # PyTorch first: the library then binds to the HIP runtime PyTorch loaded (one runtime
+        # per process; loaded the other way round, PyTorch found no GPU)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         L.jk_plan_create.argtypes = [ctypes.POINTER(Basis), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                      ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.jk_plan_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.jk_plan_check.argtypes = [vp]
+        L.jk_grad.argtypes = [vp, vp, vp, vp]
         L.jk_build.argtypes = [ctypes.POINTER(Basis), ctypes.POINTER(ctypes.c_double), ctypes.c_int, vp,
                                ctypes.c_double, vp, vp, ctypes.POINTER(Opts), vp]
         L.jk_plan_destroy.argtypes = [vp]
@@ -88,6 +94,7 @@ def lib():
                                       ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.jk_batch_offsets.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]
         L.jk_batch_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.jk_batch_check.argtypes = [vp]
         L.jk_batch_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.jk_batch_graph_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(ctypes.c_int)]
@@ -150,14 +157,15 @@ class BasisArrays:
 
 
 def make_opts(thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6, profile=False, graph=False, tune=False,
-              tune_cache=None):
+              tune_cache=None, want="jk", dmax=0.0):
     flags = (JK_FLAG_PROFILE if profile else 0) | (JK_FLAG_GRAPH if graph else 0) | (JK_FLAG_TUNE if tune else 0)
+    flags |= {"jk": 0, "j": JK_FLAG_J_ONLY, "k": JK_FLAG_K_ONLY}[want]
     return Opts(float(thresh), int(precision), float(fp32_cutoff), flags,
-                None if tune_cache is None else os.fsencode(tune_cache))
+                None if tune_cache is None else os.fsencode(tune_cache), float(dmax))
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(None if t is None else t.data_ptr())
 
 
 def _stream(stream):
@@ -167,14 +175,32 @@ def _stream(stream):
     return ctypes.c_void_p(stream)
 
 
+def build(mol, D, thresh=None, J=None, K=None, stream=None, **opts):
+    """One-shot build (jk_build). D, J, K: torch float64 CUDA tensors, nao x nao. Waits for
+    the build."""
+    import torch
+    basis = BasisArrays.from_molecule(mol)
+    coords = np.ascontiguousarray(mol.coords, np.float64)
+    th = mol.thresh if thresh is None else thresh
+    o = make_opts(th, **opts)
+    if J is None:
+        J = torch.empty_like(D)
+    if K is None:
+        K = torch.empty_like(D)
+    check(lib().jk_build(ctypes.byref(basis.struct), coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(coords.shape[0]),
+             _ptr(D), float(th), _ptr(J), _ptr(K), ctypes.byref(o), _stream(stream)))
+    return J, K
+
+
 class Plan:
     """A J/K plan for one molecule. D, J, K are torch float64 CUDA tensors (nao x nao)."""
 
     def __init__(self, coords, basis: BasisArrays, thresh=1e-12, precision=JK_FP64, fp32_cutoff=1e-6, profile=False,
-                 graph=False, tune=False, tune_cache=None):
+                 graph=False, tune=False, tune_cache=None, want="jk", dmax=0.0):
         self.basis = basis
+        self.want = want
         self.coords = np.ascontiguousarray(coords, np.float64)
-        self.opts = make_opts(thresh, precision, fp32_cutoff, profile, graph, tune, tune_cache)
+        self.opts = make_opts(thresh, precision, fp32_cutoff, profile, graph, tune, tune_cache, want, dmax)
         h = ctypes.c_void_p()
         check(lib().jk_plan_create(ctypes.byref(basis.struct),
                                    self.coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -189,16 +215,35 @@ class Plan:
         return cls(mol.coords, BasisArrays.from_molecule(mol), mol.thresh if thresh is None else thresh, **kw)
 
     def execute(self, D, J=None, K=None, stream=None):
+        """Enqueue a build (returns without waiting). A J-only plan returns (J, None), a
+        K-only plan (None, K)."""
         import torch
         assert D.dtype == torch.float64 and D.is_cuda and D.is_contiguous() and D.shape == (self.nao, self.nao)
-        if J is None:
+        if J is None and "j" in self.want:
             J = torch.empty_like(D)
-        if K is None:
+        if K is None and "k" in self.want:
             K = torch.empty_like(D)
         for t in (J, K):
-            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.shape == (self.nao, self.nao)
+            assert t is None or (t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+                                 and t.shape == (self.nao, self.nao))
         check(lib().jk_plan_execute(self.h, _ptr(D), _ptr(J), _ptr(K), _stream(stream)))
         return J, K
+
+    def check(self):
+        """Wait for the last build; raises JKError(JK_EOVERFLOW) if its work lists overflowed
+        (the plan has then grown them and a new execute completes)."""
+        check(lib().jk_plan_check(self.h))
+
+    def grad(self, D, out=None, stream=None):
+        """Enqueue the nuclear gradient of tr(D (J - K/2)) with D fixed; returns the natom x 3
+        tensor (valid after the stream synchronises)."""
+        import torch
+        assert D.dtype == torch.float64 and D.is_cuda and D.is_contiguous() and D.shape == (self.nao, self.nao)
+        if out is None:
+            out = torch.empty((self.coords.shape[0], 3), dtype=torch.float64, device=D.device)
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous() and out.numel() == 3 * self.coords.shape[0]
+        check(lib().jk_grad(self.h, _ptr(D), _ptr(out), _stream(stream)))
+        return out
 
     def eri_tensor(self, stream=None):
         import torch
@@ -282,6 +327,9 @@ class Batch:
             assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() == tot
         check(lib().jk_batch_execute(self.h, _ptr(D), _ptr(J), _ptr(K), _stream(stream)))
         return J, K
+
+    def check(self):
+        check(lib().jk_batch_check(self.h))
 
     def stats(self):
         s = Stats()

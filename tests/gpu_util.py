@@ -9,16 +9,16 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_jk(mol, thresh=None, D=None, repeat=1):
+def gpu_jk(mol, thresh=None, D=None, repeat=1, want="jk"):
     import torch
     from paper_2407_09700_amd import jk
-    plan = jk.Plan.from_molecule(mol, thresh=thresh)
+    plan = jk.Plan.from_molecule(mol, thresh=thresh, want=want)
     Dt = torch.from_numpy(np.ascontiguousarray(mol.D if D is None else D)).cuda()
     out = []
     for _ in range(repeat):
         J, K = plan.execute(Dt)
-        torch.cuda.synchronize()
-        out.append((J.cpu().numpy(), K.cpu().numpy()))
+        plan.check()
+        out.append((None if J is None else J.cpu().numpy(), None if K is None else K.cpu().numpy()))
     stats = plan.stats()
     plan.close()
     return (out if repeat > 1 else out[0]), stats

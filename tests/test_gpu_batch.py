@@ -13,12 +13,11 @@ TOL = 1e-10
 
 
 def _run_batch(mols, Ds=None, **kw):
-    import torch
     from paper_2407_09700_amd import jk
     b = jk.Batch(mols, **kw)
     D = b.pack([m.D for m in mols] if Ds is None else Ds)
     J, K = b.execute(D)
-    torch.cuda.synchronize()
+    b.check()
     Js = [x.cpu().numpy() for x in b.unpack(J)]
     Ks = [x.cpu().numpy() for x in b.unpack(K)]
     return b, Js, Ks
@@ -57,18 +56,31 @@ def test_graph_replay_and_overflow_rerecord():
     e = jk.Batch(mols, graph=False)
     D1 = g.pack([m.D for m in mols])
     rng = np.random.default_rng(11)
-    # the graph is recorded for a tiny density (few quartets pass the density-weighted
-    # screen); the full density then needs a longer work list than the recorded one
+    # the lists are sized for a tiny density (few quartets pass the density-weighted screen);
+    # the full density then needs longer lists than the recorded graph holds
     D0 = D1 * 1e-7
     D2 = g.pack([m.D + 0.1 * (lambda a: a + a.T)(rng.normal(size=m.D.shape)) for m in mols])
     J = torch.empty_like(D1)
     K = torch.empty_like(D1)
     Dbuf = torch.empty_like(D1)      # one input buffer: the recorded graph reads it in place
+    overflows = []
     for step, D in enumerate([D0, D0, D1, D1, D2]):
         Dbuf.copy_(D)
         g.execute(Dbuf, J, K)
+        try:
+            g.check()
+        except jk.JKError as err:    # the graph's lists were too short: grown, run again
+            assert err.code == jk.JK_EOVERFLOW
+            overflows.append(step)
+            g.execute(Dbuf, J, K)
+            g.check()
         Je, Ke = e.execute(D)
-        torch.cuda.synchronize()
+        try:
+            e.check()
+        except jk.JKError as err:
+            assert err.code == jk.JK_EOVERFLOW
+            Je, Ke = e.execute(D)
+            e.check()
         scale = max(1.0, float(Je.abs().max()), float(Ke.abs().max()))
         dj = float((J - Je).abs().max()) / scale
         dk = float((K - Ke).abs().max()) / scale
@@ -76,13 +88,16 @@ def test_graph_replay_and_overflow_rerecord():
         say(f"[graph] step {step}: rel |dJ|={dj:.2e} rel |dK|={dk:.2e} {info}")
         assert dj <= 1e-12 and dk <= 1e-12
     info = g.graph_info()
-    # step 0 records, step 1 replays, step 2 overflows (eager redo + new recording),
-    # steps 3 and 4 replay
-    assert info["recorded"] and info["replays"] == 3 and info["rerecords"] == 1
+    # step 0 sizes and records, step 1 replays, step 2 replays and overflows (lists grown, the
+    # graph recorded again), step 3 replays
+    say(f"[graph] overflows at steps {overflows}")
+    assert overflows and overflows[0] == 2
+    assert info["recorded"] and info["replays"] >= 3 and info["rerecords"] == len(overflows)
     # new output buffers: the graph is recorded again for them
     J2, K2 = g.execute(D2)
+    g.check()
     Je, Ke = e.execute(D2)
-    torch.cuda.synchronize()
+    e.check()
     assert float((J2 - Je).abs().max()) <= 1e-12 and float((K2 - Ke).abs().max()) <= 1e-12
     g.close()
     e.close()

@@ -11,14 +11,19 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10       # max-abs bound on J and K for the FP64 path
 
 
-def _check(mol, thresh=None, tag=""):
+def _check(mol, thresh=None, tag="", want="jk", same_kept=True):
     tau = mol.thresh if thresh is None else thresh
-    say(f"[{tag}] nbf={mol.nbf} nshell={mol.nshell} tau={tau}")
-    (J, K), st = gpu_jk(mol, thresh=tau)
-    Jo, Ko = oracle.Oracle(mol).jk(tau=tau)
-    dj, dk = maxabs(J, Jo), maxabs(K, Ko)
-    say(f"[{tag}] max|dJ|={dj:.3e} max|dK|={dk:.3e} max|J|={np.max(np.abs(Jo)):.3e} stats={st}")
+    say(f"[{tag}] nbf={mol.nbf} nshell={mol.nshell} tau={tau} want={want}")
+    (J, K), st = gpu_jk(mol, thresh=tau, want=want)
+    o = oracle.Oracle(mol)
+    Jo, Ko = o.jk(tau=tau, want=want)
+    dj = maxabs(J, Jo) if "j" in want else 0.0
+    dk = maxabs(K, Ko) if "k" in want else 0.0
+    say(f"[{tag}] max|dJ|={dj:.3e} max|dK|={dk:.3e} max|J|={np.max(np.abs(Jo)):.3e} kept gpu "
+        f"{st['kept_quartets']} oracle {o.kept} stats={st}")
     assert dj <= TOL and dk <= TOL
+    if same_kept:
+        assert st["kept_quartets"] == o.kept
     return J, K
 
 
@@ -107,18 +112,125 @@ def _sampled(mol, pairs, tag):
     assert worst <= TOL
 
 
-def test_cfg2_full_size_sampled():
-    mol = synth.make_config(2)
-    # shells per atom: s6 s1 s1 p3 p1 d1 -> shell index 6*atom + k
-    _sampled(mol, [(0, 0), (6 * 10 + 3, 6 * 2 + 0), (6 * 40 + 5, 6 * 40 + 4), (6 * 63 + 2, 6 * 17 + 1),
-                   (6 * 33 + 5, 6 * 5 + 5)], "cfg2 full")
+def test_cfg2_full_size():
+    # the whole 64-atom molecule (896 AOs) against the oracle's full build, and the kept counts
+    _check(synth.make_config(2), tag="cfg2 full")
 
 
-def test_cfg3_full_size_sampled():
+def test_cfg3_full_size_async_and_sampled():
+    """The 32-atom g molecule at full size. The plan is sized from a density bound, so the
+    execute returns before the build has run (the stream is still busy); then g-g, f-f, d-d,
+    g-f and mixed blocks are compared with oracle blocks computed one by one."""
+    import time
+    import torch
+    from paper_2407_09700_amd import jk
     mol = synth.make_config(3)
+    o = oracle.Oracle(mol)
+    I, P = o.screen_tables()
+    plan = jk.Plan.from_molecule(mol, dmax=2.0 * float(P.max()))
+    Dt = torch.from_numpy(mol.D).cuda()
+    torch.cuda.synchronize()
+    t = time.time()
+    J, K = plan.execute(Dt)
+    t_ret = time.time() - t
+    busy = not torch.cuda.current_stream().query()
+    torch.cuda.synchronize()
+    t_all = time.time() - t
+    plan.check()
+    st = plan.stats()
+    plan.close()
+    say(f"[cfg3 full] execute returned after {t_ret * 1e3:.2f} ms, stream busy then: {busy}, build "
+        f"{t_all:.2f} s, kept {st['kept_quartets']}")
+    assert busy and t_ret < 0.1 * t_all
+    J, K = J.cpu().numpy(), K.cpu().numpy()
     # shells per atom: s s s s p p p d d f g -> 11 per atom
-    _sampled(mol, [(0, 0), (11 * 7 + 4, 11 * 3 + 1), (11 * 20 + 7, 11 * 20 + 0), (11 * 31 + 9, 11 * 2 + 3)],
-             "cfg3 full")
+    pairs = [(11 * 12 + 10, 11 * 12 + 10), (11 * 5 + 10, 11 * 20 + 10), (11 * 31 + 9, 11 * 8 + 9),
+             (11 * 7 + 7, 11 * 22 + 8), (11 * 3 + 10, 11 * 3 + 9), (11 * 7 + 4, 11 * 3 + 1), (0, 0)]
+    worst = 0.0
+    for si, sj in pairs:
+        t = time.time()
+        Jb, Kb = o.jk_block(si, sj, I=I, P=P)
+        sl_i = slice(o.off[si], o.off[si + 1])
+        sl_j = slice(o.off[sj], o.off[sj + 1])
+        dj, dk = maxabs(J[sl_i, sl_j], Jb), maxabs(K[sl_i, sl_j], Kb)
+        worst = max(worst, dj, dk)
+        say(f"[cfg3 full] block ({si},{sj}) l=({mol.shell_l[si]},{mol.shell_l[sj]}) |dJ|={dj:.2e} |dK|={dk:.2e} "
+            f"max|J|={np.max(np.abs(Jb)):.2e} max|K|={np.max(np.abs(Kb)):.2e} oracle {time.time() - t:.1f}s")
+    assert worst <= TOL
+
+
+def _golden_cfg4():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg4_oracle.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cfg4_full_size_vs_oracle_fixture(prec):
+    """The 256-atom molecule (3584 AOs) against the oracle's full build, stored by
+    tests/golden/make_oracle_fixtures.py: kept count, energy and sampled blocks. FP64 is held
+    to the 1e-10 bar; mixed precision (FP32 below a bound of 1e-6) reports its energy error."""
+    import torch
+    from paper_2407_09700_amd import jk
+    g = _golden_cfg4()
+    mol = synth.make_config(4)
+    plan = jk.Plan.from_molecule(mol, precision=jk.JK_MIXED if prec == "mixed" else jk.JK_FP64, fp32_cutoff=1e-6)
+    Dt = torch.from_numpy(mol.D).cuda()
+    J, K = plan.execute(Dt)
+    plan.check()
+    st = plan.stats()
+    plan.close()
+    E = float((Dt * (J - 0.5 * K)).sum())
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    o = oracle.Oracle(mol)
+    worst = 0.0
+    for b in g["blocks"]:
+        si, sj = b["si"], b["sj"]
+        sl_i = slice(o.off[si], o.off[si + 1])
+        sl_j = slice(o.off[sj], o.off[sj + 1])
+        worst = max(worst, maxabs(J[sl_i, sl_j], np.array(b["J"])), maxabs(K[sl_i, sl_j], np.array(b["K"])))
+    dE = abs(E - g["E"])
+    say(f"[cfg4 {prec}] kept gpu {st['kept_quartets']} oracle {g['kept_quartets']} fp32 {st['kept_fp32']} "
+        f"E {E!r} oracle {g['E']!r} |dE| {dE:.3e} worst block diff {worst:.3e}")
+    assert st["kept_quartets"] == g["kept_quartets"]
+    if prec == "fp64":
+        assert worst <= TOL and dE <= 1e-8
+    else:
+        assert st["kept_fp32"] > 0
+        assert worst <= 1e-8 and dE <= 1e-6
+
+
+@pytest.mark.parametrize("want", ["j", "k"])
+@pytest.mark.parametrize("cfg,natom", [(2, 7), (3, 3)])
+def test_j_only_and_k_only(cfg, natom, want):
+    # one output with its own screen (Coulomb or exchange density blocks) against the oracle
+    # with the same predicate, and the kept counts
+    _check(synth.make_config(cfg, natom=natom), tag=f"cfg{cfg} {natom} atoms {want}-only", want=want)
+
+
+def test_overflow_reported_and_lists_grow():
+    """A plan sized for a density bound far below the real density keeps too few candidates:
+    the check reports the overflow, the lists grow, and a new execute matches the oracle."""
+    import torch
+    from paper_2407_09700_amd import jk
+    mol = synth.make_config(2, natom=6)
+    plan = jk.Plan.from_molecule(mol, dmax=1e-9)
+    cap0 = plan.stats()["list_capacity"]
+    Dt = torch.from_numpy(mol.D).cuda()
+    J, K = plan.execute(Dt)
+    with pytest.raises(jk.JKError) as e:
+        plan.check()
+    assert e.value.code == jk.JK_EOVERFLOW
+    J, K = plan.execute(Dt)
+    plan.check()
+    st = plan.stats()
+    plan.close()
+    say(f"[overflow] capacity {cap0} -> {st['list_capacity']}, kept {st['kept_quartets']}")
+    assert st["list_capacity"] > cap0 and st["overflow"] == 0
+    Jo, Ko = oracle.Oracle(mol).jk(tau=mol.thresh)
+    assert maxabs(J.cpu().numpy(), Jo) <= TOL and maxabs(K.cpu().numpy(), Ko) <= TOL
 
 
 def test_edge_all_pairs_screened_out():
@@ -149,4 +261,5 @@ def test_edge_negligible_primitive_pairs():
     # the near pair keeps only its more diffuse combinations; the oracle keeps every primitive
     coords = [[0.0, 0.0, 0.0], [12.0, 0.0, 0.0], [1.5, 0.4, 0.0]]
     mol = synth.custom(coords, [(0, 3), (1, 2), (2, 1)], 20.0, 2000.0, pure_from_l=2, nocc=4, seed=31)
-    _check(mol, thresh=0.0, tag="negligible primitive pairs")
+    # the shell pairs without a primitive pair drop out on the GPU only: fewer kept quartets
+    _check(mol, thresh=0.0, tag="negligible primitive pairs", same_kept=False)
