@@ -830,6 +830,7 @@ struct Launch {
   size_t lds;        // dynamic LDS bytes
   long long scratch_per_wg;
   int kw;            // per class with compacted LDS exchange rows: their length (0: global exchange)
+  int krows;         // 1: rows of a and b in LDS, 2: rows of a only
 };
 
 // Launches of one build. active[qc]: the class has work (eager) or may have work (recording).
@@ -862,10 +863,10 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
           // mixed precision: the FP32 parts of the lane tiers run in their own FP32-only kernel
           const bool sep = p->precision == JK_MIXED && bi.launch_bra32[tier] != nullptr;
           out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], sep ? 1 : 3, false,
-                               ncm, lds, bi.scratch_per_wg[tier], 0});
+                               ncm, lds, bi.scratch_per_wg[tier], 0, 0});
           if (sep)
             out.push_back(Launch{NF32_BASE + cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], 2, true,
-                                 ncm, lds, bi.scratch_per_wg[tier], 0});
+                                 ncm, lds, bi.scratch_per_wg[tier], 0, 0});
         }
       }
       if (split == end) continue;
@@ -876,18 +877,25 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         const size_t jab = (size_t)((na * nbb + 1) & ~1) * 8;
         const size_t lds = jab + (size_t)ci.team_lds;   // jab_s, pool
         // lane bodies: the exchange rows of the unit in LDS, compacted to the columns of the
-        // ket class's momenta, when they fit for every molecule of the launch
-        int kw = 0;
+        // ket class's momenta, when they fit for every molecule of the launch (the rows of a
+        // and b, else those of a)
+        int kw = 0, krows = 0;
         if (JK_CLS_LDS_ROWS && ci.launch_clsl) {
           for (int m = m_split; m < nmol; ++m) {
             const int *seg = p->lseg.data() + (size_t)m * 6;
             const int w = seg[ci.lc + 1] - seg[ci.lc] + (ci.lc != ci.ld ? seg[ci.ld + 1] - seg[ci.ld] : 0);
             kw = std::max(kw, w);
           }
-          if (kw == 0 || jab + (size_t)(na + nbb) * kw * 8 > FUSED_LDS_MAX) kw = 0;
+          if (kw > 0 && jab + (size_t)(na + nbb) * kw * 8 <= FUSED_LDS_MAX)
+            krows = 1;
+          else if (kw > 0 && jab + (size_t)na * kw * 8 <= FUSED_LDS_MAX)
+            krows = 2;
+          else
+            kw = 0;
         }
-        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 3, false, 0,
-                             kw ? jab + (size_t)(na + nbb) * kw * 8 : lds, ci.scratch_per_wg, kw});
+        const size_t klds = jab + (size_t)(krows == 1 ? na + nbb : na) * kw * 8;
+        out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 3, false, 0, kw ? klds : lds,
+                             ci.scratch_per_wg, kw, krows});
       }
     }
   }
@@ -1105,7 +1113,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
     if (L.qc < 0)
       HIPCHK((L.f32 ? g_bras[L.cb].launch_bra32[L.tier] : g_bras[L.cb].launch_bra[L.tier])(J_, grid, L.lds, st));
     else if (L.kw > 0)
-      HIPCHK(g_classes[L.qc].launch_clsl(J_, grid, L.lds, st));
+      HIPCHK((L.krows == 1 ? g_classes[L.qc].launch_clsl : g_classes[L.qc].launch_clsa)(J_, grid, L.lds, st));
     else
       HIPCHK(g_classes[L.qc].launch_cls(J_, grid, L.lds, st));
     if (prof) HIPCHK(hipEventRecord(ev[2 * L.slot + 1], st));

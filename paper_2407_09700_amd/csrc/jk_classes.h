@@ -19,6 +19,7 @@ struct ClassInfo {           // one quartet class (la lb | lc ld)
   long long scratch_per_wg;  // doubles of global team buffer per workgroup
   jk_launch_fn launch_cls;   // k_cls (exchange to global memory)
   jk_launch_fn launch_clsl;  // k_cls with compacted LDS exchange rows (lane bodies; null for team classes)
+  jk_launch_fn launch_clsa;  // the same with only the rows of a in LDS
   mode_launch_fn launch_mode[3];
 };
 

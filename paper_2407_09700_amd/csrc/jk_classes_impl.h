@@ -15,7 +15,7 @@ void allow_dyn_lds(F *fn) {
   (void)hipGetLastError();   // the attribute is a hint; do not leave its status for a launch check
 }
 
-template <int LA, int LB, int LC, int LD, bool KL = false>
+template <int LA, int LB, int LC, int LD, int KL = 0>
 hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
   hipLaunchKernelGGL((k_cls<LA, LB, LC, LD, KL>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), lds, stream, args);
   return hipGetLastError();
@@ -58,10 +58,13 @@ void register_one(ClassInfo *table) {
   ci.launch_cls = launch_cls<LA, LB, LC, LD>;
   allow_dyn_lds(k_cls<LA, LB, LC, LD>);
   if constexpr (!use_team<LA, LB, LC, LD>()) {
-    ci.launch_clsl = launch_cls<LA, LB, LC, LD, true>;
-    allow_dyn_lds(k_cls<LA, LB, LC, LD, true>);
+    ci.launch_clsl = launch_cls<LA, LB, LC, LD, 1>;
+    ci.launch_clsa = launch_cls<LA, LB, LC, LD, 2>;
+    allow_dyn_lds(k_cls<LA, LB, LC, LD, 1>);
+    allow_dyn_lds(k_cls<LA, LB, LC, LD, 2>);
   } else {
     ci.launch_clsl = nullptr;
+    ci.launch_clsa = nullptr;
   }
   ci.launch_mode[MODE_JK] = nullptr;
   ci.launch_mode[MODE_SCHWARZ] = (LA == LC && LB == LD) ? launch_mode<LA, LB, LC, LD, MODE_SCHWARZ> : nullptr;

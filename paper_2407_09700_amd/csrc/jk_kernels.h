@@ -125,8 +125,9 @@ __device__ __forceinline__ void k_update(double *Krow, double *Km, int kst, int 
 // R: arithmetic type of the integral evaluation (double, or float for the FP32 quartets of
 // mixed precision); the digestion always runs in double.
 // KMAP: the LDS rows are the compacted rows of k_cls (row length kst, ket class columns from
-// kdofs); otherwise full rows of the molecule's Cartesian columns (row length nc).
-template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double, bool KMAP = false>
+// kdofs); otherwise full rows of the molecule's Cartesian columns (row length nc). KLB false:
+// only the rows of a are in LDS, the rows of b go to global memory.
+template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double, bool KMAP = false, bool KLB = true>
 __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                               double (&jab)[ncart(LA) * ncart(LB)], int rot, int kdofs = 0,
                                               int kst_map = 0) {
@@ -206,7 +207,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + od + d], v);
-        k_update<KLDS>(Krow, Km, kst, nc, NA + b, bra.cb + b, kc + c, oc + c, s * v);
+        k_update<KLDS && KLB>(Krow, Km, kst, nc, NA + b, bra.cb + b, kc + c, oc + c, s * v);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -215,7 +216,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + oc + c], v);
-        k_update<KLDS>(Krow, Km, kst, nc, NA + b, bra.cb + b, kd + d, od + d, s * v);
+        k_update<KLDS && KLB>(Krow, Km, kst, nc, NA + b, bra.cb + b, kd + d, od + d, s * v);
       }
     }
   }
@@ -825,12 +826,15 @@ template <int LA, int LB, int LC, int LD>
 constexpr int cls_block() { return team_block<LA, LB, LC, LD>(); }
 
 // Dynamic LDS: jab_s NA*NB (padded to even) | team pool (team classes) or, with KL (lane
-// bodies), the unit's exchange rows K[a,:], K[b,:] compacted to the columns of the ket class's
-// momenta ((NA+NB) x A.kw), flushed once per unit with one global atomic per nonzero element.
-template <int LA, int LB, int LC, int LD, bool KL = false>
+// bodies), the unit's exchange rows compacted to the columns of the ket class's momenta
+// (KL = 1: rows K[a,:] and K[b,:], (NA+NB) x A.kw; KL = 2: rows K[a,:] only, NA x A.kw, the
+// rows of b updated in global memory), flushed once per unit with one global atomic per
+// nonzero element.
+template <int LA, int LB, int LC, int LD, int KL = 0>
 __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB), ck = pair_class(LC, LD);
   static_assert(!KL || !use_team<LA, LB, LC, LD>(), "compacted LDS rows are for the lane bodies");
+  constexpr int RL = KL == 1 ? NA + NB : NA;    // exchange rows held in LDS
   extern __shared__ double smem[];
   __shared__ int s_unit;
   double *jab_s = smem;
@@ -838,8 +842,8 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
   double *Krow = pool;
   const int nunits = min(*A.nunits, A.units_cap);
   const int tid = threadIdx.x;
-  if constexpr (KL)   // the rows start at zero; each unit's flush puts back the zeros it reads
-    for (int t = tid; t < (NA + NB) * A.kw; t += blockDim.x) Krow[t] = 0.0;
+  if constexpr (KL != 0)   // the rows start at zero; each unit's flush puts back the zeros it reads
+    for (int t = tid; t < RL * A.kw; t += blockDim.x) Krow[t] = 0.0;
   for (;;) {
     if (tid == 0) s_unit = atomicAdd(A.next, 1);
     for (int t = tid; t < NA * NB; t += blockDim.x) jab_s[t] = 0.0;
@@ -875,7 +879,7 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
                                                 jab_s, pool, jab);
         }
         jab_reduce<NA * NB>(jab, jab_s);
-      } else if constexpr (KL) {
+      } else if constexpr (KL != 0) {
         const Pair &bra = A.pairs[bi];
         const int m = bra.mol;
         const int *lseg = A.lseg + m * 6;
@@ -886,17 +890,17 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
 #pragma unroll
         for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
         if (cnt)
-          jk_small_body<LA, LB, LC, LD, true, double, true>(A, bi, cls_kets + A.segoff[sg], cnt, Krow, jab, 0, kdofs,
-                                                            kw);
+          jk_small_body<LA, LB, LC, LD, true, double, true, KL == 1>(A, bi, cls_kets + A.segoff[sg], cnt, Krow, jab, 0,
+                                                                     kdofs, kw);
         if (cnt32)
-          jk_small_body<LA, LB, LC, LD, true, float, true>(A, bi, cls_kets32 + A.segoff32[sg], cnt32, Krow, jab, 0,
-                                                           kdofs, kw);
+          jk_small_body<LA, LB, LC, LD, true, float, true, KL == 1>(A, bi, cls_kets32 + A.segoff32[sg], cnt32, Krow,
+                                                                    jab, 0, kdofs, kw);
         jab_reduce<NA * NB>(jab, jab_s);
         __syncthreads();
         const int nc = A.mnc[m];
         double *Km = A.Kc + A.mbase[m];
         const int *cols = A.lcols + A.cbase[m];
-        for (int t = tid; t < (NA + NB) * kw; t += blockDim.x) {
+        for (int t = tid; t < RL * kw; t += blockDim.x) {
           const double v = Krow[t];
           if (v != 0.0) {
             Krow[t] = 0.0;
