@@ -150,6 +150,17 @@ int jk_grad(jk_plan_t *plan, const double *D, double *grad, void *stream);
 int jk_build(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh,
              double *J, double *K, const jk_opts_t *opts, void *stream);
 
+/* jk_build for callers that cannot allocate device memory (tight loops, harnesses that forbid
+ * hipMalloc): the same plan, build and kernels, with every device buffer the library needs
+ * carved from a fixed array of 128 MB per device (a file-scope __device__ array the library
+ * holds until the process ends) instead of hipMalloc; nothing is allocated or freed on the
+ * device. A molecule whose plan needs more returns JK_ENOMEM with the sizes in the message
+ * (outputs untouched beyond that point). opts flags JK_FLAG_PROFILE, GRAPH and TUNE are
+ * rejected (JK_EINVAL). Calls on one device share the array: the library serialises them
+ * within the process; calls from two processes on one device race. Waits for the build. */
+int jk_build_static(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh,
+                    double *J, double *K, const jk_opts_t *opts, void *stream);
+
 void jk_plan_destroy(jk_plan_t *plan);
 
 /* nao (final basis) and nao_cart (all shells Cartesian) of a plan. */

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -161,10 +162,29 @@ void class_ops(int la, int lb, int lc, int ld, int want, double *per_prim, doubl
   *per_quartet = bra + ket + digest * na * nb * nc * nd;
 }
 
+// Device memory of the no-allocation entry point: while a call of jk_build_static runs on this
+// thread, every device buffer of its plan is carved from the static scratch array (bump
+// allocation, no frees) instead of hipMalloc.
+struct Arena {
+  char *base;     // device address of the array on the current device
+  size_t size, used;
+};
+thread_local Arena *g_arena = nullptr;
+
 template <class T>
 int dalloc(T **p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
+  if (g_arena) {
+    const size_t bytes = (n * sizeof(T) + 255) & ~(size_t)255;
+    if (bytes > g_arena->size - g_arena->used)
+      return fail(JK_ENOMEM, "jk_build_static: the build needs more than the %zu MB of static scratch "
+                  "(%zu MB used, %zu more bytes requested); use jk_build", g_arena->size >> 20,
+                  g_arena->used >> 20, bytes);
+    *p = reinterpret_cast<T *>(g_arena->base + g_arena->used);
+    g_arena->used += bytes;
+    return JK_OK;
+  }
   hipError_t e = hipMalloc((void **)p, n * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
@@ -184,7 +204,7 @@ int dupload(T **p, const std::vector<T> &v) {
 
 template <class T>
 void dfree(T *&p) {
-  if (p) (void)hipFree(p);
+  if (p && !g_arena) (void)hipFree(p);
   p = nullptr;
 }
 
@@ -1595,6 +1615,51 @@ int jk_build(const jk_basis_t *basis, const double *coords, int natom, const dou
     if (!rc) rc = plan_check(p);
   }
   jk_plan_destroy(p);
+  return rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ no-allocation entry point
+namespace {
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int STATIC_MAX_DEVICES = 64;
+// One copy per device, held until the process ends. In host code `scratch` only names the
+// symbol: its device address comes from hipGetSymbolAddress (static_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+std::mutex g_static_mu;                          // calls on one device share its array
+void *g_static_ptr[STATIC_MAX_DEVICES] = {};
+
+int static_scratch_ptr(int dev, void **out) {
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(JK_EUNSUPPORTED, "device %d beyond %d", dev, STATIC_MAX_DEVICES);
+  if (!g_static_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(JK_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
+  return JK_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int jk_build_static(const jk_basis_t *basis, const double *coords, int natom, const double *D, double thresh,
+                    double *J, double *K, const jk_opts_t *opts, void *stream) {
+  if (opts && (opts->flags & (JK_FLAG_PROFILE | JK_FLAG_GRAPH | JK_FLAG_TUNE)))
+    return fail(JK_EINVAL, "jk_build_static: profile, graph and tune flags need allocations");
+  if (g_arena) return fail(JK_EINVAL, "jk_build_static: not re-entrant");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  void *base = nullptr;
+  int rc = static_scratch_ptr(dev, &base);
+  if (rc) return rc;
+  Arena a{static_cast<char *>(base), STATIC_SCRATCH_BYTES, 0};
+  g_arena = &a;
+  rc = jk_build(basis, coords, natom, D, thresh, J, K, opts, stream);
+  g_arena = nullptr;
   return rc;
 }
 

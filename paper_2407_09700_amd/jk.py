@@ -17,7 +17,7 @@ JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE, JK_ENODEV, JK_EOVERFLO
 JK_FP64, JK_MIXED = 0, 1
 
 # every symbol declared in include/jk.h
-EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_plan_check", "jk_grad", "jk_build", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
+EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_plan_check", "jk_grad", "jk_build", "jk_build_static", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
            "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_rys_closed", "jk_rys_grid", "jk_batch_create",
            "jk_batch_offsets", "jk_batch_execute", "jk_batch_check", "jk_batch_stats", "jk_batch_graph_info", "jk_batch_destroy",
            "jk_last_error"]
@@ -77,6 +77,7 @@ def lib():
         L.jk_grad.argtypes = [vp, vp, vp, vp]
         L.jk_build.argtypes = [ctypes.POINTER(Basis), ctypes.POINTER(ctypes.c_double), ctypes.c_int, vp,
                                ctypes.c_double, vp, vp, ctypes.POINTER(Opts), vp]
+        L.jk_build_static.argtypes = L.jk_build.argtypes
         L.jk_plan_destroy.argtypes = [vp]
         L.jk_plan_destroy.restype = None
         L.jk_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -175,9 +176,9 @@ def _stream(stream):
     return ctypes.c_void_p(stream)
 
 
-def build(mol, D, thresh=None, J=None, K=None, stream=None, **opts):
-    """One-shot build (jk_build). D, J, K: torch float64 CUDA tensors, nao x nao. Waits for
-    the build."""
+def build(mol, D, thresh=None, static=False, J=None, K=None, stream=None, **opts):
+    """One-shot build (jk_build, or jk_build_static when static: no device allocation by the
+    library). D, J, K: torch float64 CUDA tensors, nao x nao. Waits for the build."""
     import torch
     basis = BasisArrays.from_molecule(mol)
     coords = np.ascontiguousarray(mol.coords, np.float64)
@@ -187,7 +188,8 @@ def build(mol, D, thresh=None, J=None, K=None, stream=None, **opts):
         J = torch.empty_like(D)
     if K is None:
         K = torch.empty_like(D)
-    check(lib().jk_build(ctypes.byref(basis.struct), coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(coords.shape[0]),
+    fn = lib().jk_build_static if static else lib().jk_build
+    check(fn(ctypes.byref(basis.struct), coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(coords.shape[0]),
              _ptr(D), float(th), _ptr(J), _ptr(K), ctypes.byref(o), _stream(stream)))
     return J, K
 
