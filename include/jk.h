@@ -222,6 +222,15 @@ int jk_rys_closed(int nroots, double T, double *u, double *w);
  * Gauss-Hermite limit; else JK_EINVAL. u, w: HOST arrays of nroots entries (u = t^2). */
 int jk_rys_grid(int nroots, double T, double *u, double *w);
 
+/* One-electron integrals of an SCF around the J/K build, on the host (section 4: they are
+ * evaluated on the CPU): overlap S, kinetic energy T and nuclear attraction V = -sum_C Z_C
+ * (mu|1/|r - R_C||nu) over the shells of `basis` (same conventions as jk_plan_create), in
+ * the final basis, and the nuclear repulsion energy. charges: HOST, natom nuclear charges
+ * (any real values; 0 leaves a centre out of V). S, T, V: HOST nao x nao, OVERWRITTEN;
+ * enuc: HOST scalar. Needs no device. */
+int jk_one_electron(const jk_basis_t *basis, const double *coords, int natom, const double *charges, double *S,
+                    double *T, double *V, double *enuc);
+
 /* ---- Batched build: many independent molecules in one pass.
  * The shell pairs of all molecules share the class work lists and the persistent
  * integral launches (one launch per class group for the whole batch, not per molecule);

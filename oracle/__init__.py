@@ -60,6 +60,8 @@ def lib():
         L.oracle_grad.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, dp, dp, dp, dp, ctypes.c_double,
                                   dp, ctypes.c_int]
         L.oracle_grad.restype = ctypes.c_longlong
+        L.oracle_one_electron.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, dp, dp, dp, dp, dp, dp,
+                                          dp, dp]
         L.oracle_count_kept.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double]
         L.oracle_count_kept.restype = ctypes.c_longlong
         L.oracle_count_kept_want.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int]
@@ -177,6 +179,16 @@ class Oracle:
             raise ValueError("oracle gradient: shells up to l = 3 only")
         self.kept = int(kept)
         return g
+
+    def one_electron(self, charges):
+        """Overlap, kinetic and nuclear-attraction matrices and the nuclear repulsion."""
+        Z = np.ascontiguousarray(charges, np.float64)
+        n = self.nbf
+        S, T, V = (np.zeros((n, n)) for _ in range(3))
+        e = np.zeros(1)
+        b = self._b()
+        lib().oracle_one_electron(b[0], int(self.coords.shape[0]), *b[1:], _p(Z), _p(S), _p(T), _p(V), _p(e))
+        return S, T, V, float(e[0])
 
     def count_kept(self, I, P, tau, want="jk"):
         I = np.ascontiguousarray(I, np.float64)

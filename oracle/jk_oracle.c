@@ -804,6 +804,174 @@ long long oracle_grad(const double *coords, int natom, int nshell, const int *sh
   return kept;
 }
 
+/* ------------------------------------------------------------------ one-electron integrals */
+/* Overlap S, kinetic energy T and nuclear attraction V = -sum_C Z_C (mu|1/|r-C||nu) in the final
+ * basis (the one-electron part of an SCF around the J/K build, paper section 4), by the
+ * Obara-Saika recurrences (Obara & Saika 1986):
+ *   1D overlap: S(0,0) = sqrt(pi/p), S(i+1,j) = PA S(i,j) + (i S(i-1,j) + j S(i,j-1))/(2p),
+ *               S(i,j+1) = PB S(i,j) + (i S(i-1,j) + j S(i,j-1))/(2p), times exp(-ab/p AB^2);
+ *   kinetic:    the ket Gaussian's second derivative, -1/2 [j(j-1) S(i,j-2) - 2b(2j+1) S(i,j)
+ *               + 4b^2 S(i,j+2)] per direction;
+ *   attraction: auxiliary integrals Theta^(m)(e) on the bra centre, Theta^(m)(0) = 2 pi/p K F_m(T),
+ *               Theta^(m)(e+1_i) = PA_i Theta^(m)(e) - PC_i Theta^(m+1)(e)
+ *                                  + e_i/(2p) [Theta^(m)(e-1_i) - Theta^(m+1)(e-1_i)],
+ *               then (a|b+1_i) = (a+1_i|b) + (A_i - B_i)(a|b).
+ * S, T, V: nbf x nbf; *enuc = sum_{A<B} Z_A Z_B / R_AB. */
+static void os_overlap_1d(int imax, int jmax, double PA, double PB, double p, double s00, double out[7][7]) {
+  for (int i = 0; i <= imax; ++i)
+    for (int j = 0; j <= jmax; ++j) out[i][j] = 0.0;
+  out[0][0] = s00;
+  for (int i = 0; i <= imax; ++i)
+    for (int j = 0; j <= jmax; ++j) {
+      if (i == 0 && j == 0) continue;
+      if (i > 0) {
+        double v = PA * out[i - 1][j];
+        if (i > 1) v += (i - 1) * out[i - 2][j] / (2 * p);
+        if (j > 0) v += j * out[i - 1][j - 1] / (2 * p);
+        out[i][j] = v;
+      } else {
+        double v = PB * out[i][j - 1];
+        if (j > 1) v += (j - 1) * out[i][j - 2] / (2 * p);
+        out[i][j] = v;
+      }
+    }
+}
+
+int oracle_one_electron(const double *coords, int natom, int nshell, const int *sh_atom, const int *sh_l,
+                        const int *sh_nprim, const int *sh_off, const int *sh_pure, const double *pexp,
+                        const double *pcoef, const double *tsph, const double *charges, double *S, double *T,
+                        double *V, double *enuc) {
+  init_tables();
+  basis_t B; make_basis(&B, coords, nshell, sh_atom, sh_l, sh_nprim, sh_off, sh_pure, pexp, pcoef, tsph);
+  int *off = (int *)malloc(sizeof(int) * (nshell + 1));
+  ao_offsets(&B, off);
+  const int nbf = off[nshell];
+  /* Cartesian blocks [a][b] of the three operators, then to the final basis */
+  double *cb = (double *)malloc(sizeof(double) * 3 * 15 * 15);
+  double *th = (double *)malloc(sizeof(double) * NCOMP_EMAX * (EMAX + 1));   /* Theta[e][m] */
+  double *e0 = (double *)malloc(sizeof(double) * NCOMP_EMAX);
+  double *x = (double *)malloc(sizeof(double) * NCOMP_EMAX * NCOMP_LMAX);
+  double fin[15 * 15], tmp[15 * 15];
+  for (int i = 0; i < nshell; ++i)
+    for (int j = 0; j <= i; ++j) {
+      const int la = sh_l[i], lb = sh_l[j], na = ncart(la), nb = ncart(lb), E = la + lb;
+      const double *A = coords + 3 * sh_atom[i], *Bc = coords + 3 * sh_atom[j];
+      double AB2 = 0, ABv[3];
+      for (int d = 0; d < 3; ++d) { ABv[d] = A[d] - Bc[d]; AB2 += ABv[d] * ABv[d]; }
+      memset(cb, 0, sizeof(double) * 3 * 15 * 15);
+      for (int pa = 0; pa < sh_nprim[i]; ++pa)
+        for (int pb = 0; pb < sh_nprim[j]; ++pb) {
+          const double a = pexp[sh_off[i] + pa], b = pexp[sh_off[j] + pb];
+          const double cc = pcoef[sh_off[i] + pa] * pcoef[sh_off[j] + pb];
+          const double p = a + b, K = exp(-a * b / p * AB2);
+          double P[3], s1[3][7][7];
+          for (int d = 0; d < 3; ++d) {
+            P[d] = (a * A[d] + b * Bc[d]) / p;
+            os_overlap_1d(la, lb + 2, P[d] - A[d], P[d] - Bc[d], p, sqrt(M_PI / p), s1[d]);
+          }
+          for (int ca = 0; ca < na; ++ca) {
+            const int *ea = g_comp[g_level_start[la] + ca];
+            for (int cbb = 0; cbb < nb; ++cbb) {
+              const int *eb = g_comp[g_level_start[lb] + cbb];
+              double sx[3], tx[3];
+              for (int d = 0; d < 3; ++d) {
+                const int u = ea[d], v = eb[d];
+                sx[d] = s1[d][u][v];
+                double t = -2.0 * b * (2 * v + 1) * s1[d][u][v] + 4.0 * b * b * s1[d][u][v + 2];
+                if (v >= 2) t += v * (v - 1) * s1[d][u][v - 2];
+                tx[d] = -0.5 * t;
+              }
+              cb[ca * nb + cbb] += cc * K * sx[0] * sx[1] * sx[2];
+              cb[225 + ca * nb + cbb] += cc * K * (tx[0] * sx[1] * sx[2] + sx[0] * tx[1] * sx[2] + sx[0] * sx[1] * tx[2]);
+            }
+          }
+          /* nuclear attraction: Theta on the bra centre for |e| <= E, then the transfer */
+          const int ne = g_level_start[E + 1];
+          for (int e = 0; e < ne; ++e) e0[e] = 0.0;
+          for (int c = 0; c < natom; ++c) {
+            if (charges[c] == 0.0) continue;
+            const double *C = coords + 3 * c;
+            double PC[3], PC2 = 0.0, F[EMAX + 2];
+            for (int d = 0; d < 3; ++d) { PC[d] = P[d] - C[d]; PC2 += PC[d] * PC[d]; }
+            oracle_boys(E, p * PC2, F);
+            for (int m = 0; m <= E; ++m) th[0 * (EMAX + 1) + m] = 2.0 * M_PI / p * K * F[m];
+            for (int e = 1; e < ne; ++e) {
+              const int ev[3] = {g_comp[e][0], g_comp[e][1], g_comp[e][2]};
+              const int L = ev[0] + ev[1] + ev[2];
+              const int d = ev[0] > 0 ? 0 : (ev[1] > 0 ? 1 : 2);
+              int em[3] = {ev[0], ev[1], ev[2]};
+              em[d] -= 1;
+              const int ie1 = g_flat[em[0]][em[1]][em[2]];
+              int ie2 = -1;
+              if (em[d] > 0) { int e2[3] = {em[0], em[1], em[2]}; e2[d] -= 1; ie2 = g_flat[e2[0]][e2[1]][e2[2]]; }
+              for (int m = 0; m <= E - L; ++m) {
+                double v = (P[d] - A[d]) * th[ie1 * (EMAX + 1) + m] - PC[d] * th[ie1 * (EMAX + 1) + m + 1];
+                if (ie2 >= 0)
+                  v += em[d] / (2.0 * p) * (th[ie2 * (EMAX + 1) + m] - th[ie2 * (EMAX + 1) + m + 1]);
+                th[e * (EMAX + 1) + m] = v;
+              }
+            }
+            for (int e = g_level_start[la]; e < ne; ++e) e0[e] -= charges[c] * cc * th[e * (EMAX + 1) + 0];
+          }
+          /* (a|b): X[e][b] over b levels 0..lb by (a|b+1_i) = (a+1_i|b) + AB_i (a|b) */
+          for (int e = g_level_start[la]; e < ne; ++e) x[e * NCOMP_LMAX + 0] = e0[e];
+          for (int bL = 1; bL <= lb; ++bL)
+            for (int ib = g_level_start[bL]; ib < g_level_start[bL + 1]; ++ib) {
+              const int bv[3] = {g_comp[ib][0], g_comp[ib][1], g_comp[ib][2]};
+              const int d = bv[0] > 0 ? 0 : (bv[1] > 0 ? 1 : 2);
+              int bm[3] = {bv[0], bv[1], bv[2]};
+              bm[d] -= 1;
+              const int ibm = g_flat[bm[0]][bm[1]][bm[2]];
+              for (int e = g_level_start[la]; e < g_level_start[E - bL + 1]; ++e) {
+                int ep[3] = {g_comp[e][0], g_comp[e][1], g_comp[e][2]};
+                ep[d] += 1;
+                const int iep = g_flat[ep[0]][ep[1]][ep[2]];
+                x[e * NCOMP_LMAX + ib] = x[iep * NCOMP_LMAX + ibm] + ABv[d] * x[e * NCOMP_LMAX + ibm];
+              }
+            }
+          for (int ca = 0; ca < na; ++ca)
+            for (int cbb = 0; cbb < nb; ++cbb)
+              cb[450 + ca * nb + cbb] += x[(g_level_start[la] + ca) * NCOMP_LMAX + g_level_start[lb] + cbb];
+        }
+      /* final basis: transform rows (shell i) and columns (shell j) */
+      const int sh[4] = {i, j, i, i};
+      (void)sh;
+      const double *Ti = (sh_pure[i] && la >= 2) ? tsph_of(&B, la) : NULL;
+      const double *Tj = (sh_pure[j] && lb >= 2) ? tsph_of(&B, lb) : NULL;
+      const int fi = nsph(la, sh_pure[i]), fj = nsph(lb, sh_pure[j]);
+      double *outs[3] = {S, T, V};
+      for (int k = 0; k < 3; ++k) {
+        const double *blk = cb + 225 * k;
+        for (int r = 0; r < fi; ++r)
+          for (int c = 0; c < nb; ++c) {
+            double v = 0.0;
+            if (Ti) { for (int q = 0; q < na; ++q) v += Ti[r * na + q] * blk[q * nb + c]; }
+            else v = blk[r * nb + c];
+            tmp[r * nb + c] = v;
+          }
+        for (int r = 0; r < fi; ++r)
+          for (int c = 0; c < fj; ++c) {
+            double v = 0.0;
+            if (Tj) { for (int q = 0; q < nb; ++q) v += tmp[r * nb + q] * Tj[c * nb + q]; }
+            else v = tmp[r * nb + c];
+            fin[r * fj + c] = v;
+            outs[k][(size_t)(off[i] + r) * nbf + off[j] + c] = v;
+            outs[k][(size_t)(off[j] + c) * nbf + off[i] + r] = v;
+          }
+      }
+    }
+  double e = 0.0;
+  for (int a = 0; a < natom; ++a)
+    for (int b = 0; b < a; ++b) {
+      double r2 = 0.0;
+      for (int d = 0; d < 3; ++d) r2 += (coords[3 * a + d] - coords[3 * b + d]) * (coords[3 * a + d] - coords[3 * b + d]);
+      e += charges[a] * charges[b] / sqrt(r2);
+    }
+  *enuc = e;
+  free(cb); free(th); free(e0); free(x); free(off);
+  return 0;
+}
+
 /* Full ERI tensor in the final basis, out[mu][nu][la][si] (nbf^4, small inputs only). */
 int oracle_eri_tensor(const double *coords, int nshell, const int *sh_atom, const int *sh_l, const int *sh_nprim,
                       const int *sh_off, const int *sh_pure, const double *pexp, const double *pcoef,

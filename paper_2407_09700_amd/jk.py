@@ -17,7 +17,8 @@ JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE, JK_ENODEV, JK_EOVERFLO
 JK_FP64, JK_MIXED = 0, 1
 
 # every symbol declared in include/jk.h
-EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_plan_check", "jk_grad", "jk_build", "jk_build_static", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
+EXPORTS = ["jk_plan_create", "jk_plan_execute", "jk_plan_check", "jk_grad", "jk_one_electron", "jk_build",
+           "jk_build_static", "jk_plan_destroy", "jk_plan_sizes", "jk_stats",
            "jk_profile", "jk_eri_tensor", "jk_schwarz", "jk_sph_matrix", "jk_rys_closed", "jk_rys_grid", "jk_batch_create",
            "jk_batch_offsets", "jk_batch_execute", "jk_batch_check", "jk_batch_stats", "jk_batch_graph_info", "jk_batch_destroy",
            "jk_last_error"]
@@ -75,6 +76,8 @@ def lib():
         L.jk_plan_execute.argtypes = [vp, vp, vp, vp, vp]
         L.jk_plan_check.argtypes = [vp]
         L.jk_grad.argtypes = [vp, vp, vp, vp]
+        dpp = ctypes.POINTER(ctypes.c_double)
+        L.jk_one_electron.argtypes = [ctypes.POINTER(Basis), dpp, ctypes.c_int, dpp, dpp, dpp, dpp, dpp]
         L.jk_build.argtypes = [ctypes.POINTER(Basis), ctypes.POINTER(ctypes.c_double), ctypes.c_int, vp,
                                ctypes.c_double, vp, vp, ctypes.POINTER(Opts), vp]
         L.jk_build_static.argtypes = L.jk_build.argtypes
@@ -174,6 +177,23 @@ def _stream(stream):
         import torch
         return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     return ctypes.c_void_p(stream)
+
+
+def one_electron(mol, charges):
+    """Overlap, kinetic and nuclear-attraction matrices (host numpy, nao x nao) and the nuclear
+    repulsion energy of a molecule with the given nuclear charges (jk_one_electron)."""
+    basis = BasisArrays.from_molecule(mol)
+    coords = np.ascontiguousarray(mol.coords, np.float64)
+    Z = np.ascontiguousarray(charges, np.float64)
+    assert Z.shape == (coords.shape[0],)
+    n = int(mol.nbf)
+    S, T, V = (np.zeros((n, n)) for _ in range(3))
+    e = ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().jk_one_electron(ctypes.byref(basis.struct), coords.ctypes.data_as(dp), int(coords.shape[0]),
+                                Z.ctypes.data_as(dp), S.ctypes.data_as(dp), T.ctypes.data_as(dp), V.ctypes.data_as(dp),
+                                ctypes.byref(e)))
+    return S, T, V, e.value
 
 
 def build(mol, D, thresh=None, static=False, J=None, K=None, stream=None, **opts):

@@ -199,6 +199,16 @@ def _assemble(coords, atom_basis, pure_from_l, thresh, name, rng_d, nocc):
     return mol
 
 
+def nuclear_charges(mol: Molecule) -> np.ndarray:
+    """Integer nuclear charges that make the molecule neutral with its occupied count: 2 nocc
+    electrons spread over the atoms as evenly as integers allow (the first atoms take the
+    remainder). The synthetic molecules have no elements; an SCF needs some charges."""
+    nel = 2 * int(mol.meta.get("nocc", 1))
+    z = np.full(mol.natom, nel // mol.natom, dtype=np.float64)
+    z[: nel % mol.natom] += 1.0
+    return z
+
+
 def random_density(rng, nbf, nocc):
     nocc = min(nocc, nbf)
     a = rng.normal(size=(nbf, nocc))
