@@ -17,6 +17,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -288,9 +290,27 @@ def batched_extra(steps=1, warmup=1):
         out[f"graph_replays_{name}"] = info["replays"]
     if os.path.exists(cache):
         w = open(cache).read().split()
-        out["tuned_grids"] = {w[i]: int(w[i + 1]) for i in range(0, len(w) - 1, 2)}
+        out["tuned"] = {w[i]: int(w[i + 1]) for i in range(0, len(w) - 1, 2)}
         os.remove(cache)
     return out
+
+
+def scf_extra(niter=10):
+    """Ten SCF iterations (DIIS) on the 64-atom molecule with one plan reused: per-iteration
+    time and the J/K build's share of it."""
+    from paper_2407_09700_amd import scf, synth
+    mol = synth.make_config(2)
+    Z = synth.nuclear_charges(mol)
+    r = scf.RHF(mol, Z, diis=8, level_shift=1.0)
+    e = r.run(niter)
+    it = r.iter_ms
+    r.close()
+    log(f"scf: {niter} iterations, {np.mean(it[1:]):.1f} ms each after the first, E {e[-1]:.8f}")
+    return {"workload": f"RHF, {mol.natom}-atom clustered 3s2p1d, {mol.nbf} AOs, charges {int(Z.sum())}, DIIS, "
+                        f"level shift 1.0",
+            "iterations": niter, "iter_ms": [round(x, 2) for x in it], "mean_iter_ms_after_first": float(np.mean(it[1:])),
+            "energies": e, "dE_last": abs(e[-1] - e[-2]), "plan_s": r.plan_s, "one_electron_s": r.onee_s,
+            "rebuilds_after_overflow": r.overflows}
 
 
 def config_extra(mol, steps, warmup, label):
@@ -354,6 +374,7 @@ def main():
         out["cfg_64_atoms"] = config_extra(synth.make_config(2), 10, 2,
                                            "64 atoms, 3-atom clusters, 3s2p1d (spherical d), 896 AOs, tau 1e-12, FP64")
         out["batched"] = batched_extra()
+        out["scf"] = scf_extra()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mol)
     print(json.dumps(out), flush=True)

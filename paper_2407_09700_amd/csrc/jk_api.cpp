@@ -17,6 +17,7 @@
 #include "jk_aux.h"
 #include "jk_classes.h"
 #include "jk_grad.h"
+#include "jk_host.h"
 #include "jk_kernels.h"
 
 using namespace jk;
@@ -244,6 +245,7 @@ struct jk_plan {
   int *d_sbase = nullptr, *d_cbase = nullptr, *d_abase = nullptr, *d_mnc = nullptr;
   int *d_lcol = nullptr, *d_lcols = nullptr, *d_lseg = nullptr;   // compacted exchange rows (JKArgs)
   double *d_ppab = nullptr;            // exponents of the two primitives of every primitive pair
+  double *d_pairP = nullptr;           // per kept pair: block maximum of its shells (per build)
   int *d_shell_atom = nullptr;         // per shell: its atom (nuclear gradient)
   int natom = 0, lmax = 0;
   long long *d_mc_off = nullptr, *d_mf_off = nullptr, *d_ps_off = nullptr, *d_mf_user = nullptr;
@@ -279,6 +281,7 @@ struct jk_plan {
   std::vector<int> launched;           // launch slots used by the last eager execute
   std::vector<int> grid;               // per launch slot: workgroups (0 = default)
   bool tuned = false;
+  std::vector<char> fuse;              // [NFUSED] lane tier (cb, tier) runs fused (1) or per class (0)
   int *d_kets = nullptr;
   long long list_capacity = 0;
   double *d_scratch = nullptr;
@@ -324,7 +327,7 @@ void plan_free(jk_plan *p) {
   dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
   dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair);
   dfree(p->d_room); dfree(p->d_overflow); dfree(p->d_capc);
-  dfree(p->d_lcol); dfree(p->d_lcols); dfree(p->d_lseg); dfree(p->d_ppab); dfree(p->d_shell_atom); dfree(p->d_units); dfree(p->d_nunits); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
+  dfree(p->d_lcol); dfree(p->d_lcols); dfree(p->d_lseg); dfree(p->d_ppab); dfree(p->d_shell_atom); dfree(p->d_pairP); dfree(p->d_units); dfree(p->d_nunits); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
 }
@@ -333,6 +336,11 @@ void plan_free(jk_plan *p) {
 // ket class's momenta) when they fit; 0 sends every exchange update to global memory
 #ifndef JK_CLS_LDS_ROWS
 #define JK_CLS_LDS_ROWS 1
+#endif
+// default for the lane tiers of a bra class: fused over their ket classes (1: one launch, full
+// exchange rows in LDS) or per-class launches with compacted rows (0); the tuner picks per tier
+#ifndef JK_FUSE_LANE_TIERS
+#define JK_FUSE_LANE_TIERS 0
 #endif
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
 constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels (default)
@@ -793,7 +801,8 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   p->jp_total = jt;
   if ((rc = dupload(&p->d_jp_off, p->jp_off)) || (rc = dalloc(&p->d_Jpair, (size_t)std::max(1LL, jt))) ||
       (rc = dalloc(&p->d_segoff, (size_t)p->npairs * NPAIRCLASS)) ||
-      (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)) || (rc = dalloc(&p->d_count32, NQCLASS)))
+      (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)) || (rc = dalloc(&p->d_count32, NQCLASS)) ||
+      (rc = dalloc(&p->d_pairP, (size_t)std::max(1, p->npairs))))
     return cleanup(rc);
   if (p->precision == JK_MIXED && ((rc = dalloc(&p->d_segoff32, (size_t)p->npairs * NPAIRCLASS)) ||
                                    (rc = dalloc(&p->d_segcnt32, (size_t)p->npairs * NPAIRCLASS))))
@@ -813,6 +822,8 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   p->class_off_h.assign(NQCLASS, 0);
   p->grid.assign(NSLOT, 0);
   p->slice.assign(NSLOT, 0);
+  p->fuse.assign(NFUSED, 0);
+  for (int f = 0; f < NFUSED; ++f) p->fuse[f] = (f % NTIERS == TEAM_TIER) ? 1 : JK_FUSE_LANE_TIERS;
   p->units_est.assign(NSLOT, 0);
   if (p->flags & (JK_FLAG_PROFILE | JK_FLAG_TUNE)) {
     p->events.resize((size_t)EV_SETS * EV_PER_SET, nullptr);
@@ -870,7 +881,7 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
       for (int ck = 0; ck <= cb; ++ck) any = any || (((bi.tier_mask[tier] >> ck) & 1) && active[qclass_index(cb, ck)]);
       if (!any) continue;
       int split = beg, m_split = 0;
-      if (bi.fusable[tier]) {
+      if (bi.fusable[tier] && p->fuse[cb * NTIERS + tier]) {
         const size_t fixed = (size_t)((na * nbb + 1) & ~1) * 8 + (size_t)bi.pool_bytes[tier];   // jab_s, pool
         const long long fit = fixed < FUSED_LDS_MAX ? (long long)((FUSED_LDS_MAX - fixed) / ((size_t)(na + nbb) * 8)) : 0;
         int m = 0;
@@ -959,6 +970,7 @@ ScreenArgs screen_args(const jk_plan *p) {
   A.bin_beg = p->d_bin_beg;
   A.cm_bin = p->d_cm_bin;
   A.Pblk = p->d_Pblk;
+  A.pairP = p->d_pairP;
   A.ps_off = p->d_ps_off;
   A.sbase = p->d_sbase;
   A.gmax = p->d_gmax;
@@ -1084,6 +1096,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   if (p->npairs > 0) {
     HIPCHK(launch_capacity(A, st));
     HIPCHK(launch_class_room(p->d_cap, p->d_capc, p->d_room, p->d_overflow, st));
+    HIPCHK(launch_pairp(A, st));
     HIPCHK(launch_screen(A, st));
   }
   if (prof) HIPCHK(hipEventRecord(ev[2 * NSLOT + 1], st));
@@ -1215,8 +1228,14 @@ bool load_tune_cache(jk_plan *p) {
   char name[64];
   int g = 0, n = 0;
   while (fscanf(f, "%63s %d", name, &g) == 2) {
+    const std::string nm = name;
+    if (nm.rfind("fuse:", 0) == 0) {         // fuse:k_bra<la,lb,tier> 0|1
+      for (int s = 0; s < NFUSED; ++s)
+        if ("fuse:" + slot_name(s) == nm) p->fuse[s] = g != 0;
+      continue;
+    }
     for (int s = 0; s < NSLOT; ++s)
-      if (slot_name(s) == name && g > 0 && g <= 65536) {
+      if (slot_name(s) == nm && g > 0 && g <= 65536) {
         p->grid[s] = g;
         ++n;
       }
@@ -1231,17 +1250,44 @@ void save_tune_cache(const jk_plan *p) {
   if (!f) return;
   for (int s = 0; s < NSLOT; ++s)
     if (p->grid[s] > 0) fprintf(f, "%s %d\n", slot_name(s).c_str(), p->grid[s]);
+  for (int s = 0; s < NFUSED; ++s)
+    if (s % NTIERS != TEAM_TIER && g_bras[s / NTIERS].fusable[s % NTIERS])
+      fprintf(f, "fuse:%s %d\n", slot_name(s).c_str(), (int)p->fuse[s]);
   fclose(f);
 }
 
-// Time every launch slot at each candidate workgroup count (one full build per candidate,
-// per-launch HIP events) and keep the fastest count per slot.
-int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
-  std::vector<float> best(NSLOT, 1e30f);
-  std::vector<int> pick(NSLOT, 0);
+// Work units and team scratch for the current launch set (after the tuner changed it).
+int resize_units(jk_plan *p) {
+  std::vector<Launch> launches;
+  plan_launches(p, p->active, launches);
+  long long units_need = 1;
+  for (const Launch &L : launches) {
+    long long cand = 0;
+    for (int ck = 0; ck <= L.cb; ++ck)
+      if ((L.mask >> ck) & 1) cand += p->capc[qclass_index(L.cb, ck)];
+    size_units(p, L, cand, &units_need);
+  }
+  if (units_need > 0x7fffffffLL) return fail(JK_EUNSUPPORTED, "%lld work units exceed 2^31", units_need);
+  if (units_need > p->units_cap) {
+    dfree(p->d_units);
+    p->units_cap = 0;
+    int rc = dalloc(&p->d_units, (size_t)units_need);
+    if (rc) return rc;
+    p->units_cap = (int)units_need;
+  }
+  p->graph_stale = true;
+  return ensure_launch_scratch(p);
+}
+
+// Times every launch slot at each candidate workgroup count (one full build per candidate, per-launch
+// HIP events): best[slot] and pick[slot].
+int time_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st, std::vector<float> &best,
+               std::vector<int> &pick) {
+  best.assign(NSLOT, 1e30f);
+  pick.assign(NSLOT, 0);
   for (int g : TUNE_GRIDS) {
     std::fill(p->grid.begin(), p->grid.end(), g);
-    int rc = ensure_launch_scratch(p);
+    int rc = resize_units(p);
     const hipEvent_t *ev = p->events.data() + (size_t)p->ev_next * EV_PER_SET;   // the set this build records
     if (!rc) rc = enqueue_build(p, D, J, K, st, false);
     if (rc) return rc;
@@ -1255,9 +1301,50 @@ int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st
       }
     }
   }
+  return JK_OK;
+}
+
+// The tuner: for every register tier of lane bodies, whether its ket classes run fused (one
+// launch per bra class, full exchange rows in LDS) or per class (compacted rows), and for every
+// launch the workgroup count. Both layouts are timed at every candidate count; a tier keeps the
+// layout whose launches (fused launch and the per-class launches of molecules too large for it,
+// against the per-class launches alone) take less time.
+int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
+  std::vector<float> bestF, bestC;
+  std::vector<int> pickF, pickC;
+  for (int f = 0; f < NFUSED; ++f)
+    if (f % NTIERS != TEAM_TIER) p->fuse[f] = 1;
+  int rc = time_grids(p, D, J, K, st, bestF, pickF);
+  if (rc) return rc;
+  for (int f = 0; f < NFUSED; ++f)
+    if (f % NTIERS != TEAM_TIER) p->fuse[f] = 0;
+  if ((rc = time_grids(p, D, J, K, st, bestC, pickC))) return rc;
+  auto t = [](const std::vector<float> &b, int slot) { return b[slot] < 1e29f ? (double)b[slot] : 0.0; };
+  std::vector<int> pick = pickC;
+  for (int cb = 0; cb < NPAIRCLASS; ++cb)
+    for (int tier = 0; tier < TEAM_TIER; ++tier) {
+      const BraInfo &bi = g_bras[cb];
+      const int f = cb * NTIERS + tier;
+      if (!bi.fusable[tier]) continue;
+      double costF = t(bestF, f) + t(bestF, NF32_BASE + f), costC = 0.0;
+      for (int ck = 0; ck <= cb; ++ck)
+        if ((bi.tier_mask[tier] >> ck) & 1) {
+          costF += t(bestF, NFUSED + qclass_index(cb, ck));
+          costC += t(bestC, NFUSED + qclass_index(cb, ck));
+        }
+      p->fuse[f] = costF < costC;
+      if (p->fuse[f]) {
+        pick[f] = pickF[f];
+        pick[NF32_BASE + f] = pickF[NF32_BASE + f];
+        for (int ck = 0; ck <= cb; ++ck)
+          if ((bi.tier_mask[tier] >> ck) & 1) pick[NFUSED + qclass_index(cb, ck)] = pickF[NFUSED + qclass_index(cb, ck)];
+      }
+    }
+  for (int f = 0; f < NFUSED; ++f)   // team tiers: timed in both passes, same layout
+    if (f % NTIERS == TEAM_TIER) pick[f] = bestF[f] <= bestC[f] ? pickF[f] : pickC[f];
   p->grid = pick;
   save_tune_cache(p);
-  return ensure_launch_scratch(p);
+  return resize_units(p);
 }
 
 constexpr double SIZE_HEADROOM = 2.0;   // first-execute sizing: lists hold densities up to twice its largest element
@@ -1277,7 +1364,7 @@ int plan_run(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) 
     if (rc) return rc;
   }
   if ((p->flags & JK_FLAG_TUNE) && !p->tuned) {
-    int rc = load_tune_cache(p) ? ensure_launch_scratch(p) : tune_grids(p, D, J, K, st);
+    int rc = load_tune_cache(p) ? resize_units(p) : tune_grids(p, D, J, K, st);
     if (rc) return rc;
     p->tuned = true;
     p->graph_stale = true;
@@ -1366,6 +1453,7 @@ int plan_grad(jk_plan *p, const double *D, double *grad, hipStream_t st) {
   if (p->npairs > 0) {
     HIPCHK(launch_capacity(A, st));
     HIPCHK(launch_class_room(p->d_cap, p->d_capc, p->d_room, p->d_overflow, st));
+    HIPCHK(launch_pairp(A, st));
     HIPCHK(launch_screen(A, st));
   }
   GradArgs G{};
@@ -1422,6 +1510,23 @@ int plan_stats(const jk_plan *plan, jk_stats_t *out) {
   }
   return JK_OK;
 }
+
+}  // namespace
+
+namespace jk {
+void solid_harmonics_host(int l, double *T) { solid_harmonics(l, T); }
+int set_error(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+}  // namespace jk
+
+namespace {
 
 // host copy of the Boys grid for the test hook below
 namespace host_boys {

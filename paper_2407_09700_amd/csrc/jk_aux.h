@@ -30,6 +30,7 @@ struct ScreenArgs {           // device pointers
   const int *bin_beg;         // [nbins+1] first pair of each bin (class, molecule, contraction length)
   const int *cm_bin;          // [15 * (nmol+1)] first bin of each (class, molecule)
   const double *Pblk;         // per molecule: nshell_m x nshell_m block maxima of |D_cart|
+  double *pairP;              // per kept pair: its own block maximum (k_pairp, read by k_screen)
   const long long *ps_off;    // [nmol+1] first element of each molecule's block in Pblk
   const int *sbase;           // [nmol+1] first shell of each molecule
   const double *gmax;         // global maximum of |D_cart|
@@ -68,6 +69,7 @@ hipError_t launch_class_room(const unsigned long long *cap, const long long *cap
                              hipStream_t st);
 hipError_t launch_capacity(const ScreenArgs &A, hipStream_t st);
 hipError_t launch_screen(const ScreenArgs &A, hipStream_t st);
+hipError_t launch_pairp(const ScreenArgs &A, hipStream_t st);
 hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,
                            hipStream_t st);
 hipError_t launch_fold(const FoldArgs &F, hipStream_t st);

@@ -73,6 +73,16 @@ __global__ void k_blockmax(ShellInfo S, const double *__restrict__ Dc, double *_
   atomic_max_nonneg(gmax, local);
 }
 
+// pairP[k] = Pblk of kept pair k's own two shells (read by the screen for every ket; one
+// coalesced load instead of a scattered one into the molecule's block-maximum matrix).
+__global__ void k_pairp(ScreenArgs A) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= A.npairs) return;
+  const int m = A.pair_mol[k];
+  const int sb0 = A.sbase[m], ns = A.sbase[m + 1] - sb0;
+  A.pairP[k] = A.Pblk[A.ps_off[m] + (size_t)(A.pair_sa[k] - sb0) * ns + (A.pair_sb[k] - sb0)];
+}
+
 // Number of ket pairs of one class that can pass the screen for one bra pair, under
 // the global density bound: kets are sorted by I descending, so they form a prefix.
 __device__ __forceinline__ int ket_prefix(const double *__restrict__ Iket, int nket, double Ibra, double pglob,
@@ -214,7 +224,7 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
           // largest density block the quartet's updates read: D[a,b], D[c,d] (Coulomb),
           // D[a,c], D[a,d], D[b,c], D[b,d] (exchange)
           double p = 0.0;
-          if (A.want & 1) p = fmax(pab, Pm[(size_t)sc * ns + sd]);
+          if (A.want & 1) p = fmax(pab, A.pairP[kg]);
           if (A.want & 2) p = fmax(fmax(p, fmax(Pa[sc], Pa[sd])), fmax(Pb[sc], Pb[sd]));
           const double bound = Ib * A.pairI[kg] * p;
           keep = bound >= tau;
@@ -384,6 +394,10 @@ hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, d
 }
 hipError_t launch_capacity(const ScreenArgs &A, hipStream_t st) {
   hipLaunchKernelGGL(k_capacity, dim3((A.npairs + 255) / 256), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+hipError_t launch_pairp(const ScreenArgs &A, hipStream_t st) {
+  hipLaunchKernelGGL(k_pairp, dim3((A.npairs + 255) / 256), dim3(256), 0, st, A);
   return hipGetLastError();
 }
 hipError_t launch_screen(const ScreenArgs &A, hipStream_t st) {

@@ -114,9 +114,13 @@ def test_tuner_cache_roundtrip(tmp_path):
     t = jk.Plan.from_molecule(mol, tune=True, tune_cache=path)
     J1, K1 = t.execute(Dt)
     torch.cuda.synchronize()
-    lines = open(path).read().split()
-    say(f"[tune] cache: {' '.join(lines)}")
-    assert len(lines) >= 2 and all(int(x) > 0 for x in lines[1::2])
+    words = open(path).read().split()
+    say(f"[tune] cache: {' '.join(words)}")
+    pairs = list(zip(words[0::2], words[1::2]))
+    grids = [int(v) for k, v in pairs if not k.startswith("fuse:")]
+    fuses = [int(v) for k, v in pairs if k.startswith("fuse:")]
+    # a workgroup count for every launch, a layout (fused or per class) for every lane tier
+    assert grids and all(g > 0 for g in grids) and fuses and all(f in (0, 1) for f in fuses)
     t2 = jk.Plan.from_molecule(mol, tune=True, tune_cache=path)   # reads the cache, no timing runs
     J2, K2 = t2.execute(Dt)
     torch.cuda.synchronize()
