@@ -861,7 +861,8 @@ struct Launch {
   size_t lds;        // dynamic LDS bytes
   long long scratch_per_wg;
   int kw;            // per class with compacted LDS exchange rows: their length (0: global exchange)
-  int krows;         // 1: rows of a and b in LDS, 2: rows of a only
+  int krows;         // 1: rows of a and b in LDS, 2: rows of a, and the first kwb columns of the rows of b
+  int kwb;
 };
 
 // Launches of one build. active[qc]: the class has work (eager) or may have work (recording).
@@ -894,10 +895,10 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
           // mixed precision: the FP32 parts of the lane tiers run in their own FP32-only kernel
           const bool sep = p->precision == JK_MIXED && bi.launch_bra32[tier] != nullptr;
           out.push_back(Launch{cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], sep ? 1 : 3, false,
-                               ncm, lds, bi.scratch_per_wg[tier], 0, 0});
+                               ncm, lds, bi.scratch_per_wg[tier], 0, 0, 0});
           if (sep)
             out.push_back(Launch{NF32_BASE + cb * NTIERS + tier, cb, tier, -1, beg, split, bi.tier_mask[tier], 2, true,
-                                 ncm, lds, bi.scratch_per_wg[tier], 0, 0});
+                                 ncm, lds, bi.scratch_per_wg[tier], 0, 0, 0});
         }
       }
       if (split == end) continue;
@@ -924,9 +925,13 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
           else
             kw = 0;
         }
-        const size_t klds = jab + (size_t)(krows == 1 ? na + nbb : na) * kw * 8;
+        // rows of a only: the rest of the LDS holds the first kwb columns of the rows of b
+        const int kwb = krows == 2 ? (int)std::min<size_t>((size_t)kw, (FUSED_LDS_MAX - jab - (size_t)na * kw * 8) /
+                                                                           ((size_t)nbb * 8))
+                                   : 0;
+        const size_t klds = jab + ((size_t)(krows == 1 ? na + nbb : na) * kw + (size_t)nbb * kwb) * 8;
         out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 3, false, 0, kw ? klds : lds,
-                             ci.scratch_per_wg, kw, krows});
+                             ci.scratch_per_wg, kw, krows, kwb});
       }
     }
   }
@@ -1143,6 +1148,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
     J_.next = p->d_next + L.slot;
     if (prof) HIPCHK(hipEventRecord(ev[2 * L.slot], st));
     J_.kw = L.kw;
+    J_.kwb = L.kwb;
     if (L.qc < 0)
       HIPCHK((L.f32 ? g_bras[L.cb].launch_bra32[L.tier] : g_bras[L.cb].launch_bra[L.tier])(J_, grid, L.lds, st));
     else if (L.kw > 0)

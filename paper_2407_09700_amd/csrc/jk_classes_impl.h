@@ -17,7 +17,8 @@ void allow_dyn_lds(F *fn) {
 
 template <int LA, int LB, int LC, int LD, int KL = 0>
 hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((k_cls<LA, LB, LC, LD, KL>), dim3(grid), dim3(cls_block<LA, LB, LC, LD>()), lds, stream, args);
+  hipLaunchKernelGGL((k_cls<LA, LB, LC, LD, KL>), dim3(grid), dim3(cls_threads<LA, LB, LC, LD, KL>()), lds, stream,
+                     args);
   return hipGetLastError();
 }
 

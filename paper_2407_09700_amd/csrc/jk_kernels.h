@@ -102,6 +102,7 @@ struct JKArgs {
   const int *lseg;              // [nmol * 6] start of each momentum's segment in lcols (l = 0..4, end)
   const int *cbase;             // [nmol + 1] first Cartesian AO of each molecule
   int kw;                       // LDS row length of the launch (largest over its molecules)
+  int kwb;                      // k_cls with KL = 2: compacted columns of the rows of b held in LDS
 };
 
 __device__ __forceinline__ double *jp_elem(const JKArgs &A, int cls, int pair, int e) {
@@ -126,7 +127,8 @@ __device__ __forceinline__ void k_update(double *Krow, double *Km, int kst, int 
 // mixed precision); the digestion always runs in double.
 // KMAP: the LDS rows are the compacted rows of k_cls (row length kst, ket class columns from
 // kdofs); otherwise full rows of the molecule's Cartesian columns (row length nc). KLB false:
-// only the rows of a are in LDS, the rows of b go to global memory.
+// only the rows of a are full LDS rows; the rows of b keep their first A.kwb compacted columns
+// in LDS (after the rows of a, row length A.kwb) and send the others to global memory.
 template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double, bool KMAP = false, bool KLB = true>
 __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                               double (&jab)[ncart(LA) * ncart(LB)], int rot, int kdofs = 0,
@@ -207,7 +209,10 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + od + d], v);
-        k_update<KLDS && KLB>(Krow, Km, kst, nc, NA + b, bra.cb + b, kc + c, oc + c, s * v);
+        if (KLDS && !KLB && kc + c < A.kwb)
+          atomicAdd(&Krow[(size_t)NA * A.kw + b * A.kwb + kc + c], s * v);
+        else
+          k_update<KLDS && KLB>(Krow, Km, kst, nc, NA + b, bra.cb + b, kc + c, oc + c, s * v);
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -216,7 +221,10 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
         for (int a = 0; a < NA; ++a)
 #pragma unroll
           for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + oc + c], v);
-        k_update<KLDS && KLB>(Krow, Km, kst, nc, NA + b, bra.cb + b, kd + d, od + d, s * v);
+        if (KLDS && !KLB && kd + d < A.kwb)
+          atomicAdd(&Krow[(size_t)NA * A.kw + b * A.kwb + kd + d], s * v);
+        else
+          k_update<KLDS && KLB>(Krow, Km, kst, nc, NA + b, bra.cb + b, kd + d, od + d, s * v);
       }
     }
   }
@@ -825,16 +833,30 @@ __global__ __launch_bounds__(256) void k_bra(JKArgs A) {
 template <int LA, int LB, int LC, int LD>
 constexpr int cls_block() { return team_block<LA, LB, LC, LD>(); }
 
+// Threads of a k_cls workgroup. With LDS exchange rows (KL != 0) one workgroup often fills most
+// of a CU's LDS, so a light lane body (register tier 0 and total angular momentum at most 3:
+// these fit 256 registers) carries JK_CLS_LDS_BLOCK threads (two waves per SIMD at 512) to
+// keep more waves in flight than a 256-lane workgroup would. Heavier bodies keep 256 lanes:
+// at two waves per SIMD they spill.
+#ifndef JK_CLS_LDS_BLOCK
+#define JK_CLS_LDS_BLOCK 512
+#endif
+template <int LA, int LB, int LC, int LD, int KL>
+constexpr int cls_threads() {
+  return KL != 0 && tier_of<LA, LB, LC, LD>() == 0 && LA + LB + LC + LD <= 3 ? JK_CLS_LDS_BLOCK
+                                                                              : cls_block<LA, LB, LC, LD>();
+}
+
 // Dynamic LDS: jab_s NA*NB (padded to even) | team pool (team classes) or, with KL (lane
 // bodies), the unit's exchange rows compacted to the columns of the ket class's momenta
 // (KL = 1: rows K[a,:] and K[b,:], (NA+NB) x A.kw; KL = 2: rows K[a,:] only, NA x A.kw, the
 // rows of b updated in global memory), flushed once per unit with one global atomic per
 // nonzero element.
 template <int LA, int LB, int LC, int LD, int KL = 0>
-__global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A) {
+__global__ __launch_bounds__((cls_threads<LA, LB, LC, LD, KL>())) void k_cls(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB), ck = pair_class(LC, LD);
   static_assert(!KL || !use_team<LA, LB, LC, LD>(), "compacted LDS rows are for the lane bodies");
-  constexpr int RL = KL == 1 ? NA + NB : NA;    // exchange rows held in LDS
+  constexpr int RL = KL == 1 ? NA + NB : NA;    // full exchange rows held in LDS
   extern __shared__ double smem[];
   __shared__ int s_unit;
   double *jab_s = smem;
@@ -843,7 +865,7 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
   const int nunits = min(*A.nunits, A.units_cap);
   const int tid = threadIdx.x;
   if constexpr (KL != 0)   // the rows start at zero; each unit's flush puts back the zeros it reads
-    for (int t = tid; t < RL * A.kw; t += blockDim.x) Krow[t] = 0.0;
+    for (int t = tid; t < RL * A.kw + (KL == 2 ? NB * A.kwb : 0); t += blockDim.x) Krow[t] = 0.0;
   for (;;) {
     if (tid == 0) s_unit = atomicAdd(A.next, 1);
     for (int t = tid; t < NA * NB; t += blockDim.x) jab_s[t] = 0.0;
@@ -908,6 +930,19 @@ __global__ __launch_bounds__((cls_block<LA, LB, LC, LD>())) void k_cls(JKArgs A)
             const int col = cols[j < ncl ? lseg[LC] + j : lseg[LD] + (j - ncl)];
             const int row = r < NA ? bra.ca + r : bra.cb + (r - NA);
             atomic_add(&Km[(size_t)row * nc + col], v);
+          }
+        }
+        if constexpr (KL == 2) {    // the LDS part of the rows of b (row length A.kwb)
+          const int kwb = A.kwb < kw ? A.kwb : kw;
+          double *Kb = Krow + (size_t)NA * A.kw;
+          for (int t = tid; t < NB * kwb; t += blockDim.x) {
+            const int r = t / kwb, j = t % kwb;
+            const double v = Kb[r * A.kwb + j];
+            if (v != 0.0) {
+              Kb[r * A.kwb + j] = 0.0;
+              const int col = cols[j < ncl ? lseg[LC] + j : lseg[LD] + (j - ncl)];
+              atomic_add(&Km[(size_t)(bra.cb + r) * nc + col], v);
+            }
           }
         }
       } else {

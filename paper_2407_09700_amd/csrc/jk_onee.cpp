@@ -57,28 +57,28 @@ void rys_rule(int N, double T, double *u, double *w) {
   }
 }
 
+// C(n, k) for n <= 8
 double binom_(int n, int k) {
-  double r = 1.0;
-  for (int i = 0; i < k; ++i) r = r * (n - i) / (i + 1);
-  return r;
+  static const double C[9][9] = {{1}, {1, 1}, {1, 2, 1}, {1, 3, 3, 1}, {1, 4, 6, 4, 1}, {1, 5, 10, 10, 5, 1},
+                                 {1, 6, 15, 20, 15, 6, 1}, {1, 7, 21, 35, 35, 21, 7, 1},
+                                 {1, 8, 28, 56, 70, 56, 28, 8, 1}};
+  return C[n][k];
 }
 
-double dfact_odd(int n) {   // (n-1)!! for even n >= 0
-  double r = 1.0;
-  for (int k = n - 1; k > 1; k -= 2) r *= k;
-  return r;
-}
+// (n-1)!! for even n <= 12 (index n / 2)
+const double DFACT[7] = {1.0, 1.0, 3.0, 15.0, 105.0, 945.0, 10395.0};
 
-// E[(x - A)^i (x - B)^j] for a Gaussian of mean m and variance v (v >= 0)
+// E[(x - A)^i (x - B)^j] for a Gaussian of mean m and variance v (v >= 0), i <= 4, j <= 6
 double moment(int i, int j, double mA, double mB, double v) {
+  double pa[5], pb[7], pv[7];
+  pa[0] = pb[0] = pv[0] = 1.0;
+  for (int k = 1; k <= i; ++k) pa[k] = pa[k - 1] * mA;
+  for (int k = 1; k <= j; ++k) pb[k] = pb[k - 1] * mB;
+  for (int k = 1; k <= (i + j) / 2; ++k) pv[k] = pv[k - 1] * v;
   double s = 0.0;
   for (int k = 0; k <= i; ++k)
-    for (int q = 0; q <= j; ++q) {
-      const int n = k + q;
-      if (n & 1) continue;
-      s += binom_(i, k) * binom_(j, q) * std::pow(mA, i - k) * std::pow(mB, j - q) * dfact_odd(n) *
-           std::pow(v, n / 2);
-    }
+    for (int q = (k & 1); q <= j; q += 2)      // k + q even
+      s += binom_(i, k) * binom_(j, q) * pa[i - k] * pb[j - q] * DFACT[(k + q) / 2] * pv[(k + q) / 2];
   return s;
 }
 

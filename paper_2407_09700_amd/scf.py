@@ -8,7 +8,9 @@ the CPU). The iterations' dense linear algebra (symmetric eigendecompositions an
 nao x nao matrices) runs on the GPU through PyTorch's ROCm routines; the density stays on the
 device. Each iteration waits for its J and K (the next density depends on them), so the work-list
 check runs every iteration and a build that overflowed is redone at once. Optional Pulay DIIS on
-the commutator F D S - S D F.
+the commutator F D S - S D F, and an optional level shift of the virtual orbitals
+(F + shift (S - S D S / 2), energies from the unshifted F) for molecules whose iterations
+oscillate from the core-Hamiltonian guess.
 """
 from __future__ import annotations
 
@@ -23,7 +25,8 @@ class RHF:
     """Closed-shell SCF of a molecule (synth.Molecule fields) with nuclear charges `charges`
     (2 x occupied = sum of charges)."""
 
-    def __init__(self, mol, charges, thresh=None, diis=8, precision=jk.JK_FP64, device="cuda"):
+    def __init__(self, mol, charges, thresh=None, diis=8, level_shift=0.0, damping=0.0, diis_start=0,
+                 precision=jk.JK_FP64, device="cuda"):
         import torch
         t = time.perf_counter()
         S, T, V, self.enuc = jk.one_electron(mol, charges)
@@ -39,6 +42,9 @@ class RHF:
         self.plan = jk.Plan.from_molecule(mol, thresh=thresh, precision=precision)
         self.plan_s = time.perf_counter() - t
         self.diis = diis
+        self.level_shift = level_shift     # virtual orbitals raised by this much before diagonalising
+        self.damping = damping             # fraction of the previous density kept before DIIS starts
+        self.diis_start = diis_start       # iteration from which DIIS extrapolates
 
     def density(self, F):
         import torch
@@ -57,7 +63,7 @@ class RHF:
         self.iter_ms = []
         self.overflows = 0
         torch.cuda.synchronize()
-        for _ in range(niter):
+        for it in range(niter):
             t = time.perf_counter()
             self.plan.execute(D, J, K)
             try:             # the iteration needs J and K now: wait, and redo a build that overflowed
@@ -70,7 +76,7 @@ class RHF:
                 self.plan.check()
             F = self.H + J - 0.5 * K
             energies.append(0.5 * torch.sum(D * (self.H + F)) + self.enuc)
-            if self.diis:
+            if self.diis and it >= self.diis_start:
                 err = self.X.T @ (F @ D @ self.S - self.S @ D @ F) @ self.X
                 fs.append(F)
                 es.append(err)
@@ -85,7 +91,12 @@ class RHF:
                 rhs[n] = -1.0
                 c = torch.linalg.solve(B, rhs)
                 F = sum(c[i] * fs[i] for i in range(n))
-            D = self.density(F)
+            if self.level_shift:
+                F = F + self.level_shift * (self.S - 0.5 * self.S @ D @ self.S)
+            Dn = self.density(F)
+            if self.damping and not (self.diis and it >= self.diis_start):
+                Dn = (self.damping * D + (1.0 - self.damping) * Dn).contiguous()
+            D = Dn
             torch.cuda.synchronize()
             self.iter_ms.append((time.perf_counter() - t) * 1e3)
         self.D = D

@@ -1,12 +1,13 @@
 """Reference restricted Hartree-Fock iterations for the SCF tests (TEST INFRASTRUCTURE): numpy
 linear algebra with the oracle's one-electron integrals and J/K. Roothaan iterations from the
-core-Hamiltonian guess, optionally with Pulay's DIIS on the commutator FDS - SDF."""
+core-Hamiltonian guess, optionally with Pulay's DIIS on the commutator FDS - SDF and a level
+shift of the virtual orbitals."""
 import numpy as np
 
 import oracle
 
 
-def rhf(mol, charges, niter=10, diis=0, tau=None):
+def rhf(mol, charges, niter=10, diis=0, tau=None, level_shift=0.0):
     o = oracle.Oracle(mol)
     S, T, V, enuc = o.one_electron(charges)
     H = T + V
@@ -42,5 +43,7 @@ def rhf(mol, charges, niter=10, diis=0, tau=None):
             rhs[n] = -1.0
             c = np.linalg.solve(B, rhs)
             F = sum(ci * fi for ci, fi in zip(c[:n], fs))
+        if level_shift:
+            F = F + level_shift * (S - 0.5 * S @ D @ S)
         D = density(F)
     return np.array(energies)
