@@ -270,7 +270,7 @@ struct jk_plan {
   long long *d_capc = nullptr;
   bool active[NQCLASS] = {};                     // classes launched by every build (capacity > 0)
   long long overflows = 0;                       // builds reported incomplete by jk_plan_check
-  double *d_Jpair = nullptr;
+  double *d_Jpair = nullptr, *d_Dpair = nullptr;
   long long jp_total = 0;
   std::vector<long long> jp_off;                 // [15]
   hipStream_t last_stream = nullptr;
@@ -325,7 +325,7 @@ void plan_free(jk_plan *p) {
   dfree(p->d_Jc); dfree(p->d_Kc); dfree(p->d_Pblk); dfree(p->d_gmax); dfree(p->d_cap); dfree(p->d_count);
   dfree(p->d_kets); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
   dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
-  dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair);
+  dfree(p->d_segcnt); dfree(p->d_next); dfree(p->d_class_off); dfree(p->d_jp_off); dfree(p->d_Jpair); dfree(p->d_Dpair);
   dfree(p->d_room); dfree(p->d_overflow); dfree(p->d_capc);
   dfree(p->d_lcol); dfree(p->d_lcols); dfree(p->d_lseg); dfree(p->d_ppab); dfree(p->d_shell_atom); dfree(p->d_pairP); dfree(p->d_units); dfree(p->d_nunits); dfree(p->d_segoff32); dfree(p->d_segcnt32); dfree(p->d_count32);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
@@ -800,6 +800,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   }
   p->jp_total = jt;
   if ((rc = dupload(&p->d_jp_off, p->jp_off)) || (rc = dalloc(&p->d_Jpair, (size_t)std::max(1LL, jt))) ||
+      (rc = dalloc(&p->d_Dpair, (size_t)std::max(1LL, jt))) ||
       (rc = dalloc(&p->d_segoff, (size_t)p->npairs * NPAIRCLASS)) ||
       (rc = dalloc(&p->d_segcnt, (size_t)p->npairs * NPAIRCLASS)) || (rc = dalloc(&p->d_count32, NQCLASS)) ||
       (rc = dalloc(&p->d_pairP, (size_t)std::max(1, p->npairs))))
@@ -1097,6 +1098,23 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
   HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
   HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
+  FoldArgs F{};
+  F.pair_cls = p->d_pair_cls;
+  F.pair_ca = p->d_pair_ca;
+  F.pair_cb = p->d_pair_cb;
+  F.pair_la = p->d_pair_la;
+  F.pair_lb = p->d_pair_lb;
+  F.pair_mol = p->d_pair_mol;
+  F.cls_beg = p->d_cls_beg;
+  F.jp_off = p->d_jp_off;
+  F.mc_off = p->d_mc_off;
+  F.cbase = p->d_cbase;
+  F.Jpair = p->d_Jpair;
+  F.Jc = p->d_Jc;
+  F.npairs = p->npairs;
+  F.Dc = p->d_Dc;
+  F.Dpair = p->d_Dpair;
+  if (p->npairs > 0) HIPCHK(launch_unfold(F, st));
   ScreenArgs A = screen_args(p);
   if (p->npairs > 0) {
     HIPCHK(launch_capacity(A, st));
@@ -1122,6 +1140,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   J_.mbase = p->d_mc_off;
   J_.mnc = p->d_mnc;
   J_.Jpair = p->d_Jpair;
+  J_.Dpair = p->d_Dpair;
   J_.jp_off = p->d_jp_off;
   J_.cls_beg = p->d_cls_beg;
   J_.scratch = p->d_scratch;
@@ -1159,20 +1178,6 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
     if (!record) p->launched.push_back(L.slot);
   }
   if (prof) HIPCHK(hipEventRecord(ev[2 * NSLOT + 2], st));
-  FoldArgs F{};
-  F.pair_cls = p->d_pair_cls;
-  F.pair_ca = p->d_pair_ca;
-  F.pair_cb = p->d_pair_cb;
-  F.pair_la = p->d_pair_la;
-  F.pair_lb = p->d_pair_lb;
-  F.pair_mol = p->d_pair_mol;
-  F.cls_beg = p->d_cls_beg;
-  F.jp_off = p->d_jp_off;
-  F.mc_off = p->d_mc_off;
-  F.cbase = p->d_cbase;
-  F.Jpair = p->d_Jpair;
-  F.Jc = p->d_Jc;
-  F.npairs = p->npairs;
   if (p->npairs > 0 && (J_.want & 1)) HIPCHK(launch_fold(F, st));
   HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, (J_.want & 1) ? J : nullptr, (J_.want & 2) ? K : nullptr, st));
   if (prof) {

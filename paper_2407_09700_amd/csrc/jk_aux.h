@@ -61,6 +61,8 @@ struct FoldArgs {             // Coulomb pair buffer -> Cartesian Jt of each mol
   const double *Jpair;
   double *Jc;
   int npairs;
+  const double *Dc;           // k_unfold: Cartesian densities in, pair-ordered blocks out
+  double *Dpair;
 };
 
 hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, hipStream_t st);
@@ -73,6 +75,7 @@ hipError_t launch_pairp(const ScreenArgs &A, hipStream_t st);
 hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,
                            hipStream_t st);
 hipError_t launch_fold(const FoldArgs &F, hipStream_t st);
+hipError_t launch_unfold(const FoldArgs &F, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, long long n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int *p, long long n, int v, hipStream_t st);
 hipError_t launch_units(const int *segcnt, const int *segcnt32, int bra_beg, int bra_end, int mask, int parts,

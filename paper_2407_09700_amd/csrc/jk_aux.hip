@@ -292,6 +292,22 @@ __global__ void k_fold(FoldArgs F) {
   }
 }
 
+// The reverse of k_fold for the density: each kept pair's block of the Cartesian density, laid
+// out like the Coulomb pair buffer (element-major within a pair class).
+__global__ void k_unfold(FoldArgs F) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < F.npairs; p += gridDim.x * blockDim.x) {
+    const int c = F.pair_cls[p];
+    const int beg = F.cls_beg[c], np = F.cls_beg[c + 1] - beg;
+    const int na = ncart(F.pair_la[p]), nb = ncart(F.pair_lb[p]);
+    const int m = F.pair_mol[p];
+    const int nc = F.cbase[m + 1] - F.cbase[m];
+    const double *Dm = F.Dc + F.mc_off[m];
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < nb; ++b)
+        F.Dpair[F.jp_off[c] + (long long)(a * nb + b) * np + (p - beg)] = Dm[(size_t)(F.pair_ca[p] + a) * nc + F.pair_cb[p] + b];
+  }
+}
+
 // J[mu][nu] = sum_{a,b} T[mu][a] (Jc[a][b] + Jc[b][a]) T[nu][b], same for K (per molecule).
 __global__ void k_finalize(ShellInfo S, const double *__restrict__ Jc, const double *__restrict__ Kc,
                            double *__restrict__ J, double *__restrict__ K) {
@@ -411,6 +427,10 @@ hipError_t launch_class_room(const unsigned long long *cap, const long long *cap
 }
 hipError_t launch_fold(const FoldArgs &F, hipStream_t st) {
   hipLaunchKernelGGL(k_fold, dim3(grid_for(F.npairs, 256)), dim3(256), 0, st, F);
+  return hipGetLastError();
+}
+hipError_t launch_unfold(const FoldArgs &F, hipStream_t st) {
+  hipLaunchKernelGGL(k_unfold, dim3(grid_for(F.npairs, 256)), dim3(256), 0, st, F);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const ShellInfo &S, const double *Jc, const double *Kc, double *J, double *K,

@@ -34,6 +34,9 @@
 #ifndef JK_TEAM2_PCMAX
 #define JK_TEAM2_PCMAX 8
 #endif
+#ifndef JK_TEAM2_CO_KB
+#define JK_TEAM2_CO_KB 24     // LDS (KB) of the one-stage body's coefficient window
+#endif
 
 // Rule for 1 and 2 roots in the lane bodies: 0 the interpolation table, 1 the closed form
 // from erf/series Boys moments, 2 the closed form from Boys moments taken off a grid by Taylor
@@ -198,9 +201,12 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
 }
 
 // ================================================================== workgroup per batch
+// The ten coefficients of one (quartet, primitive quartet, root) lie CO_STRIDE doubles apart:
+// an odd stride, so that lanes reading consecutive sets fall on different LDS banks.
+constexpr int CO_STRIDE = 11;
 // Recurrence coefficients of the primitive quartets [w0, w0 + PW) of every quartet of a batch
 // and every root, computed once per window (primitive pairs, Rys root and weight):
-//   co[((q * PW + p) * N + n) * 10 + k], k = b00, b10, b01, z weight x prefactor,
+//   co[((q * PW + p) * N + n) * CO_STRIDE + k], k = b00, b10, b01, z weight x prefactor,
 //   C00 (x, y, z), C00' (x, y, z).
 template <int N, int QB, int PW>
 __device__ __forceinline__ void prim_coefs(const PrimPair *__restrict__ pp, const int *qi, const double *geo, int w0,
@@ -217,7 +223,7 @@ __device__ __forceinline__ void prim_coefs(const PrimPair *__restrict__ pp, cons
     double u, w;
     rys_root1<N>(Q.T, n, u, w);
     const double uq = u * Q.pq_inv;
-    double *c = co + (size_t)t * 10;
+    double *c = co + (size_t)t * CO_STRIDE;
     c[0] = 0.5 * uq;
     c[1] = 0.5 * Q.ip * (1.0 - uq * Q.q);
     c[2] = 0.5 * Q.iq * (1.0 - uq * Q.p);
@@ -232,7 +238,7 @@ __device__ __forceinline__ void prim_coefs(const PrimPair *__restrict__ pp, cons
 
 // primitive quartets per coefficient window: a multiple of the chunk pc within `bytes` of LDS
 constexpr int coef_window(int qb, int pc, int n, int bytes) {
-  const int m = bytes / (qb * pc * n * 80);
+  const int m = bytes / (qb * pc * n * CO_STRIDE * 8);
   return pc * (m < 1 ? 1 : m);
 }
 
@@ -268,7 +274,10 @@ struct TeamCfg {
   static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
   static constexpr int NE = range_count(LA, E), NF = range_count(LC, F);
   static constexpr int GS1 = (E + 1) * (F + 1);          // one direction of one root
-  static constexpr int GS = 3 * GS1;
+  // stride of one direction's table in LDS: odd, so that lanes writing or reading consecutive
+  // tables fall on different LDS banks (an even stride such as 16 doubles puts 32 lanes on one bank)
+  static constexpr int GT = GS1 | 1;
+  static constexpr int GS = 3 * GT;
   static constexpr int EMAXACC = JK_TEAM_EMAX;           // accumulators per lane
   // Product roles. f-major: a lane owns one f component and a slice of EPS e components
   // (NEP slices per f, each slice wave-uniform). e-major (few f, many e): a lane owns one e
@@ -300,7 +309,7 @@ struct TeamCfg {
   // per-quartet digestion accumulators: K[a,c], K[a,d], K[b,c], K[b,d] and J[c,d]
   static constexpr int DG = NA * NC + NA * ND + NB * NC + NB * ND + NC * ND;
   static constexpr int PW = coef_window(QB, PC, N, 16 * 1024);     // coefficient window (primitive quartets)
-  static constexpr int CO = QB * PW * N * 10;
+  static constexpr int CO = QB * PW * N * CO_STRIDE;
   // density blocks of the digestion: D[a,b], then per quartet D[c,d], D[a,c], D[a,d], D[b,c],
   // D[b,d] and the symmetry factor; they reuse the region of the 2D integrals and coefficients
   static constexpr int DQ = NC * ND + (NA + NB) * (NC + ND);
@@ -370,7 +379,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   using C = TeamCfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
-  constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GS1 = C::GS1, BLOCK = C::BLOCK;
+  constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GT = C::GT, BLOCK = C::BLOCK;
   constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
   double *X = buf;                    // [QB][NE][NF]  (later Z: [QB][NA*NB][NC*ND])
   double *Y = buf + QB * C::R1;       // [QB][NA*NB][NF]
@@ -385,12 +394,12 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   if (prole) {
     if constexpr (C::EMAJOR) {                 // row e of each direction's table
       xo = CTD.x[E0 + pf] * (F + 1);
-      yo = GS1 + CTD.y[E0 + pf] * (F + 1);
-      zo = 2 * GS1 + CTD.z[E0 + pf] * (F + 1);
+      yo = GT + CTD.y[E0 + pf] * (F + 1);
+      zo = 2 * GT + CTD.z[E0 + pf] * (F + 1);
     } else {                                   // column f
       xo = CTD.x[F0 + pf];
-      yo = GS1 + CTD.y[F0 + pf];
-      zo = 2 * GS1 + CTD.z[F0 + pf];
+      yo = GT + CTD.y[F0 + pf];
+      zo = 2 * GT + CTD.z[F0 + pf];
     }
   }
   if (tid == 0) {
@@ -419,8 +428,8 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
       const int dir = rem % 3;
       const int pidx = c0 + pl;
       if (pidx < qi[q * 8 + 3] * qi[q * 8 + 5]) {
-        const double *c = co + ((q * PW + (pidx - w0)) * N + n) * 10;
-        double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
+        const double *c = co + ((q * PW + (pidx - w0)) * N + n) * CO_STRIDE;
+        double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GT;
         vrr2d_store<E, F>(dst, dir == 2 ? c[3] : 1.0, c[4 + dir], c[7 + dir], c[1], c[2], c[0]);
       }
     }
@@ -590,30 +599,33 @@ struct Team2Cfg {
   static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
   static constexpr int NE = range_count(LA, E), NF = range_count(LC, F);
   static constexpr int GS1 = (E + 1) * (F + 1);
-  static constexpr int GS = 3 * GS1;
+  static constexpr int GT = GS1 | 1;
+  static constexpr int GS = 3 * GT;
   static constexpr bool OK = NE <= JK_TEAM2_NEMAX && NF <= 256;
   static constexpr int YS = NA * NB * NF;
+  static constexpr int YQ = YS | 1;                 // per-quartet stride of Y in LDS (odd: bank spread)
   static constexpr int QB0 = 256 / NF;
   // The 2D integrals of a primitive chunk and, once the primitive loop is done, the
   // bra-transferred Y share one LDS region of BUDGET doubles.
   static constexpr int BUDGET = JK_TEAM2_KB * 1024 / 8;
-  static constexpr int QB1 = BUDGET / (YS > N * GS ? YS : N * GS);   // Y fits, and one primitive chunk
+  static constexpr int QB1 = BUDGET / (YQ > N * GS ? YQ : N * GS);   // Y fits, and one primitive chunk
   static constexpr int QB = (QB0 < QB1 ? QB0 : QB1) < 1 ? 1 : (QB0 < QB1 ? QB0 : QB1);
   static constexpr int PCB = BUDGET / (QB * N * GS);
   static constexpr int PCT = JK_TEAM2_VRR_PASSES * 256 / (QB * N * 3);   // VRR items in so many passes of the block
   static constexpr int PC0 = PCB < PCT ? PCB : PCT;
   static constexpr int PC = PC0 < 1 ? 1 : (PC0 > JK_TEAM2_PCMAX ? JK_TEAM2_PCMAX : PC0);
   static constexpr int SG = QB * PC * N * GS;
-  static constexpr int SGY = SG > QB * YS ? SG : QB * YS;       // the shared region
+  static constexpr int SGY = SG > QB * YQ ? SG : QB * YQ;       // the shared region
   static constexpr int KQ = (NA + NB) * (NC + ND);               // exchange block of one quartet
-  static constexpr int PW = coef_window(QB, PC, N, 24 * 1024);   // coefficient window (primitive quartets)
-  static constexpr int CO = QB * PW * N * 10;
+  static constexpr int PW = coef_window(QB, PC, N, JK_TEAM2_CO_KB * 1024);   // coefficient window (primitive quartets)
+  static constexpr int CO = QB * PW * N * CO_STRIDE;
   static constexpr int LDS_DOUBLES = SGY + CO + QB * 12;         // + QB * KQ when K goes to global memory
   static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
 
-// Fills Y[q][ab][f] = (ab|f0) of the QB quartets described in qi/geo (same layout as team_eri).
+// Fills Y[q * YQ + ab * NF + f] = (ab|f0) of the QB quartets described in qi/geo (same layout as
+// team_eri).
 // Every thread of the block calls it; it synchronises the block. Returns Y.
 template <int LA, int LB, int LC, int LD>
 __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ pp, double *sG, double *co, double *Y,
@@ -621,7 +633,7 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
   using C = Team2Cfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB;
-  constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GS1 = C::GS1;
+  constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GT = C::GT;
   constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
   const int tid = threadIdx.x;
   const int pq_ = tid / NF;
@@ -630,8 +642,8 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
   int xo = 0, yo = 0, zo = 0;
   if (prole) {
     xo = CTD.x[F0 + pf];
-    yo = GS1 + CTD.y[F0 + pf];
-    zo = 2 * GS1 + CTD.z[F0 + pf];
+    yo = GT + CTD.y[F0 + pf];
+    zo = 2 * GT + CTD.z[F0 + pf];
   }
   if (tid == 0) {
     int m = 0;
@@ -657,8 +669,8 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
       const int dir = rem % 3;
       const int pidx = c0 + pl;
       if (pidx < qi[q * 8 + 3] * qi[q * 8 + 5]) {
-        const double *c = co + ((q * PW + (pidx - w0)) * N + n) * 10;
-        double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GS1;
+        const double *c = co + ((q * PW + (pidx - w0)) * N + n) * CO_STRIDE;
+        double *dst = sG + ((q * PC + pl) * N + n) * GS + dir * GT;
         vrr2d_store<E, F>(dst, dir == 2 ? c[3] : 1.0, c[4 + dir], c[7 + dir], c[1], c[2], c[0]);
       }
     }
@@ -718,7 +730,7 @@ __device__ __forceinline__ const double *team2_eri(const PrimPair *__restrict__ 
             }
           }
         }
-        Y[(pq_ * NA * NB + a * NB + b) * NF + pf] = v;
+        Y[pq_ * C::YQ + (a * NB + b) * NF + pf] = v;
       }
     }
   }
@@ -740,7 +752,7 @@ __device__ __forceinline__ void team2_ket(const double *Y, const double *geo, in
                CDz = geo[q * 12 + 8] - geo[q * 12 + 11];
 #pragma unroll
   for (int ab = 0; ab < NA * NB; ++ab) g[ab] = 0.0;
-  const double *Yq = Y + (size_t)q * NA * NB * NF;
+  const double *Yq = Y + (size_t)q * C::YQ;
   double px = 1.0;
   for (int kx = dx; kx >= 0; --kx) {
     double py = 1.0;

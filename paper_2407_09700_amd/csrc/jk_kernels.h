@@ -79,6 +79,7 @@ struct JKArgs {
   const long long *mbase;       // [nmol] first element of each molecule's block in Dc / Kc
   const int *mnc;               // [nmol] Cartesian AO count of each molecule
   double *Jpair;                // Coulomb accumulator per shell pair
+  const double *Dpair;          // density block D[c,d] of every kept pair, laid out as Jpair
   const long long *jp_off;      // [15] first element of each pair class in Jpair
   const int *cls_beg;           // [16] first pair of each pair class
   int nc_max;                   // largest nc_m (row length of the LDS exchange rows)
@@ -108,6 +109,13 @@ struct JKArgs {
 __device__ __forceinline__ double *jp_elem(const JKArgs &A, int cls, int pair, int e) {
   const int beg = A.cls_beg[cls];
   return A.Jpair + A.jp_off[cls] + (long long)e * (A.cls_beg[cls + 1] - beg) + (pair - beg);
+}
+
+// element e of pair `pair`'s density block in the pair-ordered copy: the kets of a segment are
+// mostly consecutive pairs, so the lanes of a wave read one element of their blocks coalesced
+__device__ __forceinline__ double dp_elem(const JKArgs &A, int cls, int pair, int e) {
+  const int beg = A.cls_beg[cls];
+  return A.Dpair[A.jp_off[cls] + (long long)e * (A.cls_beg[cls + 1] - beg) + (pair - beg)];
 }
 
 // exchange update into row `r` of the unit: LDS rows (KLDS; r < NA+NB, row length kst, column
@@ -157,9 +165,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
     if (A.want & 1) {
       double Dcd[NC * ND];
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int d = 0; d < ND; ++d) Dcd[c * ND + d] = Dm[(size_t)(oc + c) * nc + od + d];
+      for (int cd = 0; cd < NC * ND; ++cd) Dcd[cd] = dp_elem(A, ck, ki, cd);
 #pragma unroll
       for (int ab = 0; ab < NA * NB; ++ab) {
         double v = 0.0;
@@ -605,7 +611,7 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
       const int c = cd / ND, d = cd % ND;
       const int cc = ket.ca + c, dd = ket.cb + d;
       if (A.want & 1) {
-        const double dcd = Dm[(size_t)cc * nc + dd];
+        const double dcd = dp_elem(A, ck, ki, cd);
         double vj = 0.0;
 #pragma unroll
         for (int ab = 0; ab < NA * NB; ++ab) {
