@@ -345,6 +345,7 @@ void plan_free(jk_plan *p) {
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
 constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels (default)
 constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
+constexpr int BOYS_GRID_BYTES = 401 * 12 * 8;   // the Boys grid of the one- and two-root rule (boys_grid.h)
 constexpr int NFUSED = NPAIRCLASS * NTIERS;     // launch slots of the fused kernels
 constexpr int NF32_BASE = NFUSED + NQCLASS;    // slots of the FP32-only fused launches (mixed precision)
 constexpr int NSLOT = NF32_BASE + NFUSED;
@@ -864,6 +865,7 @@ struct Launch {
   int kw;            // per class with compacted LDS exchange rows: their length (0: global exchange)
   int krows;         // 1: rows of a and b in LDS, 2: rows of a, and the first kwb columns of the rows of b
   int kwb;
+  bool gl;           // per class with LDS rows: the Boys grid in LDS as well
 };
 
 // Launches of one build. active[qc]: the class has work (eager) or may have work (recording).
@@ -926,13 +928,20 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
           else
             kw = 0;
         }
+        // one- and two-root bodies: the Boys grid in LDS too, where it fits next to the rows of a
+        // and b, or next to the rows of a (the rows of b then keep fewer columns in LDS)
+        const size_t gbytes = (size_t)BOYS_GRID_BYTES;
+        const bool gl = kw > 0 && ci.launch_clslg &&
+                        (krows == 1 ? jab + (size_t)(na + nbb) * kw * 8 + gbytes <= FUSED_LDS_MAX
+                                    : jab + (size_t)na * kw * 8 + gbytes <= FUSED_LDS_MAX);
+        const size_t room = FUSED_LDS_MAX - (gl ? gbytes : 0);
         // rows of a only: the rest of the LDS holds the first kwb columns of the rows of b
-        const int kwb = krows == 2 ? (int)std::min<size_t>((size_t)kw, (FUSED_LDS_MAX - jab - (size_t)na * kw * 8) /
+        const int kwb = krows == 2 ? (int)std::min<size_t>((size_t)kw, (room - jab - (size_t)na * kw * 8) /
                                                                            ((size_t)nbb * 8))
                                    : 0;
-        const size_t klds = jab + ((size_t)(krows == 1 ? na + nbb : na) * kw + (size_t)nbb * kwb) * 8;
+        const size_t klds = jab + ((size_t)(krows == 1 ? na + nbb : na) * kw + (size_t)nbb * kwb) * 8 + (gl ? gbytes : 0);
         out.push_back(Launch{NFUSED + qc, cb, -1, qc, split, end, 1 << ck, 3, false, 0, kw ? klds : lds,
-                             ci.scratch_per_wg, kw, krows, kwb});
+                             ci.scratch_per_wg, kw, krows, kwb, gl});
       }
     }
   }
@@ -1171,7 +1180,8 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
     if (L.qc < 0)
       HIPCHK((L.f32 ? g_bras[L.cb].launch_bra32[L.tier] : g_bras[L.cb].launch_bra[L.tier])(J_, grid, L.lds, st));
     else if (L.kw > 0)
-      HIPCHK((L.krows == 1 ? g_classes[L.qc].launch_clsl : g_classes[L.qc].launch_clsa)(J_, grid, L.lds, st));
+      HIPCHK((L.krows == 1 ? (L.gl ? g_classes[L.qc].launch_clslg : g_classes[L.qc].launch_clsl)
+                           : (L.gl ? g_classes[L.qc].launch_clsag : g_classes[L.qc].launch_clsa))(J_, grid, L.lds, st));
     else
       HIPCHK(g_classes[L.qc].launch_cls(J_, grid, L.lds, st));
     if (prof) HIPCHK(hipEventRecord(ev[2 * L.slot + 1], st));
@@ -1545,6 +1555,7 @@ namespace host_boys {
 #include "boys_grid.h"
 #undef BOYS_STORAGE
 }  // namespace host_boys
+static_assert(BOYS_GRID_BYTES == BOYS_NPT * BOYS_NM * 8, "LDS size of the Boys grid");
 
 }  // namespace
 

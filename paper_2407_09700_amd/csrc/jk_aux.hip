@@ -209,36 +209,60 @@ __global__ __launch_bounds__(256) void k_screen(ScreenArgs A) {
       const double cut = ((A.f32_classes[qc >> 6] >> (qc & 63)) & 1ull) ? A.fp32_cut : 0.0;
       int kept = 0, kept32 = 0;
       unsigned long long np = 0ull, np32 = 0ull;
-      for (int k0 = 0; k0 < n; k0 += 64) {
-        const int k = k0 + lane;
-        bool keep = false, lo = false;
-        int kg = 0;
-        if (k < n) {
-          int lo_b = 0, hi_b = nb - 1;        // last bin with pref[bin] <= k
-          while (lo_b < hi_b) {
-            const int mid = (lo_b + hi_b + 1) >> 1;
-            if (pref[mid] <= k) lo_b = mid; else hi_b = mid - 1;
+      // SU chunks of 64 candidates per pass: the loads of all of them are issued before any is
+      // used (two dependent round trips per pass instead of per chunk); the chunks' kept kets are
+      // then written in candidate order
+      constexpr int SU = 4;
+      for (int k0 = 0; k0 < n; k0 += 64 * SU) {
+        int kg[SU];
+        bool in[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          const int k = k0 + u * 64 + lane;
+          in[u] = k < n;
+          kg[u] = 0;
+          if (in[u]) {
+            int lo_b = 0, hi_b = nb - 1;      // last bin with pref[bin] <= k
+            while (lo_b < hi_b) {
+              const int mid = (lo_b + hi_b + 1) >> 1;
+              if (pref[mid] <= k) lo_b = mid; else hi_b = mid - 1;
+            }
+            kg[u] = A.bin_beg[b0 + lo_b] + (k - pref[lo_b]);
           }
-          kg = A.bin_beg[b0 + lo_b] + (k - pref[lo_b]);
-          const int sc = A.pair_sa[kg] - sb0, sd = A.pair_sb[kg] - sb0;
+        }
+        int sc[SU], sd[SU];
+        double ik[SU], pk[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          sc[u] = in[u] ? A.pair_sa[kg[u]] - sb0 : 0;
+          sd[u] = in[u] ? A.pair_sb[kg[u]] - sb0 : 0;
+          ik[u] = in[u] ? A.pairI[kg[u]] : 0.0;
+          pk[u] = in[u] && (A.want & 1) ? A.pairP[kg[u]] : 0.0;
+        }
+        bool keep[SU], lo[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
           // largest density block the quartet's updates read: D[a,b], D[c,d] (Coulomb),
           // D[a,c], D[a,d], D[b,c], D[b,d] (exchange)
           double p = 0.0;
-          if (A.want & 1) p = fmax(pab, A.pairP[kg]);
-          if (A.want & 2) p = fmax(fmax(p, fmax(Pa[sc], Pa[sd])), fmax(Pb[sc], Pb[sd]));
-          const double bound = Ib * A.pairI[kg] * p;
-          keep = bound >= tau;
-          lo = keep && bound < cut;            // mixed precision: evaluated in FP32
-          if (keep) np += nppb * (unsigned long long)A.pair_npp[kg];
-          if (lo) np32 += nppb * (unsigned long long)A.pair_npp[kg];
+          if (A.want & 1) p = fmax(pab, pk[u]);
+          if (A.want & 2) p = fmax(fmax(p, fmax(Pa[sc[u]], Pa[sd[u]])), fmax(Pb[sc[u]], Pb[sd[u]]));
+          const double bound = Ib * ik[u] * p;
+          keep[u] = in[u] && bound >= tau;
+          lo[u] = keep[u] && bound < cut;      // mixed precision: evaluated in FP32
         }
-        // FP64 kets fill the segment from the front, FP32 kets from the back
-        const unsigned long long below = (1ull << lane) - 1ull;
-        const unsigned long long m64 = __ballot(keep && !lo), m32 = __ballot(lo);
-        if (keep && !lo) out[kept + __popcll(m64 & below)] = kg;
-        if (lo) out[n - 1 - (kept32 + __popcll(m32 & below))] = kg;
-        kept += __popcll(m64);
-        kept32 += __popcll(m32);
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          if (keep[u]) np += nppb * (unsigned long long)A.pair_npp[kg[u]];
+          if (lo[u]) np32 += nppb * (unsigned long long)A.pair_npp[kg[u]];
+          // FP64 kets fill the segment from the front, FP32 kets from the back
+          const unsigned long long below = (1ull << lane) - 1ull;
+          const unsigned long long m64 = __ballot(keep[u] && !lo[u]), m32 = __ballot(lo[u]);
+          if (keep[u] && !lo[u]) out[kept + __popcll(m64 & below)] = kg[u];
+          if (lo[u]) out[n - 1 - (kept32 + __popcll(m32 & below))] = kg[u];
+          kept += __popcll(m64);
+          kept32 += __popcll(m32);
+        }
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {

@@ -15,9 +15,9 @@ void allow_dyn_lds(F *fn) {
   (void)hipGetLastError();   // the attribute is a hint; do not leave its status for a launch check
 }
 
-template <int LA, int LB, int LC, int LD, int KL = 0>
+template <int LA, int LB, int LC, int LD, int KL = 0, bool GL = false>
 hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((k_cls<LA, LB, LC, LD, KL>), dim3(grid), dim3(cls_threads<LA, LB, LC, LD, KL>()), lds, stream,
+  hipLaunchKernelGGL((k_cls<LA, LB, LC, LD, KL, GL>), dim3(grid), dim3(cls_threads<LA, LB, LC, LD, KL>()), lds, stream,
                      args);
   return hipGetLastError();
 }
@@ -63,9 +63,20 @@ void register_one(ClassInfo *table) {
     ci.launch_clsa = launch_cls<LA, LB, LC, LD, 2>;
     allow_dyn_lds(k_cls<LA, LB, LC, LD, 1>);
     allow_dyn_lds(k_cls<LA, LB, LC, LD, 2>);
+    if constexpr (SmallCfg<LA, LB, LC, LD>::N <= 2 && JK_GRID_LDS) {
+      ci.launch_clslg = launch_cls<LA, LB, LC, LD, 1, true>;
+      ci.launch_clsag = launch_cls<LA, LB, LC, LD, 2, true>;
+      allow_dyn_lds(k_cls<LA, LB, LC, LD, 1, true>);
+      allow_dyn_lds(k_cls<LA, LB, LC, LD, 2, true>);
+    } else {
+      ci.launch_clslg = nullptr;
+      ci.launch_clsag = nullptr;
+    }
   } else {
     ci.launch_clsl = nullptr;
     ci.launch_clsa = nullptr;
+    ci.launch_clslg = nullptr;
+    ci.launch_clsag = nullptr;
   }
   ci.launch_mode[MODE_JK] = nullptr;
   ci.launch_mode[MODE_SCHWARZ] = (LA == LC && LB == LD) ? launch_mode<LA, LB, LC, LD, MODE_SCHWARZ> : nullptr;

@@ -207,9 +207,10 @@ __host__ __device__ __forceinline__ void rys_taylor(double T, const double *grid
   }
 }
 
-// All N roots (N = 1, 2) by the grid rule, the Gauss-Hermite limit beyond RYS_TMAX[N].
+// All N roots (N = 1, 2) by the grid rule, the Gauss-Hermite limit beyond RYS_TMAX[N]. grid:
+// BOYS_GRID, or a copy of it in LDS.
 template <int N>
-__device__ __forceinline__ void rys_low(double T, double (&u)[N], double (&w)[N]) {
+__device__ __forceinline__ void rys_low(double T, double (&u)[N], double (&w)[N], const double *grid = BOYS_GRID) {
   if (T >= (double)RYS_TMAX[N]) {
     const double it = 1.0 / T;
     const double isq = sqrt(it);
@@ -219,7 +220,7 @@ __device__ __forceinline__ void rys_low(double T, double (&u)[N], double (&w)[N]
       w[n] = RYS_HERM_W[RYS_HOFF[N] + n] * isq;
     }
   } else {
-    rys_taylor<N>(T, BOYS_GRID, u, w);
+    rys_taylor<N>(T, grid, u, w);
   }
 }
 

@@ -37,6 +37,9 @@
 #ifndef JK_TEAM2_CO_KB
 #define JK_TEAM2_CO_KB 24     // LDS (KB) of the one-stage body's coefficient window
 #endif
+// LDS per workgroup (bytes) under which two one-stage workgroups fit one CU (160 KB, less the
+// bra Coulomb block and slack)
+constexpr int TEAM2_PAIR_LDS = 78 * 1024;
 
 // Rule for 1 and 2 roots in the lane bodies: 0 the interpolation table, 1 the closed form
 // from erf/series Boys moments, 2 the closed form from Boys moments taken off a grid by Taylor
@@ -63,9 +66,10 @@ struct SmallCfg {
 // R: type of the 2D integrals, their products and the transfer (double, or float for the
 // FP32 quartets of mixed precision; roots, weights, the per-primitive scalars and the sum over
 // primitive quartets and roots stay double).
+// grid: the Boys-function grid of the one- and two-root rule (BOYS_GRID or an LDS copy).
 template <int LA, int LB, int LC, int LD, typename R = double>
 __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, const PrimPair *__restrict__ pp,
-                                          R (&g)[SmallCfg<LA, LB, LC, LD>::NG]) {
+                                          R (&g)[SmallCfg<LA, LB, LC, LD>::NG], const double *grid = BOYS_GRID) {
   using C = SmallCfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
@@ -113,7 +117,7 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
         if constexpr (JK_LOW_ROOTS == 1)
           rys_closed<N>(Q.T, u, w);
         else
-          rys_low<N>(Q.T, u, w);
+          rys_low<N>(Q.T, u, w, grid);
 #pragma unroll
         for (int n = 0; n < N; ++n) root(u[n], w[n]);
       } else {
@@ -617,10 +621,18 @@ struct Team2Cfg {
   static constexpr int SG = QB * PC * N * GS;
   static constexpr int SGY = SG > QB * YQ ? SG : QB * YQ;       // the shared region
   static constexpr int KQ = (NA + NB) * (NC + ND);               // exchange block of one quartet
-  static constexpr int PW = coef_window(QB, PC, N, JK_TEAM2_CO_KB * 1024);   // coefficient window (primitive quartets)
+  static constexpr int LDS_INTS = QB * 8 + 2;
+  // LDS of a workgroup whose exchange goes to global memory (per-quartet blocks) for a
+  // coefficient window of pw primitive quartets
+  static constexpr int bytes_for(int pw) { return (SGY + QB * pw * N * CO_STRIDE + QB * 12 + QB * KQ) * 8 + LDS_INTS * 4; }
+  // Coefficient window (primitive quartets): JK_TEAM2_CO_KB of LDS, or half of it where that
+  // lets two workgroups share a CU (fewer primitive quartets per window, more waves in flight)
+  static constexpr int PW_FULL = coef_window(QB, PC, N, JK_TEAM2_CO_KB * 1024);
+  static constexpr int PW_HALF = coef_window(QB, PC, N, JK_TEAM2_CO_KB * 512);
+  static constexpr bool HALF_CO = bytes_for(PW_FULL) > TEAM2_PAIR_LDS && bytes_for(PW_HALF) <= TEAM2_PAIR_LDS;
+  static constexpr int PW = HALF_CO ? PW_HALF : PW_FULL;
   static constexpr int CO = QB * PW * N * CO_STRIDE;
   static constexpr int LDS_DOUBLES = SGY + CO + QB * 12;         // + QB * KQ when K goes to global memory
-  static constexpr int LDS_INTS = QB * 8 + 2;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
 
