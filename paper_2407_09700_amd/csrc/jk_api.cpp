@@ -345,7 +345,6 @@ void plan_free(jk_plan *p) {
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
 constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels (default)
 constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
-constexpr int BOYS_GRID_BYTES = 401 * 12 * 8;   // the Boys grid of the one- and two-root rule (boys_grid.h)
 constexpr int NFUSED = NPAIRCLASS * NTIERS;     // launch slots of the fused kernels
 constexpr int NF32_BASE = NFUSED + NQCLASS;    // slots of the FP32-only fused launches (mixed precision)
 constexpr int NSLOT = NF32_BASE + NFUSED;
@@ -928,9 +927,9 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
           else
             kw = 0;
         }
-        // one- and two-root bodies: the Boys grid in LDS too, where it fits next to the rows of a
-        // and b, or next to the rows of a (the rows of b then keep fewer columns in LDS)
-        const size_t gbytes = (size_t)BOYS_GRID_BYTES;
+        // lane bodies of few roots: their root table in LDS too, where it fits next to the rows of
+        // a and b, or next to the rows of a (the rows of b then keep fewer columns in LDS)
+        const size_t gbytes = (size_t)ci.table_lds;
         const bool gl = kw > 0 && ci.launch_clslg &&
                         (krows == 1 ? jab + (size_t)(na + nbb) * kw * 8 + gbytes <= FUSED_LDS_MAX
                                     : jab + (size_t)na * kw * 8 + gbytes <= FUSED_LDS_MAX);
@@ -1555,7 +1554,6 @@ namespace host_boys {
 #include "boys_grid.h"
 #undef BOYS_STORAGE
 }  // namespace host_boys
-static_assert(BOYS_GRID_BYTES == BOYS_NPT * BOYS_NM * 8, "LDS size of the Boys grid");
 
 }  // namespace
 

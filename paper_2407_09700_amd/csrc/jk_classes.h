@@ -20,8 +20,9 @@ struct ClassInfo {           // one quartet class (la lb | lc ld)
   jk_launch_fn launch_cls;   // k_cls (exchange to global memory)
   jk_launch_fn launch_clsl;  // k_cls with compacted LDS exchange rows (lane bodies; null for team classes)
   jk_launch_fn launch_clsa;  // the same with only the rows of a in LDS
-  jk_launch_fn launch_clslg; // the two above with the Boys grid in LDS (one- and two-root lane bodies; else null)
+  jk_launch_fn launch_clslg; // the two above with the root table in LDS (lane bodies of few roots; else null)
   jk_launch_fn launch_clsag;
+  int table_lds;             // bytes of that root table
   mode_launch_fn launch_mode[3];
 };
 

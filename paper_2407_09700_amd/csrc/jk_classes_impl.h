@@ -61,9 +61,10 @@ void register_one(ClassInfo *table) {
   if constexpr (!use_team<LA, LB, LC, LD>()) {
     ci.launch_clsl = launch_cls<LA, LB, LC, LD, 1>;
     ci.launch_clsa = launch_cls<LA, LB, LC, LD, 2>;
+    ci.table_lds = (int)(root_table_doubles<SmallCfg<LA, LB, LC, LD>::N>() * sizeof(double));
     allow_dyn_lds(k_cls<LA, LB, LC, LD, 1>);
     allow_dyn_lds(k_cls<LA, LB, LC, LD, 2>);
-    if constexpr (SmallCfg<LA, LB, LC, LD>::N <= 2 && JK_GRID_LDS) {
+    if constexpr (SmallCfg<LA, LB, LC, LD>::N <= JK_TABLE_LDS_NMAX) {
       ci.launch_clslg = launch_cls<LA, LB, LC, LD, 1, true>;
       ci.launch_clsag = launch_cls<LA, LB, LC, LD, 2, true>;
       allow_dyn_lds(k_cls<LA, LB, LC, LD, 1, true>);
@@ -75,6 +76,7 @@ void register_one(ClassInfo *table) {
   } else {
     ci.launch_clsl = nullptr;
     ci.launch_clsa = nullptr;
+    ci.table_lds = 0;
     ci.launch_clslg = nullptr;
     ci.launch_clsag = nullptr;
   }

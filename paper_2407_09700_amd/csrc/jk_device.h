@@ -225,8 +225,9 @@ __device__ __forceinline__ void rys_low(double T, double (&u)[N], double (&w)[N]
 }
 
 // One root n (run-time) of the N-point rule (table).
+// coef: the N-root block of RYS_COEF (RYS_COEF + RYS_OFF[N], or a copy of it in LDS).
 template <int N>
-__device__ __forceinline__ void rys_root1(double T, int n, double &u, double &w) {
+__device__ __forceinline__ void rys_root1(double T, int n, double &u, double &w, const double *coef = RYS_COEF + RYS_OFF[N]) {
   if (T >= (double)RYS_TMAX[N]) {
     const double it = 1.0 / T;
     u = RYS_HERM_S2[RYS_HOFF[N] + n] * it;
@@ -234,7 +235,7 @@ __device__ __forceinline__ void rys_root1(double T, int n, double &u, double &w)
   } else {
     const int k = min(max((int)T, 0), RYS_TMAX[N] - 1);
     const double s = 2.0 * (T - (double)k) - 1.0;
-    const double *cu = RYS_COEF + RYS_OFF[N] + k * (N * 2 * (RYS_DEG + 1)) + n * 2 * (RYS_DEG + 1);
+    const double *cu = coef + k * (N * 2 * (RYS_DEG + 1)) + n * 2 * (RYS_DEG + 1);
     const double *cw = cu + (RYS_DEG + 1);
     double pu = cu[RYS_DEG], pw = cw[RYS_DEG];
 #pragma unroll
@@ -245,6 +246,18 @@ __device__ __forceinline__ void rys_root1(double T, int n, double &u, double &w)
     u = pu;
     w = pw;
   }
+}
+
+// The table the roots of an N-point rule read in the lane bodies: the Boys grid (N <= 2, grid
+// rule) or the N-root block of the interpolation table; its size in doubles.
+template <int N>
+__device__ __forceinline__ const double *root_table() {
+  if constexpr (N <= 2) return BOYS_GRID;
+  else return RYS_COEF + RYS_OFF[N];
+}
+template <int N>
+constexpr int root_table_doubles() {
+  return N <= 2 ? BOYS_NPT * BOYS_NM : RYS_OFF[N + 1] - RYS_OFF[N];
 }
 
 // ------------------------------------------------------------------ 2D recurrence

@@ -66,10 +66,11 @@ struct SmallCfg {
 // R: type of the 2D integrals, their products and the transfer (double, or float for the
 // FP32 quartets of mixed precision; roots, weights, the per-primitive scalars and the sum over
 // primitive quartets and roots stay double).
-// grid: the Boys-function grid of the one- and two-root rule (BOYS_GRID or an LDS copy).
+// table: an LDS copy of root_table<N>() (the Boys grid of the one- and two-root rule, or the
+// N-root block of the interpolation table), or null for the table itself.
 template <int LA, int LB, int LC, int LD, typename R = double>
 __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, const PrimPair *__restrict__ pp,
-                                          R (&g)[SmallCfg<LA, LB, LC, LD>::NG], const double *grid = BOYS_GRID) {
+                                          R (&g)[SmallCfg<LA, LB, LC, LD>::NG], const double *table = nullptr) {
   using C = SmallCfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
@@ -79,6 +80,7 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
   double acc[NE * NF];
 #pragma unroll
   for (int i = 0; i < NE * NF; ++i) acc[i] = 0.0;
+  const double *tab = table ? table : root_table<N>();
 
   // ket primitives outside: their loads differ from lane to lane, the bra's are the same for
   // every lane of the workgroup (one cache line per wave)
@@ -117,14 +119,14 @@ __device__ __forceinline__ void small_eri(const Pair &bra, const Pair &ket, cons
         if constexpr (JK_LOW_ROOTS == 1)
           rys_closed<N>(Q.T, u, w);
         else
-          rys_low<N>(Q.T, u, w, grid);
+          rys_low<N>(Q.T, u, w, tab);
 #pragma unroll
         for (int n = 0; n < N; ++n) root(u[n], w[n]);
       } else {
 #pragma unroll 1
         for (int n = 0; n < N; ++n) {
           double un, wn;
-          rys_root1<N>(Q.T, n, un, wn);
+          rys_root1<N>(Q.T, n, un, wn, tab);
           root(un, wn);
         }
       }

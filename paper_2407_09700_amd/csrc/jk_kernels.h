@@ -140,7 +140,7 @@ __device__ __forceinline__ void k_update(double *Krow, double *Km, int kst, int 
 template <int LA, int LB, int LC, int LD, bool KLDS, typename R = double, bool KMAP = false, bool KLB = true>
 __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int *kl, int cnt, double *Krow,
                                               double (&jab)[ncart(LA) * ncart(LB)], int rot, int kdofs = 0,
-                                              int kst_map = 0, const double *grid = BOYS_GRID) {
+                                              int kst_map = 0, const double *table = nullptr) {
   using C = SmallCfg<LA, LB, LC, LD>;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int ck = pair_class(LC, LD);
@@ -159,7 +159,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
     const int ki = kl[k];
     const Pair ket = A.pairs[ki];
     R g[C::NG];                 // FP32 integrals stay FP32 in registers; each use widens to double
-    small_eri<LA, LB, LC, LD, R>(bra, ket, A.pp, g, grid);
+    small_eri<LA, LB, LC, LD, R>(bra, ket, A.pp, g, table);
     const double s = sym_factor(bra, ket, bi, ki);
     const int oc = ket.ca, od = ket.cb;
     if (A.want & 1) {
@@ -847,9 +847,12 @@ constexpr int cls_block() { return team_block<LA, LB, LC, LD>(); }
 #ifndef JK_CLS_LDS_BLOCK
 #define JK_CLS_LDS_BLOCK 512
 #endif
-// Boys grid in LDS for the one- and two-root lane bodies of k_cls with LDS rows (where it fits)
-#ifndef JK_GRID_LDS
-#define JK_GRID_LDS 1
+// Root tables in LDS for the lane bodies of k_cls with LDS rows of up to this many roots
+// (where they fit): the Boys grid for one and two roots (38.5 KB; 10 or 12 doubles per lookup
+// from a different row per lane). The three-root block of the interpolation table (32.3 KB, 72
+// doubles per lookup in runs of 24) measured slower from LDS than from the caches.
+#ifndef JK_TABLE_LDS_NMAX
+#define JK_TABLE_LDS_NMAX 2
 #endif
 template <int LA, int LB, int LC, int LD, int KL>
 constexpr int cls_threads() {
@@ -866,7 +869,7 @@ template <int LA, int LB, int LC, int LD, int KL = 0, bool GL = false>
 __global__ __launch_bounds__((cls_threads<LA, LB, LC, LD, KL>())) void k_cls(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB), ck = pair_class(LC, LD);
   static_assert(!KL || !use_team<LA, LB, LC, LD>(), "compacted LDS rows are for the lane bodies");
-  static_assert(!GL || (KL && SmallCfg<LA, LB, LC, LD>::N <= 2), "the LDS grid is for one- and two-root lane bodies");
+  static_assert(!GL || (KL && SmallCfg<LA, LB, LC, LD>::N <= JK_TABLE_LDS_NMAX), "LDS root tables: lane bodies");
   constexpr int RL = KL == 1 ? NA + NB : NA;    // full exchange rows held in LDS
   extern __shared__ double smem[];
   __shared__ int s_unit;
@@ -877,14 +880,17 @@ __global__ __launch_bounds__((cls_threads<LA, LB, LC, LD, KL>())) void k_cls(JKA
   const int tid = threadIdx.x;
   if constexpr (KL != 0)   // the rows start at zero; each unit's flush puts back the zeros it reads
     for (int t = tid; t < RL * A.kw + (KL == 2 ? NB * A.kwb : 0); t += blockDim.x) Krow[t] = 0.0;
-  // GL: the Boys-function grid of the one- and two-root rule copied to LDS after the rows, so
-  // that its per-lane lookups (a different row for nearly every lane) are LDS reads rather than
-  // vector-memory gathers (visible after the loop's first barrier)
-  const double *grid = BOYS_GRID;
+  // GL: the table the roots read (the Boys grid for one and two roots, else the N-root block of
+  // the interpolation table) copied to LDS after the rows, so that its per-lane lookups (a
+  // different row for nearly every lane) are LDS reads rather than vector-memory gathers
+  // (visible after the loop's first barrier)
+  const double *table = nullptr;
   if constexpr (GL) {
-    double *gs = Krow + RL * A.kw + (KL == 2 ? NB * A.kwb : 0);
-    for (int t = tid; t < BOYS_NPT * BOYS_NM; t += blockDim.x) gs[t] = BOYS_GRID[t];
-    grid = gs;
+    constexpr int N = SmallCfg<LA, LB, LC, LD>::N;
+    double *ts = Krow + RL * A.kw + (KL == 2 ? NB * A.kwb : 0);
+    const double *src = root_table<N>();
+    for (int t = tid; t < root_table_doubles<N>(); t += blockDim.x) ts[t] = src[t];
+    table = ts;
   }
   for (;;) {
     if (tid == 0) s_unit = atomicAdd(A.next, 1);
@@ -933,10 +939,10 @@ __global__ __launch_bounds__((cls_threads<LA, LB, LC, LD, KL>())) void k_cls(JKA
         for (int e = 0; e < NA * NB; ++e) jab[e] = 0.0;
         if (cnt)
           jk_small_body<LA, LB, LC, LD, true, double, true, KL == 1>(A, bi, cls_kets + A.segoff[sg], cnt, Krow, jab, 0,
-                                                                     kdofs, kw, grid);
+                                                                     kdofs, kw, table);
         if (cnt32)
           jk_small_body<LA, LB, LC, LD, true, float, true, KL == 1>(A, bi, cls_kets32 + A.segoff32[sg], cnt32, Krow,
-                                                                    jab, 0, kdofs, kw, grid);
+                                                                    jab, 0, kdofs, kw, table);
         jab_reduce<NA * NB>(jab, jab_s);
         __syncthreads();
         const int nc = A.mnc[m];
