@@ -24,8 +24,9 @@ hipError_t launch_cls(const JKArgs &args, int grid, size_t lds, hipStream_t stre
 
 template <int LA, int LB, int LC, int LD, int MODE>
 hipError_t launch_mode(const ModeArgs &args, int grid, hipStream_t stream) {
-  constexpr int block = use_team<LA, LB, LC, LD>() ? TeamCfg<LA, LB, LC, LD>::BLOCK : 256;
-  hipLaunchKernelGGL((k_mode<LA, LB, LC, LD, MODE>), dim3(grid), dim3(block), 0, stream, args);
+  constexpr int block = mode_block<LA, LB, LC, LD, MODE>();
+  constexpr size_t lds = (size_t)mode_lds<LA, LB, LC, LD, MODE>();
+  hipLaunchKernelGGL((k_mode<LA, LB, LC, LD, MODE>), dim3(grid), dim3(block), lds, stream, args);
   return hipGetLastError();
 }
 
@@ -83,6 +84,7 @@ void register_one(ClassInfo *table) {
   ci.launch_mode[MODE_JK] = nullptr;
   ci.launch_mode[MODE_SCHWARZ] = (LA == LC && LB == LD) ? launch_mode<LA, LB, LC, LD, MODE_SCHWARZ> : nullptr;
   ci.launch_mode[MODE_ERI] = launch_mode<LA, LB, LC, LD, MODE_ERI>;
+  if constexpr (mode_lds<LA, LB, LC, LD, MODE_ERI>() > 0) allow_dyn_lds(k_mode<LA, LB, LC, LD, MODE_ERI>);
 }
 
 template <int LA, int LB, int P = 0>

@@ -1011,13 +1011,52 @@ __device__ __forceinline__ void eri_store8(double *out, size_t nc, size_t i, siz
   out[((l * nc + k) * nc + j) * nc + i] = v;
 }
 
-template <int LA, int LB, int LC, int LD>
-constexpr int mode_block() { return use_team<LA, LB, LC, LD>() ? TeamCfg<LA, LB, LC, LD>::BLOCK : 256; }
+// The ERI tensor of a one-stage class comes from the one-stage body (the body its J/K build
+// runs), so that the tensor test checks that body element by element; its LDS is dynamic.
+template <int LA, int LB, int LC, int LD, int MODE>
+constexpr bool mode_team2() { return MODE == MODE_ERI && use_team2<LA, LB, LC, LD>(); }
+template <int LA, int LB, int LC, int LD, int MODE>
+constexpr int mode_lds() { return mode_team2<LA, LB, LC, LD, MODE>() ? Team2Cfg<LA, LB, LC, LD>::LDS_BYTES : 0; }
 
 template <int LA, int LB, int LC, int LD, int MODE>
-__global__ __launch_bounds__((mode_block<LA, LB, LC, LD>())) void k_mode(ModeArgs M) {
+constexpr int mode_block() {
+  return use_team<LA, LB, LC, LD>() && !mode_team2<LA, LB, LC, LD, MODE>() ? TeamCfg<LA, LB, LC, LD>::BLOCK : 256;
+}
+
+template <int LA, int LB, int LC, int LD, int MODE>
+__global__ __launch_bounds__((mode_block<LA, LB, LC, LD, MODE>())) void k_mode(ModeArgs M) {
   constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
-  if constexpr (use_team<LA, LB, LC, LD>()) {
+  if constexpr (mode_team2<LA, LB, LC, LD, MODE>()) {
+    using C = Team2Cfg<LA, LB, LC, LD>;
+    extern __shared__ double dyn[];
+    double *sG = dyn;                    // 2D integrals, then Y (team2_eri)
+    double *co = dyn + C::SGY;
+    double *geo = co + C::CO;
+    int *qi = reinterpret_cast<int *>(geo + C::QB * 12);
+    int *smax = qi + C::QB * 8;
+    const int nbatch = (M.count + C::QB - 1) / C::QB;
+    for (int batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
+      if (threadIdx.x < C::QB) {
+        const int q = batch * C::QB + threadIdx.x;
+        const bool valid = q < M.count;
+        const int2 qd = M.quartets[valid ? q : batch * C::QB];
+        team_fill<LA, LB, LC, LD>(threadIdx.x, M.pairs[qd.x], M.pairs[qd.y], qd.x, qd.y, valid, qi, geo);
+      }
+      __syncthreads();
+      const double *Y = team2_eri<LA, LB, LC, LD>(M.pp, sG, co, sG, qi, geo, smax);
+      for (int t = threadIdx.x; t < C::QB * NC * ND; t += blockDim.x) {
+        const int q = t / (NC * ND), cd = t % (NC * ND);
+        if (!qi[q * 8 + 6]) continue;
+        double g[NA * NB];
+        team2_ket<LA, LB, LC, LD>(Y, geo, q, cd, g);
+        const Pair &bra = M.pairs[qi[q * 8]];
+        const Pair &ket = M.pairs[qi[q * 8 + 1]];
+        for (int ab = 0; ab < NA * NB; ++ab)
+          eri_store8(M.out, M.nc, bra.ca + ab / NB, bra.cb + ab % NB, ket.ca + cd / ND, ket.cb + cd % ND, g[ab]);
+      }
+      __syncthreads();
+    }
+  } else if constexpr (use_team<LA, LB, LC, LD>()) {
     using C = TeamCfg<LA, LB, LC, LD>;
     __shared__ double sG[C::SG];
     __shared__ double sCo[C::CO];

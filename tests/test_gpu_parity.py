@@ -41,6 +41,22 @@ def test_cfg1_eri_tensor():
     assert d <= 1e-12 * np.max(np.abs(Eo))
 
 
+def test_eri_tensor_every_class_up_to_g():
+    # two atoms with one Cartesian shell of each l (0..4): all 120 classes, element by element,
+    # through the body each class's J/K build runs (lane, one-stage or two-stage workgroup body)
+    from paper_2407_09700_amd import jk
+    coords = [[0.0, 0.0, 0.0], [1.7, 0.3, -0.4]]
+    mol = synth.custom(coords, [(0, 3), (1, 2), (2, 2), (3, 1), (4, 2)], 0.25, 6.0, pure_from_l=99, nocc=5, seed=4)
+    say(f"[eri all classes] nbf {mol.nbf}")
+    plan = jk.Plan.from_molecule(mol, thresh=0.0)
+    E = plan.eri_tensor().cpu().numpy()
+    plan.close()
+    Eo = oracle.Oracle(mol).eri_tensor()
+    d = maxabs(E, Eo)
+    say(f"[eri all classes] max|dERI|={d:.3e} max|ERI|={np.max(np.abs(Eo)):.3e}")
+    assert d <= 1e-10
+
+
 def test_cfg1_jk_exact():
     _check(synth.make_config(1), thresh=0.0, tag="cfg1")
 
