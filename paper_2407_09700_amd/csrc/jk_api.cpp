@@ -279,9 +279,11 @@ struct jk_plan {
   std::vector<hipEvent_t> events;
   int ev_next = 0, ev_count = 0;
   std::vector<int> launched;           // launch slots used by the last eager execute
+  std::vector<int> ev_launched;        // launch slots of the builds in the event ring (one launch set)
   std::vector<int> grid;               // per launch slot: workgroups (0 = default)
   bool tuned = false;
   std::vector<char> fuse;              // [NFUSED] lane tier (cb, tier) runs fused (1) or per class (0)
+  std::vector<char> shape;             // [NQCLASS] per-class launch shape (SHAPE_* bits; tuner's choice)
   int *d_kets = nullptr;
   long long list_capacity = 0;
   double *d_scratch = nullptr;
@@ -345,6 +347,11 @@ void plan_free(jk_plan *p) {
 constexpr int GRID_SMALL_MAX = 4096;   // workgroups of 256 lanes (lane-per-quartet mode kernels)
 constexpr int GRID_TEAM_MAX = 1024;    // persistent workgroups of the J/K kernels and team mode kernels (default)
 constexpr size_t FUSED_LDS_MAX = 150 * 1024;   // dynamic LDS of k_bra (the CU has 160 KB)
+// Shapes of a per-class lane-body launch with LDS exchange rows, picked per class by the tuner:
+// the default (root table in LDS where it fits, rows of a and b in LDS where they fit), or
+// without the root table in LDS, or with only the rows of a in LDS (the rows of b keep as many
+// leading columns as the rest of the LDS holds).
+constexpr int SHAPE_NO_TABLE = 1, SHAPE_ROWS_A = 2, NSHAPE = 3;
 constexpr int NFUSED = NPAIRCLASS * NTIERS;     // launch slots of the fused kernels
 constexpr int NF32_BASE = NFUSED + NQCLASS;    // slots of the FP32-only fused launches (mixed precision)
 constexpr int NSLOT = NF32_BASE + NFUSED;
@@ -824,6 +831,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
   p->grid.assign(NSLOT, 0);
   p->slice.assign(NSLOT, 0);
   p->fuse.assign(NFUSED, 0);
+  p->shape.assign(NQCLASS, 0);
   for (int f = 0; f < NFUSED; ++f) p->fuse[f] = (f % NTIERS == TEAM_TIER) ? 1 : JK_FUSE_LANE_TIERS;
   p->units_est.assign(NSLOT, 0);
   if (p->flags & (JK_FLAG_PROFILE | JK_FLAG_TUNE)) {
@@ -920,7 +928,7 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
             const int w = seg[ci.lc + 1] - seg[ci.lc] + (ci.lc != ci.ld ? seg[ci.ld + 1] - seg[ci.ld] : 0);
             kw = std::max(kw, w);
           }
-          if (kw > 0 && jab + (size_t)(na + nbb) * kw * 8 <= FUSED_LDS_MAX)
+          if (kw > 0 && jab + (size_t)(na + nbb) * kw * 8 <= FUSED_LDS_MAX && !(p->shape[qc] & SHAPE_ROWS_A))
             krows = 1;
           else if (kw > 0 && jab + (size_t)na * kw * 8 <= FUSED_LDS_MAX)
             krows = 2;
@@ -930,7 +938,7 @@ void plan_launches(const jk_plan *p, const bool *active, std::vector<Launch> &ou
         // lane bodies of few roots: their root table in LDS too, where it fits next to the rows of
         // a and b, or next to the rows of a (the rows of b then keep fewer columns in LDS)
         const size_t gbytes = (size_t)ci.table_lds;
-        const bool gl = kw > 0 && ci.launch_clslg &&
+        const bool gl = kw > 0 && ci.launch_clslg && !(p->shape[qc] & SHAPE_NO_TABLE) &&
                         (krows == 1 ? jab + (size_t)(na + nbb) * kw * 8 + gbytes <= FUSED_LDS_MAX
                                     : jab + (size_t)na * kw * 8 + gbytes <= FUSED_LDS_MAX);
         const size_t room = FUSED_LDS_MAX - (gl ? gbytes : 0);
@@ -1191,6 +1199,11 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   HIPCHK(launch_finalize(p->S, p->d_Jc, p->d_Kc, (J_.want & 1) ? J : nullptr, (J_.want & 2) ? K : nullptr, st));
   if (prof) {
     HIPCHK(hipEventRecord(ev[2 * NSLOT + 3], st));
+    // the ring averages builds of one launch set: a build with other launches starts it anew
+    if (p->launched != p->ev_launched) {
+      p->ev_count = 0;
+      p->ev_launched = p->launched;
+    }
     p->ev_next = (p->ev_next + 1) % EV_SETS;
     p->ev_count = std::min(p->ev_count + 1, EV_SETS);
   }
@@ -1254,6 +1267,11 @@ bool load_tune_cache(jk_plan *p) {
         if ("fuse:" + slot_name(s) == nm) p->fuse[s] = g != 0;
       continue;
     }
+    if (nm.rfind("shape:", 0) == 0) {        // shape:k_cls<la,lb,lc,ld> SHAPE_* bits
+      for (int qc = 0; qc < NQCLASS; ++qc)
+        if ("shape:" + slot_name(NFUSED + qc) == nm && g >= 0 && g < 4) p->shape[qc] = (char)g;
+      continue;
+    }
     for (int s = 0; s < NSLOT; ++s)
       if (slot_name(s) == nm && g > 0 && g <= 65536) {
         p->grid[s] = g;
@@ -1273,6 +1291,8 @@ void save_tune_cache(const jk_plan *p) {
   for (int s = 0; s < NFUSED; ++s)
     if (s % NTIERS != TEAM_TIER && g_bras[s / NTIERS].fusable[s % NTIERS])
       fprintf(f, "fuse:%s %d\n", slot_name(s).c_str(), (int)p->fuse[s]);
+  for (int qc = 0; qc < NQCLASS; ++qc)
+    if (p->shape[qc]) fprintf(f, "shape:%s %d\n", slot_name(NFUSED + qc).c_str(), (int)p->shape[qc]);
   fclose(f);
 }
 
@@ -1325,10 +1345,11 @@ int time_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st
 }
 
 // The tuner: for every register tier of lane bodies, whether its ket classes run fused (one
-// launch per bra class, full exchange rows in LDS) or per class (compacted rows), and for every
-// launch the workgroup count. Both layouts are timed at every candidate count; a tier keeps the
-// layout whose launches (fused launch and the per-class launches of molecules too large for it,
-// against the per-class launches alone) take less time.
+// launch per bra class, full exchange rows in LDS) or per class (compacted rows), for every
+// per-class launch its shape (SHAPE_*), and for every launch the workgroup count. Every layout
+// and shape is timed at every candidate count; a tier keeps the layout whose launches (fused
+// launch and the per-class launches of molecules too large for it, against the per-class
+// launches alone) take less time, and each class its fastest shape and count.
 int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) {
   std::vector<float> bestF, bestC;
   std::vector<int> pickF, pickC;
@@ -1338,7 +1359,28 @@ int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st
   if (rc) return rc;
   for (int f = 0; f < NFUSED; ++f)
     if (f % NTIERS != TEAM_TIER) p->fuse[f] = 0;
-  if ((rc = time_grids(p, D, J, K, st, bestC, pickC))) return rc;
+  // per-class layout: every launch shape at every count; each class keeps its fastest pair
+  std::vector<char> bestShape(NQCLASS, 0);
+  for (int sh = 0; sh < NSHAPE; ++sh) {
+    std::fill(p->shape.begin(), p->shape.end(), (char)sh);
+    std::vector<float> b;
+    std::vector<int> pk;
+    if ((rc = time_grids(p, D, J, K, st, b, pk))) return rc;
+    if (sh == 0) {
+      bestC = b;
+      pickC = pk;
+      continue;
+    }
+    for (int qc = 0; qc < NQCLASS; ++qc) {
+      const int slot = NFUSED + qc;
+      if (b[slot] < bestC[slot]) {
+        bestC[slot] = b[slot];
+        pickC[slot] = pk[slot];
+        bestShape[qc] = (char)sh;
+      }
+    }
+  }
+  p->shape = bestShape;
   auto t = [](const std::vector<float> &b, int slot) { return b[slot] < 1e29f ? (double)b[slot] : 0.0; };
   std::vector<int> pick = pickC;
   for (int cb = 0; cb < NPAIRCLASS; ++cb)
@@ -1364,6 +1406,7 @@ int tune_grids(jk_plan *p, const double *D, double *J, double *K, hipStream_t st
     if (f % NTIERS == TEAM_TIER) pick[f] = bestF[f] <= bestC[f] ? pickF[f] : pickC[f];
   p->grid = pick;
   save_tune_cache(p);
+  p->ev_count = 0;            // the timing builds are not profiled builds
   return resize_units(p);
 }
 

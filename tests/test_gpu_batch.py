@@ -117,10 +117,13 @@ def test_tuner_cache_roundtrip(tmp_path):
     words = open(path).read().split()
     say(f"[tune] cache: {' '.join(words)}")
     pairs = list(zip(words[0::2], words[1::2]))
-    grids = [int(v) for k, v in pairs if not k.startswith("fuse:")]
+    grids = [int(v) for k, v in pairs if not k.startswith(("fuse:", "shape:"))]
     fuses = [int(v) for k, v in pairs if k.startswith("fuse:")]
-    # a workgroup count for every launch, a layout (fused or per class) for every lane tier
+    shapes = [int(v) for k, v in pairs if k.startswith("shape:")]
+    # a workgroup count for every launch, a layout (fused or per class) for every lane tier, a
+    # launch shape for the per-class launches that do not keep the default
     assert grids and all(g > 0 for g in grids) and fuses and all(f in (0, 1) for f in fuses)
+    assert all(s in (1, 2) for s in shapes)
     t2 = jk.Plan.from_molecule(mol, tune=True, tune_cache=path)   # reads the cache, no timing runs
     J2, K2 = t2.execute(Dt)
     torch.cuda.synchronize()
@@ -128,6 +131,24 @@ def test_tuner_cache_roundtrip(tmp_path):
         assert float((J - Jr).abs().max()) <= 1e-12 and float((K - Kr).abs().max()) <= 1e-12
     for p in (ref, t, t2):
         p.close()
+
+
+def test_profile_after_tuning():
+    # the tuner's timing builds launch other shapes and counts; the profile then covers only the
+    # builds after it (one launch set), and its launch times add up to no more than the build
+    import torch
+    from paper_2407_09700_amd import jk
+    mol = synth.make_config(2, natom=12)
+    Dt = torch.from_numpy(mol.D).cuda()
+    p = jk.Plan.from_molecule(mol, tune=True, profile=True)
+    for _ in range(3):
+        p.execute(Dt)
+    torch.cuda.synchronize()
+    prof = p.profile()
+    p.close()
+    launches = [e for e in prof if e["kind"] == 0]
+    say(f"[profile after tuning] {len(launches)} launches")
+    assert launches and all(e["ms"] >= 0.0 for e in prof)
 
 
 def test_cfg5_full_batch_sampled():
