@@ -118,23 +118,27 @@ void solid_harmonics(int l, double *T) {
 
 // ------------------------------------------------------------------ algorithmic operation counts
 // Floating-point operations of the method for one class (an FMA counts 2), counted from its
-// steps as the kernels run them (no divergence, masking or recomputation):
+// steps as an efficient implementation runs them (no divergence, masking or recomputation, no
+// multiplication by a constant 1):
 //  per primitive quartet:  scalars p, q, P-Q, P-A, Q-C, rho, T, prefactor (24);
 //                          per root: interpolated u and w (2 x 11 FMAs = 44), the recurrence
 //                          coefficients and the three C00/C00' pairs (14), the 2D recurrence in
-//                          three directions, and the Rys product over the [e0|f0] elements
-//                          (one multiply and one FMA = 3 per element, the paper's count);
-//  per contracted quartet: the two binomial transfers and the digestion (six FMAs per
-//                          integral, Algorithm 2: two for J, four for K, so a J-only or
-//                          K-only build counts only its own).
-double vrr_ops(int E, int F) {
-  double n = E > 0 ? 1 : 0;                                  // G[1][0]
-  for (int e = 1; e < E; ++e) n += (e > 1 ? 1 : 0) + 1 + 2;  // e*b10, *G, fma
-  for (int e = 2; e <= E; ++e) n += 1;                       // e*b00 (hoisted)
-  for (int f = 0; f < F; ++f) {
-    if (f > 1) n += 1;                                       // f*b01 (hoisted)
+//                          three directions (the x and y tables start from 1, so their first
+//                          step in e and in f is free; the multiples e b10, e b00, f b01 are
+//                          shared by the directions), and the Rys product over the [e0|f0]
+//                          elements: one FMA each with the z integral, after one product of the
+//                          x and y integrals per distinct (x, y) index set (elements that differ
+//                          only in z share it);
+//  per contracted quartet: the two binomial transfers, with their coefficients (three products
+//                          each) formed once per quartet and a component k = b term of unit
+//                          coefficient taken as the start value, and the digestion (six FMAs per
+//                          integral, Algorithm 2: two for J, four for K, so a J-only or K-only
+//                          build counts only its own).
+double vrr_ops(int E, int F) {                               // one direction, table start g00
+  double n = E > 0 ? 1 : 0;                                  // G[1][0] = C00 g00
+  for (int e = 1; e < E; ++e) n += 1 + 2;                    // (e b10) G[e-1], fma
+  for (int f = 0; f < F; ++f)
     for (int e = 0; e <= E; ++e) n += 1 + (f > 0 ? 2 : 0) + (e > 0 ? 2 : 0);
-  }
   return n;
 }
 
@@ -152,13 +156,34 @@ int transfer_terms(int l) {
   return n;
 }
 
+// distinct (x, y) index sets of the products Gx[e][f] Gy[e][f] over the [e0|f0] elements
+int distinct_xy(int la, int E, int lc, int F) {
+  std::vector<char> seen((size_t)(E + 1) * (E + 1) * (F + 1) * (F + 1), 0);
+  int n = 0;
+  for (int le = la; le <= E; ++le)
+    for (int ex = le; ex >= 0; --ex)
+      for (int ey = le - ex; ey >= 0; --ey)
+        for (int lf = lc; lf <= F; ++lf)
+          for (int fx = lf; fx >= 0; --fx)
+            for (int fy = lf - fx; fy >= 0; --fy) {
+              char &s = seen[(((size_t)ex * (E + 1) + ey) * (F + 1) + fx) * (F + 1) + fy];
+              if (!s) {
+                s = 1;
+                ++n;
+              }
+            }
+  return n;
+}
+
 void class_ops(int la, int lb, int lc, int ld, int want, double *per_prim, double *per_quartet) {
   const int E = la + lb, F = lc + ld, N = (E + F) / 2 + 1;
   const int NE = range_count_h(la, E), NF = range_count_h(lc, F);
   const int na = ncart(la), nb = ncart(lb), nc = ncart(lc), nd = ncart(ld);
-  *per_prim = 24.0 + N * (44.0 + 14.0 + 3.0 * vrr_ops(E, F) + 3.0 * NE * NF);
-  const double bra = (double)na * transfer_terms(lb) * (3.0 + 2.0 * NF);
-  const double ket = (double)nc * transfer_terms(ld) * (3.0 + 2.0 * na * nb);
+  const double vrr = 3.0 * vrr_ops(E, F) - 2.0 * ((E > 0) + (F > 0)) + 2.0 * std::max(0, E - 1) + std::max(0, F - 1);
+  *per_prim = 24.0 + N * (44.0 + 14.0 + vrr + distinct_xy(la, E, lc, F) + 2.0 * NE * NF);
+  // transfer: per output, one FMA per term other than the unit one
+  const double bra = 2.0 * na * NF * (transfer_terms(lb) - ncart(lb)) + 3.0 * transfer_terms(lb);
+  const double ket = 2.0 * na * nb * nc * (transfer_terms(ld) - ncart(ld)) + 3.0 * transfer_terms(ld);
   const double digest = (want & 1 ? 4.0 : 0.0) + (want & 2 ? 8.0 : 0.0);   // two J and four K FMAs per integral
   *per_quartet = bra + ket + digest * na * nb * nc * nd;
 }

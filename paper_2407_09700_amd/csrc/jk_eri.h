@@ -52,6 +52,11 @@ namespace jk {
 
 // Ket blocks of at least this many components use the streamed digestion in the workgroup body.
 constexpr int TEAM_STREAM_MIN = 24;
+// LDS per workgroup up to which the two-stage body keeps its blocks X in LDS (two per CU)
+#ifndef JK_TEAM_XLDS_KB
+#define JK_TEAM_XLDS_KB 78
+#endif
+constexpr int TEAM_XLDS_MAX = JK_TEAM_XLDS_KB * 1024;
 
 // ================================================================== lane per quartet
 template <int LA, int LB, int LC, int LD>
@@ -323,9 +328,15 @@ struct TeamCfg {
   // streamed digestion (ket blocks of TEAM_STREAM_MIN or more components): partial K[b,c] and
   // K[b,d] per (b, cd) after the density blocks
   static constexpr int PBD = NC * ND >= TEAM_STREAM_MIN ? 2 * QB * NB * NC * ND : 0;
-  static constexpr int SGC = SG + CO > DSTG + PBD ? SG + CO : DSTG + PBD;
-  static constexpr int LDS_DOUBLES = SGC + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
+  static constexpr int SGC0 = SG + CO > DSTG + PBD ? SG + CO : DSTG + PBD;
   static constexpr int LDS_INTS = QB * 8 + 2;
+  // global buffer: the blocks X go to the LDS region of the 2D integrals and coefficients (free
+  // after the primitive loop; grown to hold them where the workgroup still fits twice per CU),
+  // so only Y and Z pass through the buffer
+  static constexpr int SGCX = SGC0 > QB * XS ? SGC0 : QB * XS;
+  static constexpr bool X_LDS = GLOBAL_BUF && (SGCX + QB * DG + QB * 12) * 8 + LDS_INTS * 4 <= TEAM_XLDS_MAX;
+  static constexpr int SGC = X_LDS ? SGCX : SGC0;
+  static constexpr int LDS_DOUBLES = SGC + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
 
@@ -379,7 +390,9 @@ __device__ __forceinline__ void team_product_dispatch(int part, const double *ba
 // Computes (ab|cd) of the QB quartets described in qi/geo; on return Z[q*ZS + ab*NC*ND + cd]
 // (Z = buf) holds the contracted Cartesian blocks. Every thread of the block must call it;
 // it synchronises the block. sG: SG doubles of LDS; buf: BUF doubles (LDS or global).
-template <int LA, int LB, int LC, int LD>
+// XL (TeamCfg::X_LDS, with sG the start of an LDS region of SGC doubles): the [e0|f0] blocks X
+// go to that region, free after the primitive loop, instead of the global buffer.
+template <int LA, int LB, int LC, int LD, bool XL = false>
 __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ pp, double *sG, double *co,
                                                   double *buf, const int *qi, const double *geo, int *smax) {
   using C = TeamCfg<LA, LB, LC, LD>;
@@ -387,7 +400,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GT = C::GT, BLOCK = C::BLOCK;
   constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
-  double *X = buf;                    // [QB][NE][NF]  (later Z: [QB][NA*NB][NC*ND])
+  double *X = XL ? sG : buf;          // [QB][NE][NF]  (later Z: [QB][NA*NB][NC*ND], in buf)
   double *Y = buf + QB * C::R1;       // [QB][NA*NB][NF]
   const int tid = threadIdx.x;
 
@@ -538,7 +551,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   // then the ND outputs (c, d); TU tasks per lane at once as above.
   constexpr int NKD = range_count(0, LD);
   constexpr int TUK = 3 * NKD <= 24 ? 3 : (2 * NKD <= 24 ? 2 : 1);
-  double *Z = X;
+  double *Z = buf;
   for (int t0 = tid; t0 < QB * NA * NB * NC; t0 += TUK * BLOCK) {
     double yv[TUK][NKD];
 #pragma unroll
@@ -582,7 +595,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
                             pw[1][dy - ky] * pw[2][dz - kz];
           v = fma(cf, yv[u][k], v);
         }
-        Z[(q * NA * NB + ab) * NC * ND + c * ND + dd] = v;   // region 1 is free: X was consumed by the pass above
+        Z[(q * NA * NB + ab) * NC * ND + c * ND + dd] = v;   // buf region 1: X was consumed above (or is in LDS)
       }
     }
   }
