@@ -52,7 +52,8 @@ namespace jk {
 
 // Ket blocks of at least this many components use the streamed digestion in the workgroup body.
 constexpr int TEAM_STREAM_MIN = 24;
-// LDS per workgroup up to which the two-stage body keeps its blocks X in LDS (two per CU)
+// LDS per workgroup of the two-stage body that still fits twice per CU: the chunk of primitive
+// quartets shrinks to stay under it, and the blocks X are kept in LDS under it
 #ifndef JK_TEAM_XLDS_KB
 #define JK_TEAM_XLDS_KB 78
 #endif
@@ -310,17 +311,14 @@ struct TeamCfg {
   static constexpr int QB = QB2 < 1 ? 1 : QB2;
   static constexpr int PC0 = (40 * 1024) / (QB * N * GS * 8);
   static constexpr int PC1 = BLOCK / (QB * N * 3);
-  static constexpr int PC = (PC0 < PC1 ? PC0 : PC1) < 1 ? 1 : (PC0 < PC1 ? PC0 : PC1);
+  static constexpr int PC_MAX = (PC0 < PC1 ? PC0 : PC1) < 1 ? 1 : (PC0 < PC1 ? PC0 : PC1);
   static constexpr int XS = NE * NF, YS = NA * NB * NF, ZS = NA * NB * NC * ND;
   static constexpr int R1 = XS > ZS ? XS : ZS;
   static constexpr int BUF = QB * (R1 + YS);
   static constexpr bool GLOBAL_BUF = BUF * 8 > 48 * 1024;
-  static constexpr int SG = QB * PC * N * GS;
   // LDS carved by team_eri: 2D integrals, (buffer), geometry; descriptors are ints
   // per-quartet digestion accumulators: K[a,c], K[a,d], K[b,c], K[b,d] and J[c,d]
   static constexpr int DG = NA * NC + NA * ND + NB * NC + NB * ND + NC * ND;
-  static constexpr int PW = coef_window(QB, PC, N, 16 * 1024);     // coefficient window (primitive quartets)
-  static constexpr int CO = QB * PW * N * CO_STRIDE;
   // density blocks of the digestion: D[a,b], then per quartet D[c,d], D[a,c], D[a,d], D[b,c],
   // D[b,d] and the symmetry factor; they reuse the region of the 2D integrals and coefficients
   static constexpr int DQ = NC * ND + (NA + NB) * (NC + ND);
@@ -328,8 +326,27 @@ struct TeamCfg {
   // streamed digestion (ket blocks of TEAM_STREAM_MIN or more components): partial K[b,c] and
   // K[b,d] per (b, cd) after the density blocks
   static constexpr int PBD = NC * ND >= TEAM_STREAM_MIN ? 2 * QB * NB * NC * ND : 0;
-  static constexpr int SGC0 = SG + CO > DSTG + PBD ? SG + CO : DSTG + PBD;
   static constexpr int LDS_INTS = QB * 8 + 2;
+  // primitive quartets per chunk: PC_MAX, or the largest of its halvings with which the
+  // workgroup fits twice per CU (fewer quartets per synchronised chunk, more waves in flight)
+  static constexpr int sgc_for(int pc) {
+    const int sg = QB * pc * N * GS + QB * coef_window(QB, pc, N, 16 * 1024) * N * CO_STRIDE;
+    return sg > DSTG + PBD ? sg : DSTG + PBD;
+  }
+  static constexpr int lds_for(int pc) {
+    return (sgc_for(pc) + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12) * 8 + LDS_INTS * 4;
+  }
+  static constexpr int pick_pc() {
+    if (lds_for(PC_MAX) <= TEAM_XLDS_MAX) return PC_MAX;
+    for (int pc = PC_MAX / 2; pc >= 1; pc /= 2)
+      if (lds_for(pc) <= TEAM_XLDS_MAX) return pc;
+    return PC_MAX;
+  }
+  static constexpr int PC = pick_pc();
+  static constexpr int SG = QB * PC * N * GS;
+  static constexpr int PW = coef_window(QB, PC, N, 16 * 1024);     // coefficient window (primitive quartets)
+  static constexpr int CO = QB * PW * N * CO_STRIDE;
+  static constexpr int SGC0 = SG + CO > DSTG + PBD ? SG + CO : DSTG + PBD;
   // global buffer: the blocks X go to the LDS region of the 2D integrals and coefficients (free
   // after the primitive loop; grown to hold them where the workgroup still fits twice per CU),
   // so only Y and Z pass through the buffer
