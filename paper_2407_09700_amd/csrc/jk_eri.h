@@ -58,6 +58,9 @@ constexpr int TEAM_STREAM_MIN = 24;
 #define JK_TEAM_XLDS_KB 78
 #endif
 constexpr int TEAM_XLDS_MAX = JK_TEAM_XLDS_KB * 1024;
+#ifndef JK_TEAM_ZLDS
+#define JK_TEAM_ZLDS 1
+#endif
 
 // ================================================================== lane per quartet
 template <int LA, int LB, int LC, int LD>
@@ -353,6 +356,14 @@ struct TeamCfg {
   static constexpr int SGCX = SGC0 > QB * XS ? SGC0 : QB * XS;
   static constexpr bool X_LDS = GLOBAL_BUF && (SGCX + QB * DG + QB * 12) * 8 + LDS_INTS * 4 <= TEAM_XLDS_MAX;
   static constexpr int SGC = X_LDS ? SGCX : SGC0;
+  // Z in LDS (global buffer, streamed digestion): during the digestion the region [DSTG + PBD,
+  // SGC) is free; the ket transfer fills it with the rows (a, all b) of NAZ bra components a at a
+  // time, which the streamed digestion then reads, so Z never passes through the global buffer
+  static constexpr int NAZ0 = (SGC - DSTG - PBD) / (NB * NC * ND);
+  static constexpr int NAZ = NAZ0 > NA ? NA : NAZ0;
+  static constexpr int NWAVE = BLOCK / 64;
+  static constexpr bool Z_LDS = JK_TEAM_ZLDS && GLOBAL_BUF && NC * ND >= TEAM_STREAM_MIN &&
+                                NAZ >= (NA < NWAVE ? NA : NWAVE);   // every wave has a row block
   static constexpr int LDS_DOUBLES = SGC + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
@@ -409,7 +420,9 @@ __device__ __forceinline__ void team_product_dispatch(int part, const double *ba
 // it synchronises the block. sG: SG doubles of LDS; buf: BUF doubles (LDS or global).
 // XL (TeamCfg::X_LDS, with sG the start of an LDS region of SGC doubles): the [e0|f0] blocks X
 // go to that region, free after the primitive loop, instead of the global buffer.
-template <int LA, int LB, int LC, int LD, bool XL = false>
+// NOZ: return Y[(q*NA*NB + ab)*NF + f] after the bra transfer (the caller's team_ket_rows
+// then forms Z block by block in LDS).
+template <int LA, int LB, int LC, int LD, bool XL = false, bool NOZ = false>
 __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ pp, double *sG, double *co,
                                                   double *buf, const int *qi, const double *geo, int *smax) {
   using C = TeamCfg<LA, LB, LC, LD>;
@@ -564,6 +577,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
     }
   }
   __syncthreads();
+  if constexpr (NOZ) return Y;
   // Ket transfer, one task per (quartet, ab, c): Y[ab][c + k] for |k| <= ld loaded together,
   // then the ND outputs (c, d); TU tasks per lane at once as above.
   constexpr int NKD = range_count(0, LD);
@@ -618,6 +632,62 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   }
   __syncthreads();
   return Z;
+}
+
+// Ket transfer of the rows (a, b), a in [a0, a0 + na), every b, of quartet q: from Y (as
+// team_eri<..., true> returns it) into zb[((a - a0) * NB + b) * NC * ND + c * ND + d]. Every
+// thread of the block calls it; the caller synchronises before reading zb.
+template <int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void team_ket_rows(const double *Y, const double *geo, int q, int a0, int na, double *zb) {
+  using C = TeamCfg<LA, LB, LC, LD>;
+  constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND, NF = C::NF;
+  constexpr int F0 = CT.start[LC];
+  constexpr int NKD = range_count(0, LD);
+  constexpr int TUK = 3 * NKD <= 24 ? 3 : (2 * NKD <= 24 ? 2 : 1);
+  const int ntask = na * NB * NC;
+  const double CD[3] = {geo[q * 12 + 6] - geo[q * 12 + 9], geo[q * 12 + 7] - geo[q * 12 + 10],
+                        geo[q * 12 + 8] - geo[q * 12 + 11]};
+  double pw[3][LD + 1];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    pw[d][0] = 1.0;
+#pragma unroll
+    for (int i = 1; i <= LD; ++i) pw[d][i] = pw[d][i - 1] * CD[d];
+  }
+  const double *Yq = Y + ((size_t)q * NA + a0) * NB * NF;
+  for (int t0 = threadIdx.x; t0 < ntask; t0 += TUK * blockDim.x) {
+    double yv[TUK][NKD];
+#pragma unroll
+    for (int u = 0; u < TUK; ++u) {
+      const int t = t0 + u * blockDim.x;
+      if (t >= ntask) break;
+      const int r = t / NC, c = t % NC;                 // r = (a - a0) * NB + b
+      const int cx = CTD.x[F0 + c], cy = CTD.y[F0 + c], cz = CTD.z[F0 + c];
+#pragma unroll
+      for (int k = 0; k < NKD; ++k) yv[u][k] = Yq[(size_t)r * NF + cart_flat(cx + CT.x[k], cy + CT.y[k], cz + CT.z[k]) - F0];
+    }
+#pragma unroll
+    for (int u = 0; u < TUK; ++u) {
+      const int t = t0 + u * blockDim.x;
+      if (t >= ntask) break;
+      const int r = t / NC, c = t % NC;
+#pragma unroll
+      for (int dd = 0; dd < ND; ++dd) {
+        constexpr int D0 = CT.start[LD];
+        const int dx = CT.x[D0 + dd], dy = CT.y[D0 + dd], dz = CT.z[D0 + dd];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NKD; ++k) {
+          const int kx = CT.x[k], ky = CT.y[k], kz = CT.z[k];
+          if (kx > dx || ky > dy || kz > dz) continue;
+          const double cf = (double)(binom(dx, kx) * binom(dy, ky) * binom(dz, kz)) * pw[0][dx - kx] *
+                            pw[1][dy - ky] * pw[2][dz - kz];
+          v = fma(cf, yv[u][k], v);
+        }
+        zb[(size_t)r * NC * ND + c * ND + dd] = v;
+      }
+    }
+  }
 }
 
 }  // namespace jk

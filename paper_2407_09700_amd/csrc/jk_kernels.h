@@ -334,7 +334,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       team_fill<LA, LB, LC, LD>(tid, bra, A.pairs[ki], bi, ki, valid, qi, geo);
     }
     __syncthreads();
-    const double *Z = team_eri<LA, LB, LC, LD, C::X_LDS>(A.pp, sG, co, buf, qi, geo, smax);
+    const double *Z = team_eri<LA, LB, LC, LD, C::X_LDS, C::Z_LDS>(A.pp, sG, co, buf, qi, geo, smax);   // Z_LDS: Y
     stage_density<NA, NB, NC, ND, QB>(A, bra, bi, Dm, nc, qi, ds);
     for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
     double *pbc = ds + C::DSTG, *pbd = pbc + QB * NB * NCD;   // streamed digestion only
@@ -414,14 +414,15 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     // loaded together: all NB rows of an a when they fit), its lanes run over (c, d). J[a,b] is
     // wave-reduced eight rows at a time; J[c,d], K[a,c] and K[a,d] collect in registers; K[b,c]
     // and K[b,d] in LDS per (b, cd), summed over d or c afterwards (no two lanes of a wave add
-    // to the same address). The per-quartet sums are flushed below.
+    // to the same address). The per-quartet sums are flushed below. Z_LDS: per quartet, the
+    // ket transfer first writes the rows of NAZ components a into LDS, which the waves then read.
     const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const bool wj = A.want & 1, wk = A.want & 2;
     constexpr int RB = NB * CH <= 32 ? NB : 4;
+    double *zb = ds + C::DSTG + C::PBD;    // Z_LDS: block of ket-transferred rows (free LDS)
     for (int q = 0; q < QB; ++q) {
       if (!qi[q * 8 + 6]) continue;
       const double s2 = 2.0 * sq[q];
-      const double *g = Z + (size_t)q * NG;
       const double *Dcd = ds + NAB + q * DQ, *Dac = Dcd + NCD, *Dad = Dac + NA * NC, *Dbc = Dad + NA * ND,
                    *Dbd = Dbc + NB * NC;
       double *kac = dg + q * C::DG, *kad = kac + NA * NC;
@@ -439,7 +440,17 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
         dcd[h] = on[h] ? Dcd[cd] : 0.0;
         jcda[h] = 0.0;
       }
-      for (int a = wave; a < NA; a += nwave) {
+      for (int a0 = 0; a0 < NA; a0 += (C::Z_LDS ? C::NAZ : NA)) {
+      const int a1 = C::Z_LDS ? min(a0 + C::NAZ, NA) : NA;
+      const double *g;
+      if constexpr (C::Z_LDS) {
+        team_ket_rows<LA, LB, LC, LD>(Z, geo, q, a0, a1 - a0, zb);
+        __syncthreads();
+        g = zb - (size_t)a0 * NB * NCD;
+      } else {
+        g = Z + (size_t)q * NG;
+      }
+      for (int a = a0 + wave; a < a1; a += nwave) {
         double dad[CH], dac[CH], kacs[CH], kads[CH];
 #pragma unroll
         for (int h = 0; h < CH; ++h) {
@@ -499,6 +510,8 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
             atomicAdd(&kac[a * NC + cc[h]], kacs[h]);
             atomicAdd(&kad[a * ND + dd[h]], kads[h]);
           }
+      }
+      if constexpr (C::Z_LDS) __syncthreads();   // the block is read before the next one is written
       }
 #pragma unroll
       for (int h = 0; h < CH; ++h)
