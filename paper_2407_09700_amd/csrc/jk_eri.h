@@ -355,15 +355,21 @@ struct TeamCfg {
   // so only Y and Z pass through the buffer
   static constexpr int SGCX = SGC0 > QB * XS ? SGC0 : QB * XS;
   static constexpr bool X_LDS = GLOBAL_BUF && (SGCX + QB * DG + QB * 12) * 8 + LDS_INTS * 4 <= TEAM_XLDS_MAX;
-  static constexpr int SGC = X_LDS ? SGCX : SGC0;
+  static constexpr int SGC1 = X_LDS ? SGCX : SGC0;
   // Z in LDS (global buffer, streamed digestion): during the digestion the region [DSTG + PBD,
   // SGC) is free; the ket transfer fills it with the rows (a, all b) of NAZ bra components a at a
-  // time, which the streamed digestion then reads, so Z never passes through the global buffer
+  // time, which the streamed digestion then reads, so Z never passes through the global buffer.
+  // NAZ is at least one component per wave; the region grows for it while the workgroup still
+  // fits twice per CU.
+  static constexpr int NWAVE = BLOCK / 64;
+  static constexpr int NAZW = NA < NWAVE ? NA : NWAVE;
+  static constexpr int ZNEED = DSTG + PBD + NAZW * NB * NC * ND;
+  static constexpr int SGCZ = SGC1 > ZNEED ? SGC1 : ZNEED;
+  static constexpr bool Z_LDS = JK_TEAM_ZLDS && GLOBAL_BUF && NC * ND >= TEAM_STREAM_MIN &&
+                                (SGCZ + QB * DG + QB * 12) * 8 + LDS_INTS * 4 <= TEAM_XLDS_MAX;
+  static constexpr int SGC = Z_LDS ? SGCZ : SGC1;
   static constexpr int NAZ0 = (SGC - DSTG - PBD) / (NB * NC * ND);
   static constexpr int NAZ = NAZ0 > NA ? NA : NAZ0;
-  static constexpr int NWAVE = BLOCK / 64;
-  static constexpr bool Z_LDS = JK_TEAM_ZLDS && GLOBAL_BUF && NC * ND >= TEAM_STREAM_MIN &&
-                                NAZ >= (NA < NWAVE ? NA : NWAVE);   // every wave has a row block
   static constexpr int LDS_DOUBLES = SGC + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
   static constexpr int LDS_BYTES = LDS_DOUBLES * 8 + LDS_INTS * 4;
 };
