@@ -353,7 +353,8 @@ struct TeamCfg {
   // global buffer: the blocks X go to the LDS region of the 2D integrals and coefficients (free
   // after the primitive loop; grown to hold them where the workgroup still fits twice per CU),
   // so only Y and Z pass through the buffer
-  static constexpr int SGCX = SGC0 > QB * XS ? SGC0 : QB * XS;
+  static constexpr int XSL = NE * (NF | 1);              // X in LDS: rows at an odd stride
+  static constexpr int SGCX = SGC0 > QB * XSL ? SGC0 : QB * XSL;
   static constexpr bool X_LDS = GLOBAL_BUF && (SGCX + QB * DG + QB * 12) * 8 + LDS_INTS * 4 <= TEAM_XLDS_MAX;
   static constexpr int SGC1 = X_LDS ? SGCX : SGC0;
   // Z in LDS (global buffer, streamed digestion): during the digestion the region [DSTG + PBD,
@@ -436,7 +437,10 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
   constexpr int QB = C::QB, PC = C::PC, GS = C::GS, GT = C::GT, BLOCK = C::BLOCK;
   constexpr int E0 = CT.start[LA], F0 = CT.start[LC];
-  double *X = XL ? sG : buf;          // [QB][NE][NF]  (later Z: [QB][NA*NB][NC*ND], in buf)
+  double *X = XL ? sG : buf;          // [QB][NE][XR]  (later Z: [QB][NA*NB][NC*ND], in buf)
+  // row stride of X: odd in LDS, so that the lanes of the e-major product (one row each) store
+  // to different banks (an even NF puts half the wave on one bank)
+  constexpr int XR = XL ? (NF | 1) : NF;
   double *Y = buf + QB * C::R1;       // [QB][NA*NB][NF]
   const int tid = threadIdx.x;
 
@@ -519,12 +523,12 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   if (prole) {
     if constexpr (C::EMAJOR) {
 #pragma unroll
-      for (int j = 0; j < NF; ++j) X[(pq_ * NE + pf) * NF + j] = acc[j];
+      for (int j = 0; j < NF; ++j) X[(pq_ * NE + pf) * XR + j] = acc[j];
     } else {
 #pragma unroll
       for (int i = 0; i < C::EPS; ++i) {
         const int e = part * C::EPS + i;
-        if (e < NE) X[(pq_ * NE + e) * NF + pf] = acc[i];
+        if (e < NE) X[(pq_ * NE + e) * XR + pf] = acc[i];
       }
     }
   }
@@ -547,7 +551,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
       const int ax = CTD.x[E0 + a], ay = CTD.y[E0 + a], az = CTD.z[E0 + a];
 #pragma unroll
       for (int k = 0; k < NKB; ++k)
-        xv[u][k] = X[(q * NE + cart_flat(ax + CT.x[k], ay + CT.y[k], az + CT.z[k]) - E0) * NF + f];
+        xv[u][k] = X[(q * NE + cart_flat(ax + CT.x[k], ay + CT.y[k], az + CT.z[k]) - E0) * XR + f];
     }
 #pragma unroll
     for (int u = 0; u < TUB; ++u) {
