@@ -368,7 +368,15 @@ struct TeamCfg {
   static constexpr int SGCZ = SGC1 > ZNEED ? SGC1 : ZNEED;
   static constexpr bool Z_LDS = JK_TEAM_ZLDS && GLOBAL_BUF && NC * ND >= TEAM_STREAM_MIN &&
                                 (SGCZ + QB * DG + QB * 12) * 8 + LDS_INTS * 4 <= TEAM_XLDS_MAX;
-  static constexpr int SGC = Z_LDS ? SGCZ : SGC1;
+  // small ket blocks (per-output digestion loops, each reading every integral): Z in LDS after
+  // the staged densities, where the region (grown if need be) keeps as many workgroups per CU
+  static constexpr int ZSNEED = DSTG + QB * ZS;
+  static constexpr int SGCS = SGC1 > ZSNEED ? SGC1 : ZSNEED;
+  static constexpr int lds_with(int sgc) { return (sgc + QB * DG + QB * 12) * 8 + LDS_INTS * 4; }
+  static constexpr bool ZS_LDS = JK_TEAM_ZLDS && GLOBAL_BUF && NC * ND < TEAM_STREAM_MIN &&
+                                 lds_with(SGCS) <= TEAM_XLDS_MAX &&   // and no fewer workgroups per CU
+                                 (160 * 1024) / lds_with(SGCS) >= (160 * 1024) / lds_with(SGC1);
+  static constexpr int SGC = Z_LDS ? SGCZ : (ZS_LDS ? SGCS : SGC1);
   static constexpr int NAZ0 = (SGC - DSTG - PBD) / (NB * NC * ND);
   static constexpr int NAZ = NAZ0 > NA ? NA : NAZ0;
   static constexpr int LDS_DOUBLES = SGC + (GLOBAL_BUF ? 0 : BUF) + QB * DG + QB * 12;
@@ -429,9 +437,11 @@ __device__ __forceinline__ void team_product_dispatch(int part, const double *ba
 // go to that region, free after the primitive loop, instead of the global buffer.
 // NOZ: return Y[(q*NA*NB + ab)*NF + f] after the bra transfer (the caller's team_ket_rows
 // then forms Z block by block in LDS).
+// zl: where the ket transfer writes Z (null: buf).
 template <int LA, int LB, int LC, int LD, bool XL = false, bool NOZ = false>
 __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ pp, double *sG, double *co,
-                                                  double *buf, const int *qi, const double *geo, int *smax) {
+                                                  double *buf, const int *qi, const double *geo, int *smax,
+                                                  double *zl = nullptr) {
   using C = TeamCfg<LA, LB, LC, LD>;
   constexpr int E = C::E, F = C::F, N = C::N, NE = C::NE, NF = C::NF;
   constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
@@ -592,7 +602,7 @@ __device__ __forceinline__ const double *team_eri(const PrimPair *__restrict__ p
   // then the ND outputs (c, d); TU tasks per lane at once as above.
   constexpr int NKD = range_count(0, LD);
   constexpr int TUK = 3 * NKD <= 24 ? 3 : (2 * NKD <= 24 ? 2 : 1);
-  double *Z = buf;
+  double *Z = zl ? zl : buf;
   for (int t0 = tid; t0 < QB * NA * NB * NC; t0 += TUK * BLOCK) {
     double yv[TUK][NKD];
 #pragma unroll

@@ -334,7 +334,9 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       team_fill<LA, LB, LC, LD>(tid, bra, A.pairs[ki], bi, ki, valid, qi, geo);
     }
     __syncthreads();
-    const double *Z = team_eri<LA, LB, LC, LD, C::X_LDS, C::Z_LDS>(A.pp, sG, co, buf, qi, geo, smax);   // Z_LDS: Y
+    // Z_LDS: Y (the digestion forms Z block by block); ZS_LDS: Z in LDS after the staged densities
+    const double *Z = team_eri<LA, LB, LC, LD, C::X_LDS, C::Z_LDS>(A.pp, sG, co, buf, qi, geo, smax,
+                                                                  C::ZS_LDS ? ds + C::DSTG : nullptr);
     stage_density<NA, NB, NC, ND, QB>(A, bra, bi, Dm, nc, qi, ds);
     for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
     double *pbc = ds + C::DSTG, *pbd = pbc + QB * NB * NCD;   // streamed digestion only
