@@ -55,8 +55,10 @@ extern "C" {
 #define JK_FLAG_PROFILE 1     /* jk_opts_t.flags: time every kernel launch of an execute */
 #define JK_FLAG_GRAPH 2       /* jk_opts_t.flags: record the build in a HIP graph on the first
                                  execute and replay it afterwards (no host round trip inside) */
-#define JK_FLAG_TUNE 4        /* jk_opts_t.flags: pick the workgroup count of every integral
-                                 launch by timing candidates on the first execute */
+#define JK_FLAG_TUNE 4        /* jk_opts_t.flags: on the first execute, time candidate builds
+                                 and keep, per register tier, fused or per-class launches, per
+                                 class the launch shape (root table and exchange rows in LDS or
+                                 not), and per launch the workgroup count */
 #define JK_FLAG_J_ONLY 8      /* jk_opts_t.flags: build J only (K is not written and may be NULL);
                                  the density-weighted screen takes the two Coulomb blocks D[a,b],
                                  D[c,d] only */
