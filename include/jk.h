@@ -143,7 +143,7 @@ int jk_plan_check(jk_plan_t *plan);
  * by translational invariance). D: DEVICE nao x nao, symmetric. grad: DEVICE natom x 3
  * doubles (atoms as given to jk_plan_create), OVERWRITTEN. The quartets are those the J/K
  * screen keeps for D (six density blocks). Single-molecule plans made for J and K, shells up
- * to l = 2 (else JK_EUNSUPPORTED / JK_EINVAL). Asynchronous as jk_plan_execute; jk_plan_check
+ * to l = 3 (else JK_EUNSUPPORTED / JK_EINVAL). Asynchronous as jk_plan_execute; jk_plan_check
  * reports an overflow of the work lists the same way. */
 int jk_grad(jk_plan_t *plan, const double *D, double *grad, void *stream);
 

@@ -17,7 +17,7 @@ LIB = os.environ.get("JK_LIB_OUT", os.path.join(HERE, "libjk.so"))
 BUILD = os.environ.get("JK_BUILD_DIR", BUILD)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["jk_api.cpp", "jk_onee.cpp", "jk_aux.hip", "grad_classes.hip"] + [f"classes_{c}.hip" for c in
+SOURCES = ["jk_api.cpp", "jk_onee.cpp", "jk_aux.hip", "grad_classes.hip", "grad_classes_f.hip"] + [f"classes_{c}.hip" for c in
                                          ("44", "43", "42", "33", "41", "32", "40", "31", "22", "30", "21", "20",
                                           "11", "10", "00")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
@@ -54,7 +54,7 @@ def build(jobs: int | None = None, verbose: bool = True, force: bool = True) -> 
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or int(os.environ.get("MAX_JOBS", "0")) or min(8, os.cpu_count() or 1)
     t0 = time.time()
-    order = SOURCES[4:] + SOURCES[:4]          # biggest class units first
+    order = SOURCES[5:] + SOURCES[4:5] + SOURCES[:4]   # biggest class units first
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = dict(zip(order, ex.map(lambda s: _compile(s, force), order)))
     tmp = LIB + ".tmp%d" % os.getpid()

@@ -1,4 +1,5 @@
-// Gradient kernels of every quartet class with momenta up to d.
+// Gradient kernels of the quartet classes whose bra pair has momenta up to d (the classes with
+// an f in the bra: grad_classes_f.hip).
 #include "jk_grad.h"
 
 namespace jk {
@@ -14,7 +15,7 @@ constexpr int gpc_lb(int c) { return c - gpc_la(c) * (gpc_la(c) + 1) / 2; }
 
 template <int CB, int CK>
 void register_grad_pairs(grad_launch_fn *table) {
-  if constexpr (CB <= pair_class(GRAD_LMAX, GRAD_LMAX)) {
+  if constexpr (CB <= pair_class(2, 2)) {
     if constexpr (CK <= CB) {
       table[qclass_index(CB, CK)] = launch_grad<gpc_la(CB), gpc_lb(CB), gpc_la(CK), gpc_lb(CK)>;
       register_grad_pairs<CB, CK + 1>(table);
@@ -27,6 +28,7 @@ void register_grad_pairs(grad_launch_fn *table) {
 void register_grad(grad_launch_fn *table) {
   for (int q = 0; q < NQCLASS; ++q) table[q] = nullptr;
   register_grad_pairs<0, 0>(table);
+  register_grad_f(table);
 }
 
 }  // namespace jk

@@ -352,7 +352,8 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs A) {
 }  // namespace jk
 
 namespace jk {
-constexpr int GRAD_LMAX = 2;   // gradient kernels exist for shells up to d
+constexpr int GRAD_LMAX = 3;   // gradient kernels exist for shells up to f
 typedef hipError_t (*grad_launch_fn)(const GradArgs &args, int grid, hipStream_t stream);
 void register_grad(grad_launch_fn *table);   // [NQCLASS]; null where a class has l > GRAD_LMAX
+void register_grad_f(grad_launch_fn *table);  // the classes whose bra has an f shell (own unit)
 }  // namespace jk

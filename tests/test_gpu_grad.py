@@ -53,7 +53,16 @@ def test_grad_translation_invariance_cfg2():
     assert np.abs(g.sum(axis=0)).max() <= 1e-9 * max(1.0, np.abs(g).max())
 
 
-def test_grad_rejects_f_shells():
+@pytest.mark.parametrize("pure", [0, 1])
+def test_grad_every_class_up_to_f(pure):
+    # one contracted shell of each l <= 3 on three atoms: all 55 classes up to (ff|ff)
+    coords = [[0.0, 0.0, 0.0], [1.6, 0.3, -0.5], [-0.7, 1.4, 0.8]]
+    mol = synth.custom(coords, [(0, 3), (1, 2), (2, 2), (3, 1)], 0.25, 6.0, pure_from_l=2 if pure else 99, nocc=8,
+                       seed=70 + pure)
+    _check(mol, 0.0, f"all classes up to f pure={pure}")
+
+
+def test_grad_rejects_g_shells():
     from paper_2407_09700_amd import jk
     import torch
     mol = synth.make_config(3, natom=2)
