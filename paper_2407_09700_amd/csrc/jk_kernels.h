@@ -444,11 +444,13 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
       }
       for (int a0 = 0; a0 < NA; a0 += (C::Z_LDS ? C::NAZ : NA)) {
       const int a1 = C::Z_LDS ? min(a0 + C::NAZ, NA) : NA;
-      const double *g;
+      const double *g;         // rows (a, b) of this block: g[((a - ga0) * NB + b) * NCD + cd]
+      int ga0 = 0;
       if constexpr (C::Z_LDS) {
         team_ket_rows<LA, LB, LC, LD>(Z, geo, q, a0, a1 - a0, zb);
         __syncthreads();
-        g = zb - (size_t)a0 * NB * NCD;
+        g = zb;
+        ga0 = a0;
       } else {
         g = Z + (size_t)q * NG;
       }
@@ -472,7 +474,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
           for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int h = 0; h < CH; ++h)
-              xs[i][h] = (b0 + i < NB && on[h]) ? g[(size_t)(a * NB + b0 + i) * NCD + h * 64 + lane] : 0.0;
+              xs[i][h] = (b0 + i < NB && on[h]) ? g[(size_t)((a - ga0) * NB + b0 + i) * NCD + h * 64 + lane] : 0.0;
 #pragma unroll
           for (int i = 0; i < RB; ++i) {
             const int b = b0 + i;
