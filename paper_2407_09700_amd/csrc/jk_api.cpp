@@ -275,6 +275,7 @@ struct jk_plan {
   int natom = 0, lmax = 0;
   long long *d_mc_off = nullptr, *d_mf_off = nullptr, *d_ps_off = nullptr, *d_mf_user = nullptr;
   double *d_tsph = nullptr;
+  double *d_Dp = nullptr;   // Cartesian densities in shell panels (launch_dcart)
   double *d_Dc = nullptr, *d_Jc = nullptr, *d_Kc = nullptr, *d_Pblk = nullptr, *d_gmax = nullptr;
   unsigned long long *d_cap = nullptr, *d_nprim = nullptr;
   int *d_count = nullptr, *d_pair_npp = nullptr;
@@ -348,7 +349,7 @@ void plan_free(jk_plan *p) {
   dfree(p->d_pair_sb); dfree(p->d_cls_beg); dfree(p->d_pair_mol); dfree(p->d_bin_beg); dfree(p->d_cm_bin); dfree(p->d_l);
   dfree(p->d_pure); dfree(p->d_cart_off); dfree(p->d_ao_off); dfree(p->d_cart2shell); dfree(p->d_ao2shell);
   dfree(p->d_sbase); dfree(p->d_cbase); dfree(p->d_abase); dfree(p->d_mnc); dfree(p->d_mc_off);
-  dfree(p->d_mf_off); dfree(p->d_ps_off); dfree(p->d_mf_user); dfree(p->d_tsph); dfree(p->d_Dc);
+  dfree(p->d_mf_off); dfree(p->d_ps_off); dfree(p->d_mf_user); dfree(p->d_tsph); dfree(p->d_Dc); dfree(p->d_Dp);
   dfree(p->d_Jc); dfree(p->d_Kc); dfree(p->d_Pblk); dfree(p->d_gmax); dfree(p->d_cap); dfree(p->d_count);
   dfree(p->d_kets); dfree(p->d_scratch); dfree(p->d_nprim); dfree(p->d_pair_npp);
   dfree(p->d_pair_ca); dfree(p->d_pair_cb); dfree(p->d_pair_la); dfree(p->d_pair_lb); dfree(p->d_segoff);
@@ -843,7 +844,7 @@ int plan_create(int nmol, const jk_basis_t *const *Bs_in, const double *const *c
 
   // build workspace
   const size_t nc2 = (size_t)p->mc_off[nmol];
-  if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
+  if ((rc = dalloc(&p->d_Dc, nc2)) || (rc = dalloc(&p->d_Dp, nc2)) || (rc = dalloc(&p->d_Jc, nc2)) || (rc = dalloc(&p->d_Kc, nc2)) ||
       (rc = dalloc(&p->d_Pblk, (size_t)p->ps_off[nmol])) || (rc = dalloc(&p->d_gmax, 1)) ||
       (rc = dalloc(&p->d_cap, NQCLASS)) || (rc = dalloc(&p->d_count, NQCLASS)) ||
       (rc = dalloc(&p->d_nprim, 2 * NQCLASS)) || (rc = dalloc(&p->d_class_off, NQCLASS)) ||
@@ -1137,7 +1138,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
   HIPCHK(launch_fill_i32(p->d_nunits, NSLOT, 0, st));
   HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
-  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+  HIPCHK(launch_dcart(p->S, D, p->d_Dc, p->d_Dp, st));
   HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
   FoldArgs F{};
   F.pair_cls = p->d_pair_cls;
@@ -1176,7 +1177,7 @@ int enqueue_build(jk_plan *p, const double *D, double *J, double *K, hipStream_t
   J_.segcnt = p->d_segcnt;
   J_.segoff32 = p->d_segoff32;
   J_.segcnt32 = p->d_segcnt32;
-  J_.Dc = p->d_Dc;
+  J_.Dp = p->d_Dp;
   J_.Kc = p->d_Kc;
   J_.mbase = p->d_mc_off;
   J_.mnc = p->d_mnc;
@@ -1446,7 +1447,7 @@ int plan_run(jk_plan *p, const double *D, double *J, double *K, hipStream_t st) 
     // the first execute sizes the lists from its own density: transform, block maxima, then
     // the candidate counts under twice its largest element (one wait for the device)
     HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
-    HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+    HIPCHK(launch_dcart(p->S, D, p->d_Dc, p->d_Dp, st));
     HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
     int rc = size_lists(p, st, 0.0, SIZE_HEADROOM);
     if (rc) return rc;
@@ -1498,7 +1499,7 @@ int plan_grad(jk_plan *p, const double *D, double *grad, hipStream_t st) {
   p->last_stream = st;
   if (!p->sized) {
     HIPCHK(launch_fill_u64((unsigned long long *)p->d_gmax, 1, 0ull, st));
-    HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+    HIPCHK(launch_dcart(p->S, D, p->d_Dc, p->d_Dp, st));
     HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
     int rc = size_lists(p, st, 0.0, SIZE_HEADROOM);
     if (rc) return rc;
@@ -1534,7 +1535,7 @@ int plan_grad(jk_plan *p, const double *D, double *grad, hipStream_t st) {
   HIPCHK(launch_fill_i32(p->d_next, NSLOT, 0, st));
   HIPCHK(launch_fill_i32(p->d_nunits, NSLOT, 0, st));
   HIPCHK(launch_fill_i32(p->d_overflow, 1, 0, st));
-  HIPCHK(launch_dcart(p->S, D, p->d_Dc, st));
+  HIPCHK(launch_dcart(p->S, D, p->d_Dc, p->d_Dp, st));
   HIPCHK(launch_blockmax(p->S, p->d_Dc, p->d_Pblk, p->d_gmax, st));
   ScreenArgs A = screen_args(p);
   A.fp32_cut = 0.0;                       // every kept quartet in the FP64 part of its segment

@@ -65,7 +65,9 @@ struct FoldArgs {             // Coulomb pair buffer -> Cartesian Jt of each mol
   double *Dpair;
 };
 
-hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, hipStream_t st);
+// Dc: Cartesian densities, row-major per molecule; Dp (optional): the same values with the rows
+// of each shell stored as a column-major panel (shell rows r0..r0+n: element (r0+i, c) at r0 nc + c n + i)
+hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, double *Dp, hipStream_t st);
 hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, double *gmax, hipStream_t st);
 hipError_t launch_class_room(const unsigned long long *cap, const long long *capc, long long *room, int *overflow,
                              hipStream_t st);

@@ -20,7 +20,7 @@ __device__ __forceinline__ int mol_of(const long long *off, int nmol, long long 
 // D_cart[a][b] = sum_{mu in shell(a), nu in shell(b)} T[mu][a] D[mu][nu] T[nu][b]
 // (T = identity for Cartesian shells): the density in the Cartesian components, so that
 // digestion in the Cartesian basis followed by J = T Jc T^T reproduces the spherical result.
-__global__ void k_dcart(ShellInfo S, const double *__restrict__ D, double *__restrict__ Dc) {
+__global__ void k_dcart(ShellInfo S, const double *__restrict__ D, double *__restrict__ Dc, double *__restrict__ Dp) {
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < S.nc2_tot;
        t += (long long)gridDim.x * blockDim.x) {
     const int m = mol_of(S.mc_off, S.nmol, t);
@@ -50,6 +50,9 @@ __global__ void k_dcart(ShellInfo S, const double *__restrict__ D, double *__res
       v = fma(ta, acc, v);
     }
     Dc[t] = v;
+    // the rows of shell sa as one panel stored column by column: element (ia, b) of the panel at
+    // b * na + ia, so the block of any shell pair is one contiguous run
+    if (Dp) Dp[S.mc_off[m] + (long long)S.cart_off[sa] * nc + (long long)b * na + ia] = v;
   }
 }
 
@@ -424,8 +427,8 @@ static int grid_for(long long n, int block) {
   return (int)g;
 }
 
-hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, hipStream_t st) {
-  hipLaunchKernelGGL(k_dcart, dim3(grid_for(S.nc2_tot, 256)), dim3(256), 0, st, S, D, Dc);
+hipError_t launch_dcart(const ShellInfo &S, const double *D, double *Dc, double *Dp, hipStream_t st) {
+  hipLaunchKernelGGL(k_dcart, dim3(grid_for(S.nc2_tot, 256)), dim3(256), 0, st, S, D, Dc, Dp);
   return hipGetLastError();
 }
 hipError_t launch_blockmax(const ShellInfo &S, const double *Dc, double *Pblk, double *gmax, hipStream_t st) {

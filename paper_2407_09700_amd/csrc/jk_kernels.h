@@ -74,9 +74,11 @@ struct JKArgs {
   const int *segcnt;            // [npairs * 15] kept kets of the segment (FP64 part)
   const int *segoff32;          // [npairs * 15] start of the FP32 part of the segment (mixed precision) or null
   const int *segcnt32;          // [npairs * 15] kets of the FP32 part or null
-  const double *Dc;             // Cartesian densities, one nc_m x nc_m block per molecule
-  double *Kc;                   // Cartesian exchange accumulators, same layout
-  const long long *mbase;       // [nmol] first element of each molecule's block in Dc / Kc
+  const double *Dp;             // Cartesian densities, one nc_m x nc_m block per molecule, each shell's
+                                // rows stored as a column-major panel (the block of shells s, t:
+                                // ncart(s) ncart(t) consecutive doubles at r0_s nc + c0_t ncart(s))
+  double *Kc;                   // Cartesian exchange accumulators, row-major nc_m x nc_m per molecule
+  const long long *mbase;       // [nmol] first element of each molecule's block in Dp / Kc
   const int *mnc;               // [nmol] Cartesian AO count of each molecule
   double *Jpair;                // Coulomb accumulator per shell pair
   const double *Dpair;          // density block D[c,d] of every kept pair, laid out as Jpair
@@ -146,13 +148,16 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
   constexpr int ck = pair_class(LC, LD);
   const Pair bra = A.pairs[bi];
   const int nc = A.mnc[bra.mol];
-  const double *Dm = A.Dc + A.mbase[bra.mol];
+  // density rows of a and of b from the shell panels: D[a, col] = Pa[col NA + a], so each block
+  // D[a-shell, ket shell] the digestion reads is one contiguous run
+  const double *Pa = A.Dp + A.mbase[bra.mol] + (size_t)bra.ca * nc;
+  const double *Pb = A.Dp + A.mbase[bra.mol] + (size_t)bra.cb * nc;
   double *Km = A.Kc + A.mbase[bra.mol];
   double Dab[NA * NB];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) Dab[a * NB + b] = Dm[(size_t)(bra.ca + a) * nc + bra.cb + b];
+    for (int b = 0; b < NB; ++b) Dab[a * NB + b] = Pa[(size_t)(bra.cb + b) * NA + a];
   // ket k runs on lane (k + rot) mod blockDim: successive segments of a unit continue where the
   // previous one ended, so the waves of the workgroup share the unit's kets evenly
   for (int k = (int)((threadIdx.x + blockDim.x - rot) % blockDim.x); k < cnt; k += blockDim.x) {
@@ -193,7 +198,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + od + d], v);
+          for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Pb[(size_t)(od + d) * NB + b], v);
         k_update<KLDS>(Krow, Km, kst, nc, a, bra.ca + a, kc + c, oc + c, s * v);
       }
 #pragma unroll
@@ -202,7 +207,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.cb + b) * nc + oc + c], v);
+          for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Pb[(size_t)(oc + c) * NB + b], v);
         k_update<KLDS>(Krow, Km, kst, nc, a, bra.ca + a, kd + d, od + d, s * v);
       }
     }
@@ -214,7 +219,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int a = 0; a < NA; ++a)
 #pragma unroll
-          for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + od + d], v);
+          for (int d = 0; d < ND; ++d) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Pa[(size_t)(od + d) * NA + a], v);
         if (KLDS && !KLB && kc + c < A.kwb)
           atomicAdd(&Krow[(size_t)NA * A.kw + b * A.kwb + kc + c], s * v);
         else
@@ -226,7 +231,7 @@ __device__ __forceinline__ void jk_small_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int a = 0; a < NA; ++a)
 #pragma unroll
-          for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Dm[(size_t)(bra.ca + a) * nc + oc + c], v);
+          for (int c = 0; c < NC; ++c) v = fma((double)g[(a * NB + b) * NC * ND + c * ND + d], Pa[(size_t)(oc + c) * NA + a], v);
         if (KLDS && !KLB && kd + d < A.kwb)
           atomicAdd(&Krow[(size_t)NA * A.kw + b * A.kwb + kd + d], s * v);
         else
@@ -245,14 +250,16 @@ constexpr int stage_dq() { return NC * ND + (NA + NB) * (NC + ND); }
 template <int NA, int NB, int NC, int ND>
 constexpr int stage_doubles(int qb) { return NA * NB + qb * (stage_dq<NA, NB, NC, ND>() + 1); }
 
+// Dp: the molecule's densities in shell panels (element (r0 + i, col) of the shell whose rows
+// start at r0, with n rows, at r0 nc + col n + i), so each block below is one contiguous run.
 template <int NA, int NB, int NC, int ND, int QB>
-__device__ __forceinline__ void stage_density(const JKArgs &A, const Pair &bra, int bi, const double *Dm, int nc,
+__device__ __forceinline__ void stage_density(const JKArgs &A, const Pair &bra, int bi, const double *Dp, int nc,
                                               const int *qi, double *ds) {
   constexpr int NAB = NA * NB, NCD = NC * ND, DQ = stage_dq<NA, NB, NC, ND>();
   const int oa = bra.ca, ob = bra.cb;
   for (int t = threadIdx.x; t < NAB + QB * (DQ + 1); t += blockDim.x) {
     if (t < NAB) {
-      ds[t] = Dm[(size_t)(oa + t / NB) * nc + ob + t % NB];
+      ds[t] = Dp[(size_t)oa * nc + (size_t)(ob + t % NB) * NA + t / NB];
       continue;
     }
     int u = t - NAB;
@@ -266,20 +273,20 @@ __device__ __forceinline__ void stage_density(const JKArgs &A, const Pair &bra, 
     if (!qi[q * 8 + 6]) continue;
     const Pair &ket = A.pairs[qi[q * 8 + 1]];
     const int oc = ket.ca, od = ket.cb;
-    int r, c;
+    int r0, n, i, c;   // element (r0 + i, c) of the panel of the shell with rows r0 .. r0 + n
     if (u < NCD) {
-      r = oc + u / ND; c = od + u % ND;
+      r0 = oc; n = NC; i = u / ND; c = od + u % ND;
     } else if ((u -= NCD) < NA * NC) {
-      r = oa + u / NC; c = oc + u % NC;
+      r0 = oa; n = NA; i = u / NC; c = oc + u % NC;
     } else if ((u -= NA * NC) < NA * ND) {
-      r = oa + u / ND; c = od + u % ND;
+      r0 = oa; n = NA; i = u / ND; c = od + u % ND;
     } else if ((u -= NA * ND) < NB * NC) {
-      r = ob + u / NC; c = oc + u % NC;
+      r0 = ob; n = NB; i = u / NC; c = oc + u % NC;
     } else {
       u -= NB * NC;
-      r = ob + u / ND; c = od + u % ND;
+      r0 = ob; n = NB; i = u / ND; c = od + u % ND;
     }
-    ds[t] = Dm[(size_t)r * nc + c];
+    ds[t] = Dp[(size_t)r0 * nc + (size_t)c * n + i];
   }
 }
 
@@ -321,7 +328,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
   const Pair bra = A.pairs[bi];
   const int tid = threadIdx.x;
   const int nc = A.mnc[bra.mol];
-  const double *Dm = A.Dc + A.mbase[bra.mol];
+  const double *Dpm = A.Dp + A.mbase[bra.mol];   // shell panels
   double *Km = A.Kc + A.mbase[bra.mol];
   const int oa = bra.ca, ob = bra.cb;
   constexpr int NCD = NC * ND, CH = (NCD + 63) / 64, DQ = C::DQ;
@@ -337,7 +344,7 @@ __device__ __forceinline__ void jk_team_body(const JKArgs &A, int bi, const int 
     // Z_LDS: Y (the digestion forms Z block by block); ZS_LDS: Z in LDS after the staged densities
     const double *Z = team_eri<LA, LB, LC, LD, C::X_LDS, C::Z_LDS>(A.pp, sG, co, buf, qi, geo, smax,
                                                                   C::ZS_LDS ? ds + C::DSTG : nullptr);
-    stage_density<NA, NB, NC, ND, QB>(A, bra, bi, Dm, nc, qi, ds);
+    stage_density<NA, NB, NC, ND, QB>(A, bra, bi, Dpm, nc, qi, ds);
     for (int t = tid; t < QB * C::DG; t += blockDim.x) dg[t] = 0.0;
     double *pbc = ds + C::DSTG, *pbd = pbc + QB * NB * NCD;   // streamed digestion only
     for (int t = tid; t < C::PBD; t += blockDim.x) pbc[t] = 0.0;
@@ -594,7 +601,9 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
   const Pair bra = A.pairs[bi];
   const int tid = threadIdx.x;
   const int nc = A.mnc[bra.mol];
-  const double *Dm = A.Dc + A.mbase[bra.mol];
+  // density rows of a and of b from the shell panels: D[a, col] = Pa[col NA + a]
+  const double *Pa = A.Dp + A.mbase[bra.mol] + (size_t)bra.ca * nc;
+  const double *Pb = A.Dp + A.mbase[bra.mol] + (size_t)bra.cb * nc;
   double *Km = A.Kc + A.mbase[bra.mol];
   const int oa = bra.ca, ob = bra.cb;
   for (int k0 = 0; k0 < cnt; k0 += QB) {
@@ -633,7 +642,7 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
 #pragma unroll
         for (int ab = 0; ab < NA * NB; ++ab) {
           jab[ab] = fma(2.0 * s * dcd, g[ab], jab[ab]);
-          vj = fma(g[ab], Dm[(size_t)(oa + ab / NB) * nc + ob + ab % NB], vj);
+          vj = fma(g[ab], Pa[(size_t)(ob + ab % NB) * NA + ab / NB], vj);
         }
         atomic_add(jp_elem(A, ck, ki, cd), 2.0 * s * vj);
       }
@@ -643,8 +652,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
         double kc = 0.0, kd = 0.0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          kc = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + dd], kc);
-          kd = fma(g[a * NB + b], Dm[(size_t)(ob + b) * nc + cc], kd);
+          kc = fma(g[a * NB + b], Pb[(size_t)dd * NB + b], kc);
+          kd = fma(g[a * NB + b], Pb[(size_t)cc * NB + b], kd);
         }
         kadd(q, a, oa + a, c, cc, s * kc);
         kadd(q, a, oa + a, NC + d, dd, s * kd);
@@ -654,8 +663,8 @@ __device__ __forceinline__ void jk_team2_body(const JKArgs &A, int bi, const int
         double kc = 0.0, kd = 0.0;
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-          kc = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + dd], kc);
-          kd = fma(g[a * NB + b], Dm[(size_t)(oa + a) * nc + cc], kd);
+          kc = fma(g[a * NB + b], Pa[(size_t)dd * NA + a], kc);
+          kd = fma(g[a * NB + b], Pa[(size_t)cc * NA + a], kd);
         }
         kadd(q, NA + b, ob + b, c, cc, s * kc);
         kadd(q, NA + b, ob + b, NC + d, dd, s * kd);
