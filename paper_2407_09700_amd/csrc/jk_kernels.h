@@ -886,13 +886,24 @@ constexpr int cls_threads() {
                                                                               : cls_block<LA, LB, LC, LD>();
 }
 
+// Waves per SIMD a per-class kernel is compiled for (0: the compiler's choice). The (ps|ss) lane
+// body with LDS rows takes 129 vector registers by default (three waves per SIMD); held to 128
+// it runs four waves without spilling. (The other light bodies spill when held to their next
+// step, and run slower.)
+template <int LA, int LB, int LC, int LD, int KL>
+constexpr int cls_waves() {
+  return KL != 0 && LA == 1 && LB == 0 && LC == 0 && LD == 0 ? 4 : 0;
+}
+
 // Dynamic LDS: jab_s NA*NB (padded to even) | team pool (team classes) or, with KL (lane
 // bodies), the unit's exchange rows compacted to the columns of the ket class's momenta
 // (KL = 1: rows K[a,:] and K[b,:], (NA+NB) x A.kw; KL = 2: rows K[a,:] only, NA x A.kw, the
 // rows of b updated in global memory), flushed once per unit with one global atomic per
 // nonzero element.
 template <int LA, int LB, int LC, int LD, int KL = 0, bool GL = false>
-__global__ __launch_bounds__((cls_threads<LA, LB, LC, LD, KL>())) void k_cls(JKArgs A) {
+__global__ __launch_bounds__((cls_threads<LA, LB, LC, LD, KL>()))
+__attribute__((amdgpu_waves_per_eu(cls_waves<LA, LB, LC, LD, KL>() ? cls_waves<LA, LB, LC, LD, KL>() : 1)))
+void k_cls(JKArgs A) {
   constexpr int NA = ncart(LA), NB = ncart(LB), cb = pair_class(LA, LB), ck = pair_class(LC, LD);
   static_assert(!KL || !use_team<LA, LB, LC, LD>(), "compacted LDS rows are for the lane bodies");
   static_assert(!GL || (KL && SmallCfg<LA, LB, LC, LD>::N <= JK_TABLE_LDS_NMAX), "LDS root tables: lane bodies");
