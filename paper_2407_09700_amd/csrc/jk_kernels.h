@@ -886,13 +886,33 @@ constexpr int cls_threads() {
                                                                               : cls_block<LA, LB, LC, LD>();
 }
 
-// Waves per SIMD a per-class kernel is compiled for (0: the compiler's choice). The (ps|ss) lane
-// body with LDS rows takes 129 vector registers by default (three waves per SIMD); held to 128
-// it runs four waves without spilling. (The other light bodies spill when held to their next
-// step, and run slower.)
+// Waves per SIMD a per-class kernel is compiled for (0: the compiler's choice).
+// - The (ps|ss) lane body with LDS rows takes 129 vector registers by default (three waves per
+//   SIMD); held to 128 it runs four waves without spilling. (The other light bodies spill when
+//   held to their next step, and run slower.)
+// - Workgroup-body classes whose registers exceed 256 by a few accumulation registers (or, for
+//   (gg|gd), (gp|dd), (gp|fd), (gp|ff), (fd|dp), by more) run one 256-lane workgroup per CU
+//   although their LDS was sized for two; held to two waves per SIMD they spill a little and run
+//   two. Listed by measurement: (gp|dp), (gp|gs), (gp|gp), (gp|fs), (gp|fp) and the (fd|**)
+//   classes other than (fd|dp) ran slower that way and are left out.
 template <int LA, int LB, int LC, int LD, int KL>
 constexpr int cls_waves() {
-  return KL != 0 && LA == 1 && LB == 0 && LC == 0 && LD == 0 ? 4 : 0;
+  constexpr int k = ((LA * 5 + LB) * 5 + LC) * 5 + LD;
+  constexpr int two[] = {
+      ((3 * 5 + 1) * 5 + 1) * 5 + 1, ((3 * 5 + 1) * 5 + 2) * 5 + 0, ((3 * 5 + 1) * 5 + 2) * 5 + 1,
+      ((3 * 5 + 1) * 5 + 2) * 5 + 2, ((3 * 5 + 1) * 5 + 3) * 5 + 0, ((3 * 5 + 1) * 5 + 3) * 5 + 1,
+      ((3 * 5 + 3) * 5 + 3) * 5 + 2, ((4 * 5 + 1) * 5 + 2) * 5 + 2, ((4 * 5 + 2) * 5 + 3) * 5 + 2,
+      ((4 * 5 + 3) * 5 + 3) * 5 + 2, ((4 * 5 + 4) * 5 + 2) * 5 + 2, ((4 * 5 + 4) * 5 + 3) * 5 + 1,
+      ((4 * 5 + 4) * 5 + 3) * 5 + 2, ((4 * 5 + 4) * 5 + 4) * 5 + 1, ((4 * 5 + 4) * 5 + 4) * 5 + 2,
+      ((2 * 5 + 0) * 5 + 2) * 5 + 0, ((4 * 5 + 1) * 5 + 3) * 5 + 2, ((4 * 5 + 1) * 5 + 3) * 5 + 3,
+      ((3 * 5 + 2) * 5 + 2) * 5 + 1};
+  if constexpr (KL == 0) {
+    for (int t : two)
+      if (t == k) return 2;
+    return 0;
+  } else {
+    return LA == 1 && LB == 0 && LC == 0 && LD == 0 ? 4 : 0;
+  }
 }
 
 // Dynamic LDS: jab_s NA*NB (padded to even) | team pool (team classes) or, with KL (lane
